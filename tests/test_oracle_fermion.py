@@ -1,0 +1,221 @@
+"""Pins of the oracle's fermion weight (SM Eqs. S2, S3) against closed forms, Fock-space
+brute force and exact symmetries.  CPU only."""
+
+import numpy as np
+import pytest
+
+import oracle as o
+import pins
+
+T1 = 1e-10   # closed forms
+T2 = 1e-11   # Fock space
+T3 = 1e-10   # invariances
+
+
+def _E(Lx, Ly, t=1.0, mu=0.0, dtau=0.1):
+    return o.expk(o.hopping_matrix(Lx, Ly, t, mu), dtau)
+
+
+def _field(seed, Ltau, N, s=1.0):
+    return np.random.default_rng(seed).normal(0.0, s, size=(Ltau, N))
+
+
+# ------------------------------------------------------------------ lattice / exponential
+
+def test_hopping_matrix_spectrum_matches_band():
+    for Lx, Ly in ((2, 2), (2, 3), (4, 4), (3, 5), (6, 4)):
+        K = o.hopping_matrix(Lx, Ly, 1.0, 0.3)
+        ev = np.sort(np.linalg.eigvalsh(K))
+        assert np.allclose(ev, np.sort(pins.band(Lx, Ly, 1.0, 0.3)), atol=1e-13)
+
+
+def test_hopping_matrix_length2_direction_has_double_bond():
+    K = o.hopping_matrix(2, 3, 1.0, 0.0)
+    assert K[0, 1] == -2.0 and K[1, 0] == -2.0     # x-bond on a length-2 ring
+    assert K[0, 2] == -1.0                          # y-bond on a length-3 ring
+
+
+def test_expk_against_fourier_sum():
+    # e^{-dtau K}_{ij} = N^-1 sum_k e^{-dtau eps_k} e^{ik(ri-rj)}: the free Green's
+    # function formula's Fourier transform, with occupation replaced by e^{-dtau eps}
+    Lx, Ly, dtau = 4, 6, 0.1
+    kx, ky = pins.momenta(Lx, Ly)
+    e = pins.band(Lx, Ly, 1.0, 0.0)
+    N = Lx * Ly
+    rx, ry = np.arange(N) % Lx, np.arange(N) // Lx
+    ph = np.exp(1j * (np.outer(rx, kx) + np.outer(ry, ky)))
+    Eref = ((ph * np.exp(-dtau * e)[None, :]) @ ph.conj().T / N).real
+    assert np.max(np.abs(_E(Lx, Ly, dtau=dtau) - Eref)) < 1e-14
+
+
+# ------------------------------------------------------------------ P1, P2, P3 closed forms
+
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s,mu", [(4, 4, 20, 10, 0.0), (4, 4, 40, 10, 0.0),
+                                                (6, 4, 30, 7, 0.4), (8, 8, 80, 10, 0.0)])
+def test_P1_free_fermions(Lx, Ly, Ltau, n_s, mu):
+    E = _E(Lx, Ly, mu=mu)
+    ld, s, G = o.logdet_green(E, np.zeros((Ltau, Lx * Ly)), 0.1, 1.5, n_s)
+    ref = pins.free_logdet(Lx, Ly, 1.0, mu, Ltau * 0.1)
+    assert abs(ld - ref) <= T1 * max(1.0, abs(ref))
+    assert s == 1
+    assert np.max(np.abs(G - pins.free_green(Lx, Ly, 1.0, mu, Ltau * 0.1))) < T1
+
+
+def test_P1_value_printed_in_design_notes():
+    # 4x4, Ltau=20, dtau=0.1, mu=0: 28.304753319448 (momentum sum)
+    assert abs(pins.free_logdet(4, 4, 1.0, 0.0, 2.0) - 28.304753319448) < 1e-11
+
+
+def test_P1_large_beta_N256():
+    E = _E(16, 16)
+    ld, s, G = o.logdet_green(E, np.zeros((160, 256)), 0.1, 1.5, 8)
+    ref = pins.free_logdet(16, 16, 1.0, 0.0, 16.0)
+    assert abs(ld - ref) <= T1 * abs(ref)
+    assert np.max(np.abs(G - pins.free_green(16, 16, 1.0, 0.0, 16.0))) < T1
+
+
+@pytest.mark.parametrize("lam", [1.0, 2.0])
+def test_P2_uniform_field(lam):
+    Lx, Ly, Ltau = 4, 6, 40
+    c = np.random.default_rng(3).normal(0.0, 1.0, size=Ltau)
+    x = np.tile(c[:, None], (1, Lx * Ly))
+    ld, _, _ = o.logdet_green(_E(Lx, Ly), x, 0.1, lam, 10)
+    ref = pins.free_logdet(Lx, Ly, 1.0, 0.0, Ltau * 0.1, shift=0.1 * lam * np.sum(c))
+    assert abs(ld - ref) <= T1 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("L,Ltau,n_s,lam,x0", [(4, 20, 10, 1.5, 1.5), (4, 40, 10, 1.5, -1.5),
+                                               (8, 80, 10, 2.0, 2.0), (16, 160, 8, 2.0, 2.0)])
+def test_P3_staggered_field(L, Ltau, n_s, lam, x0):
+    N = L * L
+    stag = np.array([(-1.0) ** ((i % L) + (i // L)) for i in range(N)])
+    x = np.tile(x0 * stag, (Ltau, 1))
+    ld, s, _ = o.logdet_green(_E(L, L), x, 0.1, lam, n_s)
+    ref = pins.staggered_logdet(L, L, 1.0, 0.0, 0.1, lam, x0, Ltau)
+    assert abs(ld - ref) <= T1 * max(1.0, abs(ref))
+    assert s == 1
+
+
+# ------------------------------------------------------------------ P4 Fock space
+
+@pytest.mark.parametrize("Lx,Ly,Ltau,lam,seed", [(2, 2, 8, 1.5, 1), (2, 2, 12, 3.0, 2),
+                                                 (2, 3, 12, 1.5, 3), (2, 3, 10, 2.5, 4)])
+def test_P4_fock_space(Lx, Ly, Ltau, lam, seed):
+    N = Lx * Ly
+    K = o.hopping_matrix(Lx, Ly, 1.0, 0.2)
+    x = _field(seed, Ltau, N, 1.5)
+    ldf, sf, Gf = pins.fock_logdet_green(K, x, 0.1, lam)
+    ld, s, G = o.logdet_green(o.expk(K, 0.1), x, 0.1, lam, 4)
+    assert abs(ld - ldf) < T2
+    assert s == sf
+    assert np.max(np.abs(G - Gf)) < T2
+
+
+def test_P4_negative_single_spin_determinant_is_reported():
+    # strong random fields on 2x2 give det(1 + B...B) < 0 for some draws
+    K = o.hopping_matrix(2, 2, 1.0, 0.0)
+    E = o.expk(K, 0.1)
+    negs = 0
+    for seed in range(40):
+        x = _field(100 + seed, 40, 4, 3.0)
+        ld, s, _ = o.logdet_green(E, x, 0.1, 3.0, 5)
+        ldf, sf, _ = pins.fock_logdet_green(K, x, 0.1, 3.0)
+        assert s == sf and abs(ld - ldf) < T2
+        negs += s < 0
+    assert negs >= 1
+
+
+# ------------------------------------------------------------------ P5..P9 invariances
+
+def test_P5_stabilization_interval_invariance():
+    Lx = Ly = 4
+    x = _field(5, 40, 16)
+    E = _E(Lx, Ly)
+    ref, sref, Gref = o.logdet_green(E, x, 0.1, 1.5, 1)
+    for n_s in (2, 3, 5, 8, 10, 40):
+        ld, s, G = o.logdet_green(E, x, 0.1, 1.5, n_s)
+        assert abs(ld - ref) <= T3 * abs(ref)
+        assert s == sref
+        # one unstabilized block of 40 slices has condition ~1e7: G loses that much
+        assert np.max(np.abs(G - Gref)) < (T3 if n_s <= 10 else 1e-8)
+    ldd, sd, Gd = o.logdet_green_direct(E, x, 0.1, 1.5)
+    assert abs(ldd - ref) <= 1e-9 * abs(ref) and sd == sref
+
+
+def _perm_translate(Lx, Ly, dx, dy):
+    i = np.arange(Lx * Ly)
+    return ((i % Lx + dx) % Lx) + Lx * ((i // Lx + dy) % Ly)
+
+
+def _perm_c4v(L, op):
+    i = np.arange(L * L)
+    ix, iy = i % L, i // L
+    maps = [(ix, iy), (-iy, ix), (-ix, -iy), (iy, -ix), (-ix, iy), (ix, -iy), (iy, ix), (-iy, -ix)]
+    gx, gy = maps[op]
+    return (gx % L) + L * (gy % L)
+
+
+def test_P6_lattice_symmetries():
+    L = 4
+    x = _field(6, 20, 16)
+    E = _E(L, L)
+    ref, _, Gref = o.logdet_green(E, x, 0.1, 1.5, 5)
+    perms = [_perm_translate(L, L, 1, 0), _perm_translate(L, L, 2, 3)] + \
+            [_perm_c4v(L, op) for op in range(1, 8)]
+    for g in perms:
+        xg = x[:, g]               # (x o g)[l, i] = x[l, g(i)]
+        ld, _, G = o.logdet_green(E, xg, 0.1, 1.5, 5)
+        assert abs(ld - ref) <= T3 * abs(ref)
+        assert np.max(np.abs(G - Gref[np.ix_(g, g)])) < T3
+
+
+def test_P7_time_shift_and_reversal():
+    x = _field(7, 30, 16)
+    E = _E(4, 4)
+    ref = o.logdet_green(E, x, 0.1, 1.5, 5)[0]
+    for xs in (np.roll(x, 1, axis=0), np.roll(x, 7, axis=0), x[::-1]):
+        assert abs(o.logdet_green(E, xs, 0.1, 1.5, 5)[0] - ref) <= T3 * abs(ref)
+
+
+@pytest.mark.parametrize("Lx,Ly", [(4, 4), (2, 4), (6, 4)])
+def test_P8_particle_hole(Lx, Ly):
+    N = Lx * Ly
+    x = _field(8, 30, N, 1.2)
+    E = _E(Lx, Ly)
+    lam, dtau = 1.7, 0.1
+    ld, s, G = o.logdet_green(E, x, dtau, lam, 6)
+    ldm, sm, Gm = o.logdet_green(E, -x, dtau, lam, 6)
+    assert abs(ldm - (ld + dtau * lam * np.sum(x))) <= T3 * abs(ld)
+    assert sm == s
+    P = np.diag([(-1.0) ** ((i % Lx) + (i // Lx)) for i in range(N)])
+    assert np.max(np.abs(Gm - P @ (np.eye(N) - G.T) @ P)) < T3
+
+
+def test_P9_rank_one_ratio_and_two_site_ratio():
+    N = 16
+    x = _field(9, 20, N)
+    E = _E(4, 4)
+    lam, dtau = 1.5, 0.1
+    ld, _, G = o.logdet_green(E, x, dtau, lam, 5)
+    for i, d in ((3, 0.7), (10, -1.3)):
+        xp = x.copy()
+        xp[0, i] += d
+        ldp = o.logdet_green(E, xp, dtau, lam, 5)[0]
+        D = np.exp(-dtau * lam * d) - 1.0
+        assert abs((ldp - ld) - np.log(abs(1.0 + (1.0 - G[i, i]) * D))) < 1e-12
+    i, j, di, dj = 2, 7, 0.9, -0.4
+    xp = x.copy()
+    xp[0, i] += di
+    xp[0, j] += dj
+    ldp = o.logdet_green(E, xp, dtau, lam, 5)[0]
+    Di, Dj = np.exp(-dtau * lam * di) - 1.0, np.exp(-dtau * lam * dj) - 1.0
+    r = (1 + (1 - G[i, i]) * Di) * (1 + (1 - G[j, j]) * Dj) - G[i, j] * G[j, i] * Di * Dj
+    assert abs((ldp - ld) - np.log(abs(r))) < 1e-12
+
+
+def test_P9_ratio_catches_transposed_green():
+    # the two-site ratio needs G_ij G_ji; a test of the pin's sensitivity: a shifted
+    # off-diagonal entry changes the predicted ratio visibly
+    x = _field(10, 20, 16)
+    ld, _, G = o.logdet_green(_E(4, 4), x, 0.1, 1.5, 5)
+    assert np.max(np.abs(G - G.T)) > 1e-3     # G is not symmetric for a random field
