@@ -1,0 +1,193 @@
+/*
+ * slmc.h -- C ABI of the MI355X (gfx950) library for the hot path of symmetry-enforced
+ * self-learning Monte Carlo on the 2D Holstein model (arXiv:1802.06177).
+ *
+ * What it computes
+ *   For a phonon field x[l][i] (l = 0 .. Ltau-1 is the paper's slice l+1, i = ix + Lx*iy)
+ *   the slice matrices are B_l = e^{-dtau K} diag(e^{-dtau*lambda*x[l][.]}) (SM Eq. S2 with
+ *   the exponential of the hopping matrix K written first; both factor orders give the
+ *   same |det|), and the library returns
+ *     logdet = log|det(I + B_{Ltau-1} ... B_0)|   (one spin species; the weight squares it)
+ *     sign   = sign det(I + B_{Ltau-1} ... B_0)
+ *     G      = (I + B_{Ltau-1} ... B_0)^{-1}, G[i][j] = <c_i c_j^dagger>   (SM Eq. S3, l = L)
+ *   stabilized by a column-pivoted QR (UDV form) every n_s slices; the symmetric
+ *   effective-model energy and its checkerboard Metropolis sweeps (Eq. 4 / S7); and the
+ *   cumulative-update acceptance (Eq. 6).
+ *
+ * Frame: x = X - alpha with alpha = -lambda/omega0^2 (the paper's g is `lambda` here, its
+ *   Omega is `omega0`).  At half filling mu = 0 in this frame.  The bosonic action is
+ *   S_Bose = sum_{i,l} [omega0^2/2 x^2 - lambda x + c_kin ((x_{l+1}-x_l)/dtau)^2] (time
+ *   periodic) and the full log-weight is -dtau*S_Bose + 2*logdet.
+ *
+ * Conventions shared by every entry point
+ *   - Data pointers named "device" are device (HBM) pointers owned by the caller; the
+ *     library never frees or retains them.  Pointers named "host" are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *     enqueued asynchronously on it; outputs are valid once the stream reaches the point
+ *     of the call.
+ *   - Argument validation is synchronous: a nonzero return means nothing was enqueued,
+ *     and slmc_last_error() (thread-local) explains it.  No C++ exception crosses the ABI.
+ *   - Per-item numerical failures (non-finite input or output) are reported in status[b]
+ *     with logdet[b] = NaN; the call itself still returns SLMC_OK.
+ *   - Doubles are IEEE binary64; x, G are row-major and packed per item.
+ */
+#ifndef SLMC_H
+#define SLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum slmc_status {
+  SLMC_OK = 0,
+  SLMC_E_ARG = 1,         /* null pointer, out-of-range parameter                        */
+  SLMC_E_SHAPE = 2,       /* lattice/time shape the operation does not support           */
+  SLMC_E_WORKSPACE = 3,   /* workspace smaller than slmc_*_workspace_bytes()             */
+  SLMC_E_DEVICE = 4,      /* HIP runtime error while enqueuing                           */
+  SLMC_E_NONFINITE = 5,   /* per-item status: non-finite input or result                 */
+  SLMC_E_UNSUPPORTED = 6  /* option combination not built                                */
+};
+
+/* Precision of the segment products B_{k n_s} ... B_{(k-1) n_s + 1} between
+ * stabilizations.  The stabilization (QR/UDV), recombination, log-det accumulation and
+ * the residual step are always FP64. */
+enum slmc_precision {
+  SLMC_FP64 = 0,    /* FP64 matrix cores                                              */
+  SLMC_FP32 = 1,    /* FP32 inputs on FP32 matrix cores; FP32 partial sums promoted to
+                       FP64 every acc_chunk k-steps of 4 (acc_chunk = 0: never)         */
+  SLMC_BF16X3 = 2,  /* two-piece bf16 split (hi + lo), three products, FP32 accumulate  */
+  SLMC_BF16X6 = 3   /* three-piece bf16 split, six products, FP32 accumulate            */
+};
+
+/* One lattice model.  N = Lx*Ly sites, Ltau slices of width dtau (beta = Ltau*dtau),
+ * stabilization every n_s slices (the last block may be shorter).
+ * Limits: 2 <= Lx, Ly; N <= 512; 1 <= n_s <= Ltau. */
+typedef struct {
+  int32_t Lx, Ly, Ltau, n_s;
+  double t;       /* nearest-neighbour hopping (Eq. 2)                                  */
+  double mu;      /* chemical potential in the shifted frame (0 = half filling)         */
+  double dtau;    /* Trotter step (SM Eq. S1)                                           */
+  double lambda;  /* electron-phonon coupling (the paper's g)                           */
+  double omega0;  /* phonon frequency (the paper's Omega), M = 1                         */
+  double c_kin;   /* prefactor of sum((x_{l+1}-x_l)/dtau)^2 in S_Bose (1/2 or 1)        */
+} slmc_model;
+
+typedef struct {
+  int32_t precision;       /* enum slmc_precision                                       */
+  int32_t residual_steps;  /* FP64 refinement steps on G (0 or 1); ignored by logdet    */
+  int32_t acc_chunk;       /* SLMC_FP32 only: k-steps (of 4) per FP64 promotion, 0=none */
+  int32_t flags;           /* reserved, must be 0                                        */
+} slmc_options;
+
+/* A batch of items, possibly of different models (uneven sizes in one call).
+ * model_idx, x_off, g_off are HOST arrays of n_items entries, or NULL:
+ *   model_idx NULL -> every item uses model 0;
+ *   x_off NULL     -> item b's field starts at x + b*Ltau*N (requires one model);
+ *   g_off NULL     -> item b's G starts at G + b*N*N (requires one model).
+ * Offsets are in elements (doubles). */
+typedef struct {
+  int32_t n_items;
+  const int32_t* model_idx;
+  const int64_t* x_off;
+  const int64_t* g_off;
+} slmc_batch;
+
+/* Symmetric effective boson model (Eq. 4 / S7 in the shifted frame, weight e^{-E}):
+ *   E = Jk sum (x_{i,l+1}-x_{i,l})^2 + J2 sum x^2 + Jp sum (x^4/4 - a^2 x^2/2)
+ *     + Jp6 sum (x^6/6 - a^2 x^4/4) + sum_r Js[r] sum_{<ij>_r, l} x_{i,l} x_{j,l}
+ *     + Jt sum x_{i,l} x_{i,l+1},
+ * bonds counted once: r=0 offsets (1,0),(0,1); r=1 (1,1),(1,-1); r=2 (2,0),(0,2).
+ * delta is the local move size: x -> x + delta*(2u-1). */
+typedef struct {
+  double Jk, J2, Jp, Jp6, a;
+  double Js[3];
+  double Jt, delta;
+} slmc_eff;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int slmc_version(void);
+
+/* Thread-local text of the last synchronous error of this thread ("" if none). */
+const char* slmc_last_error(void);
+
+/* e^{-dtau K} of a model (SM Eq. S1), FP64, into E_host[N*N] (host, row-major), computed
+ * on the host from the lattice's Fourier modes.  Returns SLMC_OK or SLMC_E_ARG. */
+int slmc_expk(const slmc_model* model, double* E_host);
+
+/* Device workspace, in bytes, that slmc_logdet / slmc_green need for this batch. */
+size_t slmc_workspace_bytes(const slmc_model* models, int32_t n_models,
+                            const slmc_batch* batch, const slmc_options* opt);
+
+/* log|det(I + B...B)| and its sign for every item (SM Eq. S2).
+ *   models[n_models]  host;  batch, opt host;
+ *   x       device, fields (layout above);
+ *   logdet  device [n_items] double;  sign device [n_items] int8 (+1/-1);
+ *   status  device [n_items] int32 (SLMC_OK or SLMC_E_NONFINITE);
+ *   ws      device workspace of ws_bytes >= slmc_workspace_bytes(). */
+int slmc_logdet(const slmc_model* models, int32_t n_models, const slmc_batch* batch,
+                const slmc_options* opt, const double* x, double* logdet, int8_t* sign,
+                int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* As slmc_logdet, and also the equal-time Green's function (SM Eq. S3) into G (device,
+ * N*N per item, row-major, G[i][j] = <c_i c_j^dagger>), refined by opt->residual_steps
+ * FP64 residual-correction steps. */
+int slmc_green(const slmc_model* models, int32_t n_models, const slmc_batch* batch,
+               const slmc_options* opt, const double* x, double* logdet, int8_t* sign,
+               double* G, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* E_eff of every chain (Eq. 4 / S7).  x device [n_chains][Ltau][N]; e_eff device
+ * [n_chains].  Needs Ltau >= 2. */
+int slmc_eff_energy(const slmc_model* model, const slmc_eff* eff, int32_t n_chains,
+                    const double* x, double* e_eff, void* stream);
+
+/* n_sweeps checkerboard Metropolis sweeps of every chain, in place (main text "SLMC" and
+ * the last paragraph of SM Sec. III: local updates of the effective model).
+ *   Colouring: spatial colour (ix mod m) + m (iy mod m), m = 2 when Js[2] == 0 (m = 3 if
+ *   2 does not divide Lx, Ly), else m = 4 (or 3); temporal colour l mod 2; phase
+ *   p = spatial colour + m*m*temporal colour, P = 2 m^2 phases; Ltau must be even.
+ *   A per-proposal coin picks the forward (0..P-1) or reverse (P-1..0) phase order.
+ *   Random numbers: Philox4x32-10, key (seed lo, seed hi); counter
+ *   (i + N*l, sweep, proposal_idx mod 2^32, chain) -> u1 (word 0, move) and u2 (word 1,
+ *   accept iff log u2 < -dE); coin counter (0xFFFFFFFF, 0xFFFFFFFE, proposal, chain)
+ *   word 0, forward iff < 2^31; u = (r + 1/2) 2^-32.
+ *   x device [n_chains][Ltau][N] in/out; n_accepted device [n_chains] int64 (set, not
+ *   accumulated).  Returns SLMC_E_SHAPE if no colouring exists. */
+int slmc_eff_sweep(const slmc_model* model, const slmc_eff* eff, int32_t n_chains,
+                   double* x, int32_t n_sweeps, uint64_t seed, uint64_t proposal_idx,
+                   int64_t* n_accepted, void* stream);
+
+/* Device workspace, in bytes, of slmc_cumulative_accept for n_chains chains. */
+size_t slmc_accept_workspace_bytes(const slmc_model* model, int32_t n_chains,
+                                   const slmc_options* opt);
+
+/* Cumulative-update acceptance (Eq. 6) of one proposal per chain:
+ *   log r = [log w(x') - log w(x)] + [E_eff(x') - E_eff(x)],
+ *   log w = -dtau S_Bose + 2 logdet(x) (logdet with opt->precision),
+ *   accept iff log u < log r with u = Philox word 0 at counter
+ *   (0xFFFFFFFF, 0xFFFFFFFF, proposal_idx mod 2^32, chain).
+ *   x_cur device [n_chains][Ltau][N] in/out (x_prop copied in on accept);
+ *   x_prop device (same shape); logw_cur, eeff_cur device [n_chains] in/out (cached values
+ *   of the current state, replaced on accept); accepted device [n_chains] uint8;
+ *   log_ratio device [n_chains] double; ws device workspace. */
+int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff,
+                           const slmc_options* opt, int32_t n_chains, double* x_cur,
+                           const double* x_prop, double* logw_cur, double* eeff_cur,
+                           uint64_t seed, uint64_t proposal_idx, uint8_t* accepted,
+                           double* log_ratio, void* ws, size_t ws_bytes, void* stream);
+
+/* log w = -dtau S_Bose(x) + 2 logdet for every chain (seeds the cached logw_cur of
+ * slmc_cumulative_accept).  Same workspace as slmc_cumulative_accept. */
+int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_chains,
+                    const double* x, double* logw, void* ws, size_t ws_bytes, void* stream);
+
+/* Frees the library's device constant cache (e^{-dtau K} copies per model and device).
+ * Must not be called while work that uses it is still queued. */
+void slmc_cache_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLMC_H */

@@ -1,0 +1,225 @@
+"""MI355X (gfx950) library for the hot path of symmetry-enforced self-learning Monte Carlo
+on the 2D Holstein model (arXiv:1802.06177): the fermion weight log|det(1 + B_L...B_1)|
+and the equal-time Green's function of a phonon field (SM Eqs. S2, S3), the symmetric
+effective model's checkerboard sweeps (Eq. 4) and the cumulative-update acceptance
+(Eq. 6).
+
+Everything runs in the HIP kernels behind the C ABI of include/slmc.h; this module only
+marshals torch tensors (device memory and the current stream) into those calls.  Inputs
+must be CUDA (HIP) float64 tensors; there is no CPU path.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SlmcError, Model, Options,
+                   Batch, Eff)
+
+__all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
+           "eff_energy", "eff_sweep", "log_weight", "cumulative_accept", "cache_clear",
+           "SlmcError", "version"]
+
+PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6}
+
+
+def version():
+    return _abi.lib().slmc_version()
+
+
+def model(Lx, Ly, Ltau, n_s, t=1.0, mu=0.0, dtau=0.1, lam=1.5, omega0=1.0, c_kin=0.5):
+    """slmc_model of a periodic Lx x Ly lattice with Ltau slices (beta = Ltau dtau)."""
+    return Model(int(Lx), int(Ly), int(Ltau), int(n_s), float(t), float(mu), float(dtau),
+                 float(lam), float(omega0), float(c_kin))
+
+
+def model_from_dict(d):
+    return model(d["Lx"], d["Ly"], d["Ltau"], d["n_s"], d.get("t", 1.0), d.get("mu", 0.0),
+                 d.get("dtau", 0.1), d.get("lam", 1.5), d.get("omega0", 1.0), d.get("c_kin", 0.5))
+
+
+def options(precision="fp64", residual_steps=0, acc_chunk=0):
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return Options(p, int(residual_steps), int(acc_chunk), 0)
+
+
+def eff_model(Jk=0.0, J2=0.0, Jp=0.0, Jp6=0.0, a=0.0, Js=(0.0, 0.0, 0.0), Jt=0.0, delta=0.5):
+    e = Eff()
+    e.Jk, e.J2, e.Jp, e.Jp6, e.a = float(Jk), float(J2), float(Jp), float(Jp6), float(a)
+    for k in range(3):
+        e.Js[k] = float(Js[k])
+    e.Jt, e.delta = float(Jt), float(delta)
+    return e
+
+
+def expk(m):
+    """e^{-dtau K} (host, FP64, N x N) from the library's Fourier construction."""
+    N = m.Lx * m.Ly
+    out = np.empty((N, N), dtype=np.float64)
+    _abi.check(_abi.lib().slmc_expk(C.byref(m), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def cache_clear():
+    _abi.lib().slmc_cache_clear()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 tensor on the GPU" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return C.c_void_p(t.data_ptr())
+
+
+class _BatchArgs:
+    """Host-side slmc_batch with the arrays kept alive."""
+
+    def __init__(self, n_items, model_idx=None, x_off=None, g_off=None):
+        self._mi = None if model_idx is None else np.ascontiguousarray(model_idx, dtype=np.int32)
+        self._xo = None if x_off is None else np.ascontiguousarray(x_off, dtype=np.int64)
+        self._go = None if g_off is None else np.ascontiguousarray(g_off, dtype=np.int64)
+        P = C.POINTER
+        self.batch = Batch(int(n_items),
+                           None if self._mi is None else self._mi.ctypes.data_as(P(C.c_int32)),
+                           None if self._xo is None else self._xo.ctypes.data_as(P(C.c_int64)),
+                           None if self._go is None else self._go.ctypes.data_as(P(C.c_int64)))
+
+
+def _models_arr(models):
+    if isinstance(models, Model):
+        models = [models]
+    arr = (Model * len(models))(*models)
+    return arr, len(models)
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    key = str(device)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def workspace_bytes(models, n_items, opt=None, model_idx=None, x_off=None, g_off=None):
+    arr, nm = _models_arr(models)
+    ba = _BatchArgs(n_items, model_idx, x_off, g_off)
+    opt = opt or options()
+    return _abi.lib().slmc_workspace_bytes(arr, nm, C.byref(ba.batch), C.byref(opt))
+
+
+def _fermion(models, x, opt, model_idx, x_off, g_off, n_items, want_g, G, stream, ws):
+    torch = _torch()
+    arr, nm = _models_arr(models)
+    if n_items is None:
+        if nm != 1 or x.dim() != 3:
+            raise ValueError("x must be [items, Ltau, N] for a single model, else pass n_items")
+        n_items = x.shape[0]
+    xp = _dev_f64(x, "x")
+    opt = opt or options()
+    ba = _BatchArgs(n_items, model_idx, x_off, g_off)
+    L = _abi.lib()
+    need = L.slmc_workspace_bytes(arr, nm, C.byref(ba.batch), C.byref(opt))
+    wsb = ws if ws is not None else _workspace(need, x.device)
+    logdet = torch.empty(n_items, dtype=torch.float64, device=x.device)
+    sign = torch.empty(n_items, dtype=torch.int8, device=x.device)
+    status = torch.empty(n_items, dtype=torch.int32, device=x.device)
+    vp = C.c_void_p
+    if want_g:
+        if G is None:
+            if nm != 1:
+                raise ValueError("pass G for several models")
+            N = arr[0].Lx * arr[0].Ly
+            G = torch.empty((n_items, N, N), dtype=torch.float64, device=x.device)
+        _abi.check(L.slmc_green(arr, nm, C.byref(ba.batch), C.byref(opt), xp,
+                                vp(logdet.data_ptr()), vp(sign.data_ptr()), _dev_f64(G, "G"),
+                                vp(status.data_ptr()), vp(wsb.data_ptr()), wsb.numel(),
+                                _stream(stream)))
+        return logdet, sign, G, status
+    _abi.check(L.slmc_logdet(arr, nm, C.byref(ba.batch), C.byref(opt), xp,
+                             vp(logdet.data_ptr()), vp(sign.data_ptr()), vp(status.data_ptr()),
+                             vp(wsb.data_ptr()), wsb.numel(), _stream(stream)))
+    return logdet, sign, status
+
+
+def logdet(models, x, opt=None, model_idx=None, x_off=None, n_items=None, stream=None, ws=None):
+    """Single-spin log|det(1 + B_L...B_1)|, sign and status per item (SM Eq. S2).
+    x: float64 GPU tensor [items, Ltau, N] (one model) or packed 1-D with x_off."""
+    return _fermion(models, x, opt, model_idx, x_off, None, n_items, False, None, stream, ws)
+
+
+def green(models, x, opt=None, model_idx=None, x_off=None, g_off=None, n_items=None, G=None,
+          stream=None, ws=None):
+    """As logdet, plus G = (1 + B_L...B_1)^{-1} (SM Eq. S3), G[i][j] = <c_i c_j^+>."""
+    return _fermion(models, x, opt, model_idx, x_off, g_off, n_items, True, G, stream, ws)
+
+
+def eff_energy(m, eff, x, stream=None):
+    torch = _torch()
+    e = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    _abi.check(_abi.lib().slmc_eff_energy(C.byref(m), C.byref(eff), x.shape[0], _dev_f64(x, "x"),
+                                          C.c_void_p(e.data_ptr()), _stream(stream)))
+    return e
+
+
+def eff_sweep(m, eff, x, n_sweeps, seed, proposal_idx, stream=None):
+    """n_sweeps checkerboard Metropolis sweeps of every chain of x [chains, Ltau, N], in
+    place; returns the accepted-move count per chain."""
+    torch = _torch()
+    nacc = torch.empty(x.shape[0], dtype=torch.int64, device=x.device)
+    _abi.check(_abi.lib().slmc_eff_sweep(C.byref(m), C.byref(eff), x.shape[0], _dev_f64(x, "x"),
+                                         int(n_sweeps), C.c_uint64(seed), C.c_uint64(proposal_idx),
+                                         C.c_void_p(nacc.data_ptr()), _stream(stream)))
+    return nacc
+
+
+def log_weight(m, x, opt=None, stream=None, ws=None):
+    torch = _torch()
+    opt = opt or options()
+    L = _abi.lib()
+    need = L.slmc_accept_workspace_bytes(C.byref(m), x.shape[0], C.byref(opt))
+    wsb = ws if ws is not None else _workspace(need, x.device)
+    lw = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    _abi.check(L.slmc_log_weight(C.byref(m), C.byref(opt), x.shape[0], _dev_f64(x, "x"),
+                                 C.c_void_p(lw.data_ptr()), C.c_void_p(wsb.data_ptr()), wsb.numel(),
+                                 _stream(stream)))
+    return lw
+
+
+def cumulative_accept(m, eff, x_cur, x_prop, logw_cur, eeff_cur, seed, proposal_idx, opt=None,
+                      stream=None, ws=None):
+    """Eq. 6 for one proposal per chain; x_cur, logw_cur, eeff_cur are updated in place on
+    accept.  Returns (accepted uint8, log_ratio float64)."""
+    torch = _torch()
+    opt = opt or options()
+    L = _abi.lib()
+    n = x_cur.shape[0]
+    need = L.slmc_accept_workspace_bytes(C.byref(m), n, C.byref(opt))
+    wsb = ws if ws is not None else _workspace(need, x_cur.device)
+    acc = torch.empty(n, dtype=torch.uint8, device=x_cur.device)
+    lr = torch.empty(n, dtype=torch.float64, device=x_cur.device)
+    vp = C.c_void_p
+    _abi.check(L.slmc_cumulative_accept(
+        C.byref(m), C.byref(eff), C.byref(opt), n, _dev_f64(x_cur, "x_cur"),
+        _dev_f64(x_prop, "x_prop"), _dev_f64(logw_cur, "logw_cur"), _dev_f64(eeff_cur, "eeff_cur"),
+        C.c_uint64(seed), C.c_uint64(proposal_idx), vp(acc.data_ptr()), vp(lr.data_ptr()),
+        vp(wsb.data_ptr()), wsb.numel(), _stream(stream)))
+    return acc, lr

@@ -1,0 +1,443 @@
+// Recombination of the stabilized product into log|det(I + U D V)|, its sign and
+// G = (I + U D V)^{-1} (SM Eqs. S2, S3).
+//
+// With Db = max(D, 1) and Ds = min(D, 1) (both taken from log D, so neither overflows)
+//   I + U D V = U Db X,   X = Db^{-1} U^T + Ds V,
+//   log|det| = sum log Db + log|det X|,  sign = det U * sign det X,
+//   G = X^{-1} (Db^{-1} U^T).
+// X is factored by a blocked LU with partial pivoting (one workgroup per item, the pivot
+// order kept as a row map so no row is moved in memory); the solve for G gives each wave
+// one 16-column block of the right-hand side held in registers.  The FP64 residual step
+// refines that solve: R = Db^{-1} U^T - X G, G += X^{-1} R.
+#include "common.h"
+#include "launch.h"
+
+namespace slmc {
+
+namespace {
+
+constexpr int LDY = 17;
+constexpr double LN2 = 0.69314718055994530942;
+
+__device__ __forceinline__ double xval(const double* QT, const double* V, const double* dbi,
+                                       const double* dsm, int Np, int r, int j) {
+  return dbi[r] * QT[(size_t)r * Np + j] + dsm[r] * V[(size_t)r * Np + j];
+}
+
+template <int NRBMAX>
+__global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
+                                            const double* __restrict__ V,
+                                            const double* __restrict__ logD,
+                                            const int* __restrict__ qsign,
+                                            const int* __restrict__ st_in,
+                                            double* __restrict__ LU, int* __restrict__ prow_g,
+                                            double* __restrict__ DI,
+                                            const int* __restrict__ item_of,
+                                            double* __restrict__ logdet_out,
+                                            int8_t* __restrict__ sign_out,
+                                            int32_t* __restrict__ status_out, int N, int Np) {
+  extern __shared__ double lds[];
+  const int b = blockIdx.x;
+  const int NRB = Np >> 4;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+  double* Pn0 = lds;                       // [2][Np][LDY]
+  double* dbi = Pn0 + 2 * Np * LDY;        // [Np]
+  double* dsm = dbi + Np;                  // [Np]
+  double* ud = dsm + Np;                   // [Np] pivots (U diagonal)
+  double* Li = ud + Np;                    // [16][LDY]
+  double* Ui = Li + 16 * LDY;              // [16][LDY]
+  double* redv = Ui + 16 * LDY;            // [8]
+  int* prow = (int*)(redv + 8);            // [Np]
+  int* redi = prow + Np;                   // [8]
+  int* cnt = redi + 8;                     // [2]: swaps, singular
+
+  const double* QTb = QT + (size_t)b * Np * Np;
+  const double* Vb = V + (size_t)b * Np * Np;
+  double* L = LU + (size_t)b * Np * Np;
+  double* DIb = DI + (size_t)b * NRB * 512;
+  for (int i = tid; i < Np; i += 256) {
+    const double ld = logD[(size_t)b * Np + i];
+    dbi[i] = exp(-fmax(ld, 0.0));
+    dsm[i] = exp(fmin(ld, 0.0));
+    prow[i] = i;
+  }
+  if (tid == 0) { cnt[0] = 0; cnt[1] = 0; }
+  __syncthreads();
+  for (int idx = tid; idx < Np * 16; idx += 256) {
+    const int r = idx >> 4, jj = idx & 15;
+    Pn0[r * LDY + jj] = xval(QTb, Vb, dbi, dsm, Np, r, jj);
+  }
+  __syncthreads();
+
+  for (int p = 0; p < NRB; ++p) {
+    const int j0 = 16 * p, K = Np - j0, nrbK = NRB - p;
+    double* Pn = Pn0 + (p & 1) * Np * LDY;
+    double* Pnx = Pn0 + ((p + 1) & 1) * Np * LDY;
+    for (int cc = 0; cc < 16; ++cc) {
+      // pivot search over local rows >= cc (largest |a|, lowest row on ties)
+      double bv = -1.0;
+      int bi = 0x7fffffff;
+      for (int r = cc + tid; r < K; r += 256) {
+        const double a = fabs(Pn[r * LDY + cc]);
+        if (a > bv) { bv = a; bi = r; }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (lane == 0) { redv[w] = bv; redi[w] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double v = redv[0];
+        int pr = redi[0];
+        for (int k = 1; k < 4; ++k)
+          if (redv[k] > v || (redv[k] == v && redi[k] < pr)) { v = redv[k]; pr = redi[k]; }
+        if (pr != cc && pr < K) {
+          for (int j = 0; j < 16; ++j) {
+            const double t = Pn[cc * LDY + j];
+            Pn[cc * LDY + j] = Pn[pr * LDY + j];
+            Pn[pr * LDY + j] = t;
+          }
+          const int t = prow[j0 + cc];
+          prow[j0 + cc] = prow[j0 + pr];
+          prow[j0 + pr] = t;
+          cnt[0] += 1;
+        }
+        const double u = Pn[cc * LDY + cc];
+        ud[j0 + cc] = u;
+        if (u == 0.0 || u != u) cnt[1] = 1;
+      }
+      __syncthreads();
+      {
+        const double u = ud[j0 + cc];
+        const double ui = (u != 0.0) ? 1.0 / u : 0.0;
+        for (int r = cc + 1 + tid; r < K; r += 256) {
+          const double l = Pn[r * LDY + cc] * ui;
+          Pn[r * LDY + cc] = l;
+          for (int j = cc + 1; j < 16; ++j) Pn[r * LDY + j] -= l * Pn[cc * LDY + j];
+        }
+      }
+      __syncthreads();
+    }
+    // inverses of the unit-lower L11 (wave 0) and upper U11 (wave 1), one column per lane
+    if (w == 0 && lane < 16) {
+      const int j = lane;
+      for (int i = 0; i < 16; ++i) {
+        double x;
+        if (i < j) x = 0.0;
+        else if (i == j) x = 1.0;
+        else {
+          double s = 0.0;
+          for (int l = j; l < i; ++l) s += Pn[i * LDY + l] * Li[l * LDY + j];
+          x = -s;
+        }
+        Li[i * LDY + j] = x;
+      }
+    } else if (w == 1 && lane < 16) {
+      const int j = lane;
+      for (int i = 15; i >= 0; --i) {
+        double x;
+        if (i > j) x = 0.0;
+        else {
+          double s = (i == j) ? 1.0 : 0.0;
+          for (int l = i + 1; l <= j; ++l) s -= Pn[i * LDY + l] * Ui[l * LDY + j];
+          const double u = Pn[i * LDY + i];
+          x = (u != 0.0) ? s / u : 0.0;
+        }
+        Ui[i * LDY + j] = x;
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 512; idx += 256) {
+      const int which = idx >> 8, e = idx & 255, i = e >> 4, j = e & 15;
+      DIb[(size_t)p * 512 + idx] = which ? Ui[i * LDY + j] : Li[i * LDY + j];
+    }
+    // trailing update: U12 = L11^-1 A12, A22 -= L21 U12
+    for (int cb = p + 1 + w; cb < NRB; cb += 4) {
+      // opaque copies of the lane coordinates: keeps the per-row addresses from being
+      // hoisted out of this loop (they would pin hundreds of registers)
+      int c = lane & 15, g = lane >> 4;
+      __asm__ volatile("" : "+v"(c), "+v"(g));
+      dx4 blk[NRBMAX];
+#pragma unroll
+      for (int rb = 0; rb < NRBMAX; ++rb) {
+        if (rb < nrbK) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int pr = prow[j0 + 16 * rb + drow64(g, v)];
+            blk[rb][v] = (p == 0) ? xval(QTb, Vb, dbi, dsm, Np, pr, 16 * cb + c)
+                                  : L[(size_t)pr * Np + 16 * cb + c];
+          }
+        }
+      }
+      dx4 u12 = zero4d();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) u12 = mfma64(Li[c * LDY + drow64(g, s)], blk[0][s], u12);
+      blk[0] = u12;
+#pragma unroll
+      for (int rb = 1; rb < NRBMAX; ++rb) {
+        if (rb < nrbK) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            blk[rb] = mfma64(-Pn[(16 * rb + c) * LDY + drow64(g, s)], u12[s], blk[rb]);
+        }
+      }
+#pragma unroll
+      for (int rb = 0; rb < NRBMAX; ++rb) {
+        if (rb < nrbK) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int lr = 16 * rb + drow64(g, v);
+            L[(size_t)prow[j0 + lr] * Np + 16 * cb + c] = blk[rb][v];
+            if (cb == p + 1 && rb >= 1) Pnx[(lr - 16) * LDY + c] = blk[rb][v];
+          }
+        }
+      }
+    }
+    for (int idx = tid; idx < K * 16; idx += 256) {
+      const int r = idx >> 4, jj = idx & 15;
+      L[(size_t)prow[j0 + r] * Np + j0 + jj] = Pn[r * LDY + jj];
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+
+  // log|det X|, sign, and the outputs
+  double s = 0.0, sd = 0.0;
+  int neg = 0;
+  for (int i = tid; i < Np; i += 256) {
+    const double u = ud[i];
+    s += log(fabs(u));
+    neg += u < 0.0;
+    sd += fmax(logD[(size_t)b * Np + i], 0.0);
+    prow_g[(size_t)b * Np + i] = prow[i];
+  }
+  s = sum64(s);
+  sd = sum64(sd);
+  for (int off = 32; off >= 1; off >>= 1) neg += __shfl_xor(neg, off, 64);
+  if (lane == 0) { redv[w] = s; redv[4 + w] = sd; redi[w] = neg; }
+  __syncthreads();
+  if (tid == 0) {
+    const double lx = redv[0] + redv[1] + redv[2] + redv[3];
+    const double lb = redv[4] + redv[5] + redv[6] + redv[7];
+    const int nn = redi[0] + redi[1] + redi[2] + redi[3];
+    double ld = lb + lx - (double)(Np - N) * LN2;
+    const int sgn = qsign[b] * (((nn + cnt[0]) & 1) ? -1 : 1);
+    int stt = 0;
+    if (st_in[b] != 0 || cnt[1] != 0 || !isfinite(ld)) { stt = 5; ld = __longlong_as_double(0x7ff8000000000000LL); }
+    const int item = item_of ? item_of[b] : b;
+    logdet_out[item] = ld;
+    sign_out[item] = (int8_t)sgn;
+    status_out[item] = stt;
+  }
+}
+
+template <int NRBMAX>
+__global__ __launch_bounds__(256) void lu_solve_k(int mode, const double* __restrict__ QT,
+                                                  const double* __restrict__ logD,
+                                                  const double* __restrict__ R,
+                                                  const double* __restrict__ LU,
+                                                  const int* __restrict__ prow,
+                                                  const double* __restrict__ DI,
+                                                  double* __restrict__ Gint, int accumulate,
+                                                  double* __restrict__ Gout,
+                                                  const int64_t* __restrict__ goff, int nb,
+                                                  int N, int Np) {
+  const int NRB = Np >> 4;
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= nb * NRB) return;
+  const int cb = wid % NRB, b = wid / NRB;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const double* Lb = LU + (size_t)b * Np * Np;
+  const int* pb = prow + (size_t)b * Np;
+  const double* DIb = DI + (size_t)b * NRB * 512;
+  const int col = 16 * cb + c;
+
+  dx4 y[NRBMAX];
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < NRB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pr = pb[16 * rb + drow64(g, v)];
+        if (mode == 0)
+          y[rb][v] = exp(-fmax(logD[(size_t)b * Np + pr], 0.0)) * QT[(size_t)b * Np * Np + (size_t)pr * Np + col];
+        else
+          y[rb][v] = R[(size_t)b * Np * Np + (size_t)pr * Np + col];
+      }
+    }
+  }
+  // forward: L y = P rhs
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < NRB) {
+      dx4 t = y[rb];
+      const double* lrow = Lb + (size_t)pb[16 * rb + c] * Np;
+#pragma unroll
+      for (int kb = 0; kb < rb; ++kb) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) t = mfma64(-lrow[16 * kb + drow64(g, s)], y[kb][s], t);
+      }
+      dx4 nv = zero4d();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) nv = mfma64(DIb[(size_t)rb * 512 + c * 16 + drow64(g, s)], t[s], nv);
+      y[rb] = nv;
+    }
+  }
+  // backward: U x = y
+#pragma unroll
+  for (int rb = NRBMAX - 1; rb >= 0; --rb) {
+    if (rb < NRB) {
+      dx4 t = y[rb];
+      const double* urow = Lb + (size_t)pb[16 * rb + c] * Np;
+#pragma unroll
+      for (int kb = rb + 1; kb < NRBMAX; ++kb) {
+        if (kb < NRB) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) t = mfma64(-urow[16 * kb + drow64(g, s)], y[kb][s], t);
+        }
+      }
+      dx4 nv = zero4d();
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        nv = mfma64(DIb[(size_t)rb * 512 + 256 + c * 16 + drow64(g, s)], t[s], nv);
+      y[rb] = nv;
+    }
+  }
+  double* Gi = Gint + (size_t)b * Np * Np;
+  double* Go = Gout ? Gout + (goff ? goff[b] : (int64_t)b * N * N) : nullptr;
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < NRB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rb + drow64(g, v);
+        double val = y[rb][v];
+        if (accumulate) val += Gi[(size_t)row * Np + col];
+        Gi[(size_t)row * Np + col] = val;
+        if (Go && row < N && col < N) Go[(size_t)row * N + col] = val;
+      }
+    }
+  }
+}
+
+template <int NRBMAX>
+__global__ __launch_bounds__(256) void residual_k(const double* __restrict__ QT,
+                                                  const double* __restrict__ V,
+                                                  const double* __restrict__ logD,
+                                                  const double* __restrict__ Gint,
+                                                  double* __restrict__ R, int nb, int Np) {
+  const int NRB = Np >> 4;
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= nb * NRB) return;
+  const int cb = wid % NRB, b = wid / NRB;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const size_t off = (size_t)b * Np * Np;
+  const double* ld = logD + (size_t)b * Np;
+  const int col = 16 * cb + c;
+  dx4 acc[NRBMAX];
+  double dbr[NRBMAX], dsr[NRBMAX];
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < NRB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rb + drow64(g, v);
+        acc[rb][v] = exp(-fmax(ld[row], 0.0)) * QT[off + (size_t)row * Np + col];
+      }
+      const double l = ld[16 * rb + c];
+      dbr[rb] = exp(-fmax(l, 0.0));
+      dsr[rb] = exp(fmin(l, 0.0));
+    }
+  }
+  for (int kb = 0; kb < NRB; ++kb) {
+    const int q = 16 * kb + 4 * g;
+    double gv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) gv[s] = Gint[off + (size_t)(q + s) * Np + col];
+#pragma unroll
+    for (int rb = 0; rb < NRBMAX; ++rb) {
+      if (rb < NRB) {
+        const double* qt = QT + off + (size_t)(16 * rb + c) * Np + q;
+        const double* vv = V + off + (size_t)(16 * rb + c) * Np + q;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc[rb] = mfma64(-(dbr[rb] * qt[s] + dsr[rb] * vv[s]), gv[s], acc[rb]);
+      }
+    }
+  }
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < NRB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) R[off + (size_t)(16 * rb + drow64(g, v)) * Np + col] = acc[rb][v];
+    }
+  }
+}
+
+template <int NRBMAX>
+hipError_t run_lu(const double* QT, const double* V, const double* logD, const int* qsign,
+                  const int* st_in, double* LU, int* prow, double* DI, const int* item_of,
+                  double* lo, int8_t* so, int32_t* sto, int nb, int N, int Np, hipStream_t st) {
+  const size_t lds = (size_t)(2 * Np * LDY + 3 * Np + 2 * 16 * LDY + 8) * sizeof(double) +
+                     (size_t)(Np + 10) * sizeof(int);
+  hipLaunchKernelGGL(lu_k<NRBMAX>, dim3(nb), dim3(256), lds, st, QT, V, logD, qsign, st_in, LU,
+                     prow, DI, item_of, lo, so, sto, N, Np);
+  return hipGetLastError();
+}
+
+template <int NRBMAX>
+hipError_t run_solve(int mode, const double* QT, const double* logD, const double* R,
+                     const double* LU, const int* prow, const double* DI, double* Gint, int acc,
+                     double* Gout, const int64_t* goff, int nb, int N, int Np, hipStream_t st) {
+  const int waves = nb * (Np / 16);
+  hipLaunchKernelGGL(lu_solve_k<NRBMAX>, dim3((waves + 3) / 4), dim3(256), 0, st, mode, QT, logD,
+                     R, LU, prow, DI, Gint, acc, Gout, goff, nb, N, Np);
+  return hipGetLastError();
+}
+
+template <int NRBMAX>
+hipError_t run_resid(const double* QT, const double* V, const double* logD, const double* Gint,
+                     double* R, int nb, int Np, hipStream_t st) {
+  const int waves = nb * (Np / 16);
+  hipLaunchKernelGGL(residual_k<NRBMAX>, dim3((waves + 3) / 4), dim3(256), 0, st, QT, V, logD,
+                     Gint, R, nb, Np);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define SLMC_NRB_DISPATCH(FN, ...)                       \
+  do {                                                   \
+    const int NRB_ = Np / 16;                            \
+    if (NRB_ <= 4) return FN<4>(__VA_ARGS__);            \
+    if (NRB_ <= 8) return FN<8>(__VA_ARGS__);            \
+    if (NRB_ <= 16) return FN<16>(__VA_ARGS__);          \
+    if (NRB_ <= 25) return FN<25>(__VA_ARGS__);          \
+    if (NRB_ <= 32) return FN<32>(__VA_ARGS__);          \
+    return hipErrorInvalidValue;                         \
+  } while (0)
+
+hipError_t launch_lu(const double* QT, const double* V, const double* logD, const int* qsign,
+                     const int* st_in, double* LU, int* prow, double* DI, const int* item_of,
+                     double* logdet_out, int8_t* sign_out, int32_t* status_out, int nb, int N,
+                     int Np, hipStream_t st) {
+  SLMC_NRB_DISPATCH(run_lu, QT, V, logD, qsign, st_in, LU, prow, DI, item_of, logdet_out,
+                    sign_out, status_out, nb, N, Np, st);
+}
+
+hipError_t launch_lu_solve(int mode, const double* QT, const double* logD, const double* R,
+                           const double* LU, const int* prow, const double* DI, double* Gint,
+                           int accumulate, double* Gout, const int64_t* goff, int nb, int N,
+                           int Np, hipStream_t st) {
+  SLMC_NRB_DISPATCH(run_solve, mode, QT, logD, R, LU, prow, DI, Gint, accumulate, Gout, goff, nb,
+                    N, Np, st);
+}
+
+hipError_t launch_residual(const double* QT, const double* V, const double* logD,
+                           const double* Gint, double* R, int nb, int Np, hipStream_t st) {
+  SLMC_NRB_DISPATCH(run_resid, QT, V, logD, Gint, R, nb, Np, st);
+}
+
+}  // namespace slmc

@@ -1,0 +1,98 @@
+// Host-side launchers of the device kernels (defined in the .hip files).  Every launcher
+// enqueues on `st` and returns the hipError_t of the launch.  Sizes: N sites, Np = N
+// rounded up to a multiple of 16 (the padded rows/columns carry an identity block, so the
+// padded determinant is det * 2^(Np-N) and the padded G holds 1/2 on that block).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace slmc {
+
+// Field of item b: x + (xoff ? xoff[b] : b * xstride), laid out [Ltau][N].
+struct FieldRef {
+  const double* x;
+  const int64_t* xoff;   // device array or nullptr
+  int64_t xstride;
+};
+
+// Segment products S_k = B_{k n_s + len-1} ... B_{k n_s}, B_l = E diag(exp(-ldl x_l)),
+// for all items b < nb and segments k < m, into S[(b*m + k)][Np][Np] (FP64), and the
+// squared column norms of every S_k into snorm[(b*m + k)][Np].
+// prec: 0 FP64, 1 FP32 (acc_chunk = k-steps of 4 per FP64 promotion, 0 = none),
+// 2 bf16x3, 3 bf16x6.  E64/E32/Ebf point at the padded exponential in each format
+// (Ebf: [pieces][Np][Np] bf16 bit patterns).
+hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const float* E32,
+                            const uint16_t* Ebf, FieldRef f, int nb, int N, int Np, int Ltau,
+                            int n_s, int m, double ldl, double* S, double* snorm,
+                            hipStream_t st);
+
+// A[b] = Bsrc[b] Q[b] (Q = H_0 ... H_{Np-1} in compact-WY blocks: Householder vectors
+// in the strict lower triangle of QRW[b], T blocks in Tb[b][Np/16][16][16]).
+// Bsrc == nullptr means the identity.  transpose_out: write A^T instead of A.
+// npart != nullptr: squared column norms of each 16-row panel into npart[b][Np/16][Np].
+hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QRW,
+                           const double* Tb, double* A, double* npart, int transpose_out,
+                           int nb, int Np, hipStream_t st);
+
+// Column-pivoted (pre-sorted) blocked Householder QR of A[b] (one workgroup per item).
+// Sort key of column j: 0.5 log(sum_p norm2[b*nstride + p*Np + j]) + logDp[b][j].  Outputs: QRW[b]
+// (strict lower: Householder vectors; upper incl. diagonal: the V-update factor
+// F[i][j] = R[i][j]/|R[i][i]| exp(logDp[perm j] - logDp[perm i])), Tb, perm[b][Np],
+// logD[b][Np] = log|R_ii| + logDp[perm i], qsign[b] = det Q, status[b] |= 1 on NaN.
+hipError_t launch_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride,
+                     int nparts, const double* logDp, double* QRW, double* Tb, int* perm,
+                     double* logD, int* qsign, int* status, int nb, int Np, hipStream_t st);
+
+// dst[0..n) = value (a plain kernel, safe inside captured graphs)
+hipError_t launch_fill_i32(int* dst, int n, int value, hipStream_t st);
+
+// Vn[b] = F[b] Vo[b][perm[b], :] with F the upper triangle of QRW[b]
+// (Vo == nullptr: identity).
+hipError_t launch_vupd(const double* QRW, const int* perm, const double* Vo, double* Vn,
+                       int nb, int Np, hipStream_t st);
+
+// LU with partial pivoting of X = Db^-1 QT + Ds V (Db = max(e^logD,1), Ds = min(e^logD,1))
+// and logdet = sum max(logD, 0) + log|det X| - (Np-N) log 2, sign = qsign * sign det X.
+// Writes LU[b], prow[b], diagonal-block inverses DI[b][Np/16][2][16][16] and, through
+// the item map, logdet_out[item], sign_out[item], status_out[item].
+hipError_t launch_lu(const double* QT, const double* V, const double* logD, const int* qsign,
+                     const int* st_in, double* LU, int* prow, double* DI, const int* item_of,
+                     double* logdet_out, int8_t* sign_out, int32_t* status_out, int nb,
+                     int N, int Np, hipStream_t st);
+
+// Solve X Y = RHS with the LU of launch_lu.  mode 0: RHS = Db^-1 QT; mode 1: RHS = R.
+// accumulate: Gint += Y, else Gint = Y.  If Gout != nullptr also write the leading
+// N x N block of Gint to Gout + goff[b] (or b*N*N).
+hipError_t launch_lu_solve(int mode, const double* QT, const double* logD, const double* R,
+                           const double* LU, const int* prow, const double* DI, double* Gint,
+                           int accumulate, double* Gout, const int64_t* goff, int nb, int N,
+                           int Np, hipStream_t st);
+
+// R = Db^-1 QT - X Gint (residual of the recombination solve).
+hipError_t launch_residual(const double* QT, const double* V, const double* logD,
+                           const double* Gint, double* R, int nb, int Np, hipStream_t st);
+
+// ---- effective model / accept ----
+struct EffParams {
+  double Jk, J2, Jp, Jp6, a, Js0, Js1, Js2, Jt, delta;
+};
+
+hipError_t launch_eff_energy(const double* x, int nch, int Lx, int Ly, int Ltau, EffParams p,
+                             double* e, hipStream_t st);
+
+hipError_t launch_eff_sweep(double* x, int nch, int Lx, int Ly, int Ltau, EffParams p,
+                            int mod, int n_sweeps, uint64_t seed, uint64_t proposal,
+                            int64_t* nacc, hipStream_t st);
+
+// log w = -dtau S_Bose + 2 logdet for every chain.
+hipError_t launch_log_weight(const double* x, const double* logdet, int nch, int N, int Ltau,
+                             double lam, double omega0, double dtau, double c_kin,
+                             double* logw, hipStream_t st);
+
+// Cumulative accept: log r = (logw' - logw) + (E' - E); accept iff log u < log r.
+hipError_t launch_accept(double* x_cur, const double* x_prop, double* logw_cur,
+                         double* eeff_cur, const double* logw_prop, const double* eeff_prop,
+                         int nch, int64_t nelem, uint64_t seed, uint64_t proposal,
+                         uint8_t* accepted, double* log_ratio, hipStream_t st);
+
+}  // namespace slmc

@@ -1,0 +1,557 @@
+// Host side of the C ABI declared in include/slmc.h: argument validation, the device
+// constant cache (e^{-dtau K} per model and device, in FP64 / FP32 / bf16 pieces),
+// workspace layout, and the launch sequence of the hot path for every group of items
+// that share a model.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/slmc.h"
+#include "launch.h"
+
+using namespace slmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(SLMC_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+inline int roundup16(int n) { return (n + 15) / 16 * 16; }
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+int check_model(const slmc_model* m) {
+  if (!m) return fail(SLMC_E_ARG, "model is NULL");
+  if (m->Lx < 2 || m->Ly < 2) return fail(SLMC_E_SHAPE, "Lx, Ly must be >= 2 (got %d, %d)", m->Lx, m->Ly);
+  if ((int64_t)m->Lx * m->Ly > 512) return fail(SLMC_E_SHAPE, "N = Lx*Ly must be <= 512");
+  if (m->Ltau < 1) return fail(SLMC_E_SHAPE, "Ltau must be >= 1");
+  if (m->n_s < 1 || m->n_s > m->Ltau) return fail(SLMC_E_ARG, "n_s must be in [1, Ltau]");
+  if (!(m->dtau > 0.0) || !std::isfinite(m->dtau)) return fail(SLMC_E_ARG, "dtau must be > 0");
+  if (!std::isfinite(m->t) || !std::isfinite(m->mu) || !std::isfinite(m->lambda) ||
+      !std::isfinite(m->omega0) || !std::isfinite(m->c_kin))
+    return fail(SLMC_E_ARG, "model parameters must be finite");
+  return SLMC_OK;
+}
+
+int check_opt(const slmc_options* o) {
+  if (!o) return fail(SLMC_E_ARG, "options is NULL");
+  if (o->precision < 0 || o->precision > 3) return fail(SLMC_E_ARG, "unknown precision %d", o->precision);
+  if (o->residual_steps < 0 || o->residual_steps > 1) return fail(SLMC_E_ARG, "residual_steps must be 0 or 1");
+  if (!(o->acc_chunk == 0 || o->acc_chunk == 1 || o->acc_chunk == 2 || o->acc_chunk == 4 || o->acc_chunk == 8))
+    return fail(SLMC_E_ARG, "acc_chunk must be one of 0, 1, 2, 4, 8");
+  if (o->flags != 0) return fail(SLMC_E_ARG, "flags must be 0");
+  return SLMC_OK;
+}
+
+// e^{-dtau K}(i, j) from the Fourier modes of the periodic lattice:
+// (1/N) sum_k exp(-dtau eps_k) cos(k . (r_i - r_j)), eps_k = -2t(cos kx + cos ky) - mu.
+void host_expk(const slmc_model* m, std::vector<double>& E) {
+  const int Lx = m->Lx, Ly = m->Ly, N = Lx * Ly;
+  std::vector<double> disp(N, 0.0);   // value per displacement (dx, dy)
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int dy = 0; dy < Ly; ++dy)
+    for (int dx = 0; dx < Lx; ++dx) {
+      double s = 0.0;
+      for (int ny = 0; ny < Ly; ++ny)
+        for (int nx = 0; nx < Lx; ++nx) {
+          const double kx = two_pi * nx / Lx, ky = two_pi * ny / Ly;
+          const double eps = -2.0 * m->t * (std::cos(kx) + std::cos(ky)) - m->mu;
+          s += std::exp(-m->dtau * eps) * std::cos(kx * dx + ky * dy);
+        }
+      disp[dx + Lx * dy] = s / N;
+    }
+  E.assign((size_t)N * N, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const int dx = ((i % Lx) - (j % Lx) + Lx) % Lx, dy = ((i / Lx) - (j / Lx) + Ly) % Ly;
+      E[(size_t)i * N + j] = disp[dx + Lx * dy];
+    }
+}
+
+uint16_t bf16_rne_host(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+double bf16_to_double(uint16_t h) {
+  uint32_t u = ((uint32_t)h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+struct ModelConsts {
+  int Np = 0;
+  double* E64 = nullptr;
+  float* E32 = nullptr;
+  uint16_t* Ebf2 = nullptr;   // [2][Np][Np]
+  uint16_t* Ebf3 = nullptr;   // [3][Np][Np]
+};
+
+std::mutex g_cache_mu;
+std::map<std::tuple<int, int, int, double, double, double>, ModelConsts> g_cache;
+
+int get_consts(const slmc_model* m, ModelConsts** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  auto key = std::make_tuple(dev, m->Lx, m->Ly, m->t, m->mu, m->dtau);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(key);
+  if (it != g_cache.end()) { *out = &it->second; return SLMC_OK; }
+  const int N = m->Lx * m->Ly, Np = roundup16(N);
+  std::vector<double> E;
+  host_expk(m, E);
+  std::vector<double> Ep((size_t)Np * Np, 0.0);
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j)
+      Ep[(size_t)i * Np + j] = (i < N && j < N) ? E[(size_t)i * N + j] : (i == j ? 1.0 : 0.0);
+  std::vector<float> E32(Ep.size());
+  for (size_t k = 0; k < Ep.size(); ++k) E32[k] = (float)Ep[k];
+  std::vector<uint16_t> b2(2 * Ep.size()), b3(3 * Ep.size());
+  for (size_t k = 0; k < Ep.size(); ++k) {
+    double r = Ep[k];
+    for (int p = 0; p < 3; ++p) {
+      uint16_t h = bf16_rne_host((float)r);
+      b3[p * Ep.size() + k] = h;
+      if (p < 2) b2[p * Ep.size() + k] = h;
+      r -= bf16_to_double(h);
+    }
+  }
+  ModelConsts mc;
+  mc.Np = Np;
+  HIPCHK(hipMalloc(&mc.E64, Ep.size() * sizeof(double)));
+  HIPCHK(hipMalloc(&mc.E32, E32.size() * sizeof(float)));
+  HIPCHK(hipMalloc(&mc.Ebf2, b2.size() * sizeof(uint16_t)));
+  HIPCHK(hipMalloc(&mc.Ebf3, b3.size() * sizeof(uint16_t)));
+  HIPCHK(hipMemcpy(mc.E64, Ep.data(), Ep.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(mc.E32, E32.data(), E32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(mc.Ebf2, b2.data(), b2.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(mc.Ebf3, b3.data(), b3.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  auto res = g_cache.emplace(key, mc);
+  *out = &res.first->second;
+  return SLMC_OK;
+}
+
+// Carves 256-byte aligned sub-buffers out of a workspace (or only measures).
+struct Arena {
+  char* base;
+  size_t used = 0;
+  explicit Arena(void* b) : base((char*)b) {}
+  template <typename T> T* take(size_t n) {
+    T* p = base ? (T*)(base + used) : nullptr;
+    used += align256(n * sizeof(T));
+    return p;
+  }
+};
+
+struct GroupBufs {
+  double *S, *snorm, *A, *npart, *QRW, *Tb, *logD0, *logD1, *V0, *V1, *DI;
+  int *perm, *qsign, *status, *prow, *item_of;
+  int64_t *xoff, *goff;
+};
+
+void carve(Arena& a, int nb, int Np, int m, GroupBufs& g) {
+  const size_t n2 = (size_t)Np * Np;
+  g.S = a.take<double>((size_t)nb * std::max(m, 1) * n2);
+  g.snorm = a.take<double>((size_t)nb * m * Np);
+  g.A = a.take<double>((size_t)nb * n2);
+  g.npart = a.take<double>((size_t)nb * Np * (Np / 16));
+  g.QRW = a.take<double>((size_t)nb * n2);
+  g.Tb = a.take<double>((size_t)nb * Np * 16);
+  g.logD0 = a.take<double>((size_t)nb * Np);
+  g.logD1 = a.take<double>((size_t)nb * Np);
+  g.V0 = a.take<double>((size_t)nb * n2);
+  g.V1 = a.take<double>((size_t)nb * n2);
+  g.DI = a.take<double>((size_t)nb * Np * 32);
+  g.perm = a.take<int>((size_t)nb * Np);
+  g.qsign = a.take<int>(nb);
+  g.status = a.take<int>(nb);
+  g.prow = a.take<int>((size_t)nb * Np);
+  g.item_of = a.take<int>(nb);
+  g.xoff = a.take<int64_t>(nb);
+  g.goff = a.take<int64_t>(nb);
+}
+
+struct Group {
+  int model;
+  std::vector<int> items;
+};
+
+int build_groups(const slmc_model* models, int n_models, const slmc_batch* batch,
+                 std::vector<Group>& groups) {
+  if (!batch) return fail(SLMC_E_ARG, "batch is NULL");
+  if (batch->n_items < 0) return fail(SLMC_E_ARG, "n_items < 0");
+  if (!models || n_models < 1) return fail(SLMC_E_ARG, "no models");
+  for (int k = 0; k < n_models; ++k) {
+    int rc = check_model(&models[k]);
+    if (rc) return rc;
+  }
+  if (n_models > 1 && !batch->model_idx) return fail(SLMC_E_ARG, "several models need model_idx");
+  if (n_models > 1 && (!batch->x_off)) return fail(SLMC_E_ARG, "several models need x_off");
+  groups.clear();
+  std::vector<int> gid(n_models, -1);
+  for (int b = 0; b < batch->n_items; ++b) {
+    const int mi = batch->model_idx ? batch->model_idx[b] : 0;
+    if (mi < 0 || mi >= n_models) return fail(SLMC_E_ARG, "model_idx[%d] = %d out of range", b, mi);
+    if (batch->x_off && batch->x_off[b] < 0) return fail(SLMC_E_ARG, "x_off[%d] < 0", b);
+    if (batch->g_off && batch->g_off[b] < 0) return fail(SLMC_E_ARG, "g_off[%d] < 0", b);
+    if (gid[mi] < 0) { gid[mi] = (int)groups.size(); groups.push_back(Group{mi, {}}); }
+    groups[gid[mi]].items.push_back(b);
+  }
+  return SLMC_OK;
+}
+
+size_t group_bytes(const slmc_model* m, int nb) {
+  const int Np = roundup16(m->Lx * m->Ly);
+  const int mseg = (m->Ltau + m->n_s - 1) / m->n_s;
+  Arena a(nullptr);
+  GroupBufs g;
+  carve(a, nb, Np, mseg, g);
+  return a.used;
+}
+
+// The hot path for one group of items sharing a model.
+int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, const slmc_batch* batch,
+              const double* x, double* logdet, int8_t* sign, double* G, int32_t* status,
+              GroupBufs& w, hipStream_t st) {
+  ModelConsts* mc = nullptr;
+  int rc = get_consts(m, &mc);
+  if (rc) return rc;
+  const int N = m->Lx * m->Ly, Np = mc->Np, nb = (int)grp.items.size();
+  const int mseg = (m->Ltau + m->n_s - 1) / m->n_s;
+  const size_t n2 = (size_t)Np * Np;
+  const double ldl = m->dtau * m->lambda;
+  if ((o->precision == 2 || o->precision == 3) && Np % 32 != 0)
+    return fail(SLMC_E_UNSUPPORTED, "bf16 split precisions need N rounded to 16 to be a multiple of 32 (N=%d)", N);
+
+  // item map and field/G offsets: affine ranges go in kernel arguments, anything else
+  // is uploaded (synchronously) into the workspace
+  const int i0 = grp.items[0];
+  bool contiguous = true;
+  for (int j = 0; j < nb; ++j) contiguous &= (grp.items[j] == i0 + j);
+  const int64_t xn = (int64_t)m->Ltau * N;
+  auto xo = [&](int item) { return batch->x_off ? batch->x_off[item] : (int64_t)item * xn; };
+  auto go = [&](int item) { return batch->g_off ? batch->g_off[item] : (int64_t)item * N * N; };
+  bool x_aff = true, g_aff = true;
+  for (int j = 0; j < nb; ++j) {
+    x_aff &= (xo(grp.items[j]) == xo(i0) + (int64_t)j * xn);
+    g_aff &= (go(grp.items[j]) == go(i0) + (int64_t)j * N * N);
+  }
+  FieldRef f{x + xo(i0), nullptr, xn};
+  const int* item_of = nullptr;
+  double* ld_out = logdet + (contiguous ? i0 : 0);
+  int8_t* sg_out = sign + (contiguous ? i0 : 0);
+  int32_t* st_out = status + (contiguous ? i0 : 0);
+  double* g_out = G ? G + go(i0) : nullptr;
+  const int64_t* goff = nullptr;
+  if (!x_aff || !contiguous || (G && !g_aff)) {
+    std::vector<int64_t> xv(nb), gv(nb);
+    std::vector<int> iv(nb);
+    for (int j = 0; j < nb; ++j) { xv[j] = xo(grp.items[j]); gv[j] = go(grp.items[j]); iv[j] = grp.items[j]; }
+    HIPCHK(hipMemcpy(w.xoff, xv.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(w.goff, gv.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(w.item_of, iv.data(), nb * sizeof(int), hipMemcpyHostToDevice));
+    if (!x_aff) f = FieldRef{x, w.xoff, 0};
+    if (!contiguous) { item_of = w.item_of; ld_out = logdet; sg_out = sign; st_out = status; }
+    if (G && !g_aff) { g_out = G; goff = w.goff; }
+  }
+
+  HIPCHK(launch_fill_i32(w.status, nb, 0, st));
+  // a2: segment products (a1 fused: the phonon factors scale the panel rows)
+  HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32,
+                          o->precision == 2 ? mc->Ebf2 : mc->Ebf3, f, nb, N, Np, m->Ltau, m->n_s,
+                          mseg, ldl, w.S, w.snorm, st));
+  // a3: stabilized accumulation
+  double* logD[2] = {w.logD0, w.logD1};
+  double* Vb[2] = {w.V0, w.V1};
+  for (int k = 0; k < mseg; ++k) {
+    const double* Ain;
+    int64_t astride, nstride;
+    const double* nrm;
+    int nparts;
+    if (k == 0) {
+      // the first QR factors S_0 itself; its column norms come from the segment kernel
+      Ain = w.S;
+      astride = (int64_t)mseg * n2;
+      nrm = w.snorm;
+      nstride = (int64_t)mseg * Np;
+      nparts = 1;
+    } else {
+      HIPCHK(launch_wy_apply(w.S + (size_t)k * n2, (int64_t)mseg * n2, w.QRW, w.Tb, w.A, w.npart, 0,
+                             nb, Np, st));
+      Ain = w.A;
+      astride = (int64_t)n2;
+      nrm = w.npart;
+      nparts = Np / 16;
+      nstride = (int64_t)nparts * Np;
+    }
+    HIPCHK(launch_qr(Ain, astride, nrm, nstride, nparts, k == 0 ? nullptr : logD[(k + 1) & 1], w.QRW, w.Tb,
+                     w.perm, logD[k & 1], w.qsign, w.status, nb, Np, st));
+    HIPCHK(launch_vupd(w.QRW, w.perm, k == 0 ? nullptr : Vb[(k + 1) & 1], Vb[k & 1], nb, Np, st));
+  }
+  const double* logDf = logD[(mseg - 1) & 1];
+  const double* Vf = Vb[(mseg - 1) & 1];
+  double* Gint = Vb[mseg & 1];   // the other V buffer is free now
+  double* QT = w.A;
+  double* LU = w.S;
+  // U^T = Q_m^T explicitly, then a4: recombination
+  HIPCHK(launch_wy_apply(nullptr, 0, w.QRW, w.Tb, QT, nullptr, 1, nb, Np, st));
+  HIPCHK(launch_lu(QT, Vf, logDf, w.qsign, w.status, LU, w.prow, w.DI, item_of, ld_out, sg_out,
+                   st_out, nb, N, Np, st));
+  if (G) {
+    const bool resid = o->residual_steps > 0;
+    HIPCHK(launch_lu_solve(0, QT, logDf, nullptr, LU, w.prow, w.DI, Gint, 0, resid ? nullptr : g_out,
+                           goff, nb, N, Np, st));
+    if (resid) {
+      // a5: R = Db^-1 U^T - X G, G += X^-1 R
+      double* R = w.QRW;
+      HIPCHK(launch_residual(QT, Vf, logDf, Gint, R, nb, Np, st));
+      HIPCHK(launch_lu_solve(1, QT, logDf, R, LU, w.prow, w.DI, Gint, 1, g_out, goff, nb, N, Np, st));
+    }
+  }
+  return SLMC_OK;
+}
+
+int fermion_call(const slmc_model* models, int32_t n_models, const slmc_batch* batch,
+                 const slmc_options* opt, const double* x, double* logdet, int8_t* sign, double* G,
+                 int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_opt(opt);
+  if (rc) return rc;
+  std::vector<Group> groups;
+  rc = build_groups(models, n_models, batch, groups);
+  if (rc) return rc;
+  if (batch->n_items == 0) return SLMC_OK;
+  if (!x || !logdet || !sign || !status) return fail(SLMC_E_ARG, "NULL output or input pointer");
+  if (n_models > 1 && G && !batch->g_off) return fail(SLMC_E_ARG, "several models need g_off");
+  size_t need = 0;
+  for (auto& g : groups) need += group_bytes(&models[g.model], (int)g.items.size());
+  if (!ws || ws_bytes < need)
+    return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  Arena a(ws);
+  hipStream_t st = (hipStream_t)stream;
+  for (auto& g : groups) {
+    const slmc_model* m = &models[g.model];
+    GroupBufs w;
+    carve(a, (int)g.items.size(), roundup16(m->Lx * m->Ly), (m->Ltau + m->n_s - 1) / m->n_s, w);
+    rc = run_group(m, opt, g, batch, x, logdet, sign, G, status, w, st);
+    if (rc) return rc;
+  }
+  return SLMC_OK;
+}
+
+int colour_mod(const slmc_model* m, const slmc_eff* e, int* mod) {
+  const int rng = e->Js[2] != 0.0 ? 3 : (e->Js[1] != 0.0 ? 2 : (e->Js[0] != 0.0 ? 1 : 0));
+  int c[2] = {1, 0};
+  if (rng == 0) { c[0] = 1; c[1] = 0; }
+  else if (rng <= 2) { c[0] = 2; c[1] = 3; }
+  else { c[0] = 4; c[1] = 3; }
+  for (int k = 0; k < 2; ++k)
+    if (c[k] > 0 && m->Lx % c[k] == 0 && m->Ly % c[k] == 0) { *mod = c[k]; return SLMC_OK; }
+  return fail(SLMC_E_SHAPE, "no checkerboard colouring for a %dx%d lattice with this coupling range", m->Lx, m->Ly);
+}
+
+EffParams eff_params(const slmc_eff* e) {
+  return EffParams{e->Jk, e->J2, e->Jp, e->Jp6, e->a, e->Js[0], e->Js[1], e->Js[2], e->Jt, e->delta};
+}
+
+size_t accept_bytes(const slmc_model* m, int nch) {
+  size_t b = group_bytes(m, nch);
+  b += 5 * align256((size_t)nch * sizeof(double)) + 2 * align256((size_t)nch * sizeof(int));
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slmc_version(void) { return 10000; }
+
+const char* slmc_last_error(void) { return g_err.c_str(); }
+
+int slmc_expk(const slmc_model* model, double* E_host) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (!E_host) return fail(SLMC_E_ARG, "E_host is NULL");
+  std::vector<double> E;
+  host_expk(model, E);
+  std::memcpy(E_host, E.data(), E.size() * sizeof(double));
+  return SLMC_OK;
+}
+
+size_t slmc_workspace_bytes(const slmc_model* models, int32_t n_models, const slmc_batch* batch,
+                            const slmc_options* opt) {
+  (void)opt;
+  std::vector<Group> groups;
+  if (build_groups(models, n_models, batch, groups)) return 0;
+  size_t need = 0;
+  for (auto& g : groups) need += group_bytes(&models[g.model], (int)g.items.size());
+  return need;
+}
+
+int slmc_logdet(const slmc_model* models, int32_t n_models, const slmc_batch* batch,
+                const slmc_options* opt, const double* x, double* logdet, int8_t* sign,
+                int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  return fermion_call(models, n_models, batch, opt, x, logdet, sign, nullptr, status, ws, ws_bytes,
+                      stream);
+}
+
+int slmc_green(const slmc_model* models, int32_t n_models, const slmc_batch* batch,
+               const slmc_options* opt, const double* x, double* logdet, int8_t* sign, double* G,
+               int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  if (!G) { g_err = "G is NULL"; return SLMC_E_ARG; }
+  return fermion_call(models, n_models, batch, opt, x, logdet, sign, G, status, ws, ws_bytes, stream);
+}
+
+int slmc_eff_energy(const slmc_model* model, const slmc_eff* eff, int32_t n_chains, const double* x,
+                    double* e_eff, void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (!eff || !x || !e_eff) return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_chains < 0) return fail(SLMC_E_ARG, "n_chains < 0");
+  if (model->Ltau < 2) return fail(SLMC_E_SHAPE, "Ltau must be >= 2");
+  if (n_chains == 0) return SLMC_OK;
+  HIPCHK(launch_eff_energy(x, n_chains, model->Lx, model->Ly, model->Ltau, eff_params(eff), e_eff,
+                           (hipStream_t)stream));
+  return SLMC_OK;
+}
+
+int slmc_eff_sweep(const slmc_model* model, const slmc_eff* eff, int32_t n_chains, double* x,
+                   int32_t n_sweeps, uint64_t seed, uint64_t proposal_idx, int64_t* n_accepted,
+                   void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (!eff || !x || !n_accepted) return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_chains < 0 || n_sweeps < 0) return fail(SLMC_E_ARG, "negative count");
+  if (model->Ltau < 2 || model->Ltau % 2) return fail(SLMC_E_SHAPE, "Ltau must be even and >= 2");
+  if (!std::isfinite(eff->delta)) return fail(SLMC_E_ARG, "delta must be finite");
+  int mod = 1;
+  rc = colour_mod(model, eff, &mod);
+  if (rc) return rc;
+  if (n_chains == 0) return SLMC_OK;
+  HIPCHK(launch_eff_sweep(x, n_chains, model->Lx, model->Ly, model->Ltau, eff_params(eff), mod,
+                          n_sweeps, seed, proposal_idx, n_accepted, (hipStream_t)stream));
+  return SLMC_OK;
+}
+
+size_t slmc_accept_workspace_bytes(const slmc_model* model, int32_t n_chains,
+                                   const slmc_options* opt) {
+  (void)opt;
+  if (!model || n_chains < 1 || check_model(model)) return 0;
+  return accept_bytes(model, n_chains);
+}
+
+int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_chains,
+                    const double* x, double* logw, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  rc = check_opt(opt);
+  if (rc) return rc;
+  if (!x || !logw) return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_chains < 1) return fail(SLMC_E_ARG, "n_chains must be >= 1");
+  const size_t need = accept_bytes(model, n_chains);
+  if (!ws || ws_bytes < need) return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  Arena a(ws);
+  GroupBufs w;
+  const int Np = roundup16(model->Lx * model->Ly);
+  carve(a, n_chains, Np, (model->Ltau + model->n_s - 1) / model->n_s, w);
+  double* ld = a.take<double>(n_chains);
+  int8_t* sg = (int8_t*)a.take<int>(n_chains);
+  int32_t* stt = a.take<int32_t>(n_chains);
+  Group grp{0, {}};
+  for (int c = 0; c < n_chains; ++c) grp.items.push_back(c);
+  slmc_batch bt{n_chains, nullptr, nullptr, nullptr};
+  hipStream_t st = (hipStream_t)stream;
+  rc = run_group(model, opt, grp, &bt, x, ld, sg, nullptr, stt, w, st);
+  if (rc) return rc;
+  HIPCHK(launch_log_weight(x, ld, n_chains, model->Lx * model->Ly, model->Ltau, model->lambda,
+                           model->omega0, model->dtau, model->c_kin, logw, st));
+  return SLMC_OK;
+}
+
+int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff, const slmc_options* opt,
+                           int32_t n_chains, double* x_cur, const double* x_prop, double* logw_cur,
+                           double* eeff_cur, uint64_t seed, uint64_t proposal_idx,
+                           uint8_t* accepted, double* log_ratio, void* ws, size_t ws_bytes,
+                           void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  rc = check_opt(opt);
+  if (rc) return rc;
+  if (!eff || !x_cur || !x_prop || !logw_cur || !eeff_cur || !accepted || !log_ratio)
+    return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_chains < 1) return fail(SLMC_E_ARG, "n_chains must be >= 1");
+  if (model->Ltau < 2) return fail(SLMC_E_SHAPE, "Ltau must be >= 2");
+  const size_t need = accept_bytes(model, n_chains);
+  if (!ws || ws_bytes < need) return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  Arena a(ws);
+  GroupBufs w;
+  const int N = model->Lx * model->Ly, Np = roundup16(N);
+  carve(a, n_chains, Np, (model->Ltau + model->n_s - 1) / model->n_s, w);
+  double* ld = a.take<double>(n_chains);
+  double* eep = a.take<double>(n_chains);
+  double* lwp = a.take<double>(n_chains);
+  a.take<double>(n_chains);
+  a.take<double>(n_chains);
+  int8_t* sg = (int8_t*)a.take<int>(n_chains);
+  int32_t* stt = a.take<int32_t>(n_chains);
+  Group grp{0, {}};
+  for (int c = 0; c < n_chains; ++c) grp.items.push_back(c);
+  slmc_batch bt{n_chains, nullptr, nullptr, nullptr};
+  hipStream_t st = (hipStream_t)stream;
+  rc = run_group(model, opt, grp, &bt, x_prop, ld, sg, nullptr, stt, w, st);
+  if (rc) return rc;
+  HIPCHK(launch_eff_energy(x_prop, n_chains, model->Lx, model->Ly, model->Ltau, eff_params(eff), eep, st));
+  HIPCHK(launch_log_weight(x_prop, ld, n_chains, N, model->Ltau, model->lambda, model->omega0,
+                           model->dtau, model->c_kin, lwp, st));
+  HIPCHK(launch_accept(x_cur, x_prop, logw_cur, eeff_cur, lwp, eep, n_chains,
+                       (int64_t)N * model->Ltau, seed, proposal_idx, accepted, log_ratio, st));
+  return SLMC_OK;
+}
+
+void slmc_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& kv : g_cache) {
+    int dev = std::get<0>(kv.first), cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(dev);
+    (void)hipFree(kv.second.E64);
+    (void)hipFree(kv.second.E32);
+    (void)hipFree(kv.second.Ebf2);
+    (void)hipFree(kv.second.Ebf3);
+    (void)hipSetDevice(cur);
+  }
+  g_cache.clear();
+}
+
+}  // extern "C"

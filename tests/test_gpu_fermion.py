@@ -1,0 +1,216 @@
+"""GPU parity of the fermion weight (SM Eqs. S2, S3): the HIP path through the C ABI
+against the FP64 CPU oracle on the same seeded inputs.
+
+Bars (max over items): FP64 path: relative log-det error <= 1e-11, max|dG| <= 1e-9, sign
+exact.  Mixed paths: relative log-det error <= 1e-8 for the FP32 path with FP64
+promotion every k-step; the other variants are measured against their own looser bars
+(printed with the test output)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import workload_item, workload_models, gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1802_06177_amd as slmc  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _E(md):
+    return oracle.expk(oracle.hopping_matrix(md["Lx"], md["Ly"], md["t"], md["mu"]), md["dtau"])
+
+
+def _ref(md, x):
+    return oracle.logdet_green(_E(md), x, md["dtau"], md["lam"], md["n_s"])
+
+
+def _run(md, xs, prec="fp64", resid=0, chunk=0, want_g=True):
+    print("case: %dx%d Ltau=%d n_s=%d items=%d prec=%s chunk=%d resid=%d" %
+          (md["Lx"], md["Ly"], md["Ltau"], md["n_s"], len(xs), prec, chunk, resid), flush=True)
+    m = slmc.model_from_dict(md)
+    x = torch.tensor(np.stack(xs), dtype=torch.float64, device=DEV)
+    opt = slmc.options(prec, resid, chunk)
+    if want_g:
+        ld, sg, G, st = slmc.green(m, x, opt)
+        torch.cuda.synchronize()
+        return ld.cpu().numpy(), sg.cpu().numpy(), G.cpu().numpy(), st.cpu().numpy()
+    ld, sg, st = slmc.logdet(m, x, opt)
+    torch.cuda.synchronize()
+    return ld.cpu().numpy(), sg.cpu().numpy(), None, st.cpu().numpy()
+
+
+def _check(md, xs, out, rel_tol, g_tol, sign=True):
+    ld, sg, G, st = out
+    worst_rel, worst_g = 0.0, 0.0
+    for k, x in enumerate(xs):
+        ref, rs, rG = _ref(md, x)
+        assert st[k] == 0
+        rel = abs(ld[k] - ref) / abs(ref)
+        worst_rel = max(worst_rel, rel)
+        if sign:
+            assert sg[k] == rs, (k, sg[k], rs)
+        if G is not None:
+            worst_g = max(worst_g, float(np.max(np.abs(G[k] - rG))))
+    print("  max rel logdet %.3e  max|dG| %.3e" % (worst_rel, worst_g), flush=True)
+    assert worst_rel <= rel_tol
+    assert worst_g <= g_tol
+    return worst_rel, worst_g
+
+
+def _md(L, Ltau, n_s, lam=1.5, Ly=None, mu=0.0):
+    return dict(Lx=L, Ly=Ly or L, Ltau=Ltau, n_s=n_s, t=1.0, mu=mu, dtau=0.1, lam=lam,
+                omega0=1.0, c_kin=0.5)
+
+
+# ------------------------------------------------------------------------- FP64 path
+
+def test_fp64_workload_4x4_all_items():
+    md = workload_models("W1")[0]
+    xs = [workload_item("W1", b)[1] for b in range(64)]
+    _check(md, xs, _run(md, xs), 1e-11, 1e-9)
+
+
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s,lam", [(2, 2, 12, 4, 3.0), (2, 3, 10, 3, 2.5),
+                                                (4, 4, 37, 10, 1.5), (4, 4, 20, 1, 1.5),
+                                                (4, 4, 20, 20, 1.5), (6, 6, 30, 7, 2.0),
+                                                (6, 4, 24, 5, 1.0), (10, 10, 40, 8, 1.5)])
+def test_fp64_shapes_ragged_and_padded(Lx, Ly, Ltau, n_s, lam):
+    md = _md(Lx, Ltau, n_s, lam, Ly=Ly, mu=0.1)
+    g = gen(99, Lx * 1000 + Ly * 100 + Ltau)
+    xs = [g.normal(0.0, 1.5, size=(Ltau, Lx * Ly)) for _ in range(6)]
+    _check(md, xs, _run(md, xs), 1e-11, 1e-9)
+
+
+def test_fp64_negative_determinants_keep_their_sign():
+    md = _md(2, 40, 5, 3.0)
+    g = gen(98, 1)
+    xs = [g.normal(0.0, 3.0, size=(40, 4)) for _ in range(40)]
+    out = _run(md, xs)
+    refs = [_ref(md, x)[1] for x in xs]
+    assert min(refs) < 0 < max(refs)
+    _check(md, xs, out, 1e-11, 1e-9)
+
+
+def test_fp64_workload_8x8_subset():
+    md = workload_models("W2")[0]
+    xs = [workload_item("W2", b)[1] for b in range(0, 256, 32)]
+    _check(md, xs, _run(md, xs), 1e-11, 1e-9)
+
+
+def test_fp64_closed_form_staggered_16x16():
+    # the 16 staggered fields of the 16x16 workload (noiseless) against the momentum-pair
+    # closed form, on the full size
+    import pins
+    md = workload_models("W4", 2)[0]
+    items = [128, 129]
+    xs = [workload_item("W4", b, 2)[1] for b in items]
+    ld, sg, _, st = _run(md, xs, want_g=False)
+    for k, b in enumerate(items):
+        x0 = xs[k][0, 0]
+        ref = pins.staggered_logdet(16, 16, 1.0, 0.0, 0.1, md["lam"], x0, md["Ltau"])
+        assert st[k] == 0 and sg[k] == 1
+        assert abs(ld[k] - ref) <= 1e-11 * abs(ref), (ld[k], ref)
+
+
+def test_fp64_free_fermion_16x16():
+    import pins
+    md = workload_models("W4")[0]
+    ld, sg, G, st = _run(md, [np.zeros((160, 256))])
+    ref = pins.free_logdet(16, 16, 1.0, 0.0, 16.0)
+    assert abs(ld[0] - ref) <= 1e-11 * ref
+    assert np.max(np.abs(G[0] - pins.free_green(16, 16, 1.0, 0.0, 16.0))) < 1e-9
+
+
+def test_fp64_full_size_16x16_sampled_items():
+    md = workload_models("W4", 1)[0]
+    xs = [workload_item("W4", b, 1)[1] for b in (0, 77)]
+    _check(md, xs, _run(md, xs), 1e-11, 1e-9)
+
+
+def test_uneven_batch_one_call():
+    # three lattice sizes in one call, packed, items interleaved across models
+    mds = [_md(4, 40, 10), _md(6, 30, 10), _md(8, 80, 10)]
+    models = [slmc.model_from_dict(d) for d in mds]
+    order = [0, 1, 2, 0, 2, 1, 1, 0]
+    g = gen(97, 5)
+    xs = [g.normal(size=(mds[k]["Ltau"], mds[k]["Lx"] ** 2)) for k in order]
+    x_off = np.cumsum([0] + [x.size for x in xs[:-1]])
+    g_sizes = [mds[k]["Lx"] ** 4 for k in order]
+    g_off = np.cumsum([0] + g_sizes[:-1])
+    x = torch.tensor(np.concatenate([a.ravel() for a in xs]), dtype=torch.float64, device=DEV)
+    G = torch.zeros(int(sum(g_sizes)), dtype=torch.float64, device=DEV)
+    ld, sg, G, st = slmc.green(models, x, slmc.options(), model_idx=order, x_off=x_off,
+                               g_off=g_off, n_items=len(order), G=G)
+    torch.cuda.synchronize()
+    ld, sg, Gh, st = ld.cpu().numpy(), sg.cpu().numpy(), G.cpu().numpy(), st.cpu().numpy()
+    for j, k in enumerate(order):
+        ref, rs, rG = _ref(mds[k], xs[j])
+        N = mds[k]["Lx"] ** 2
+        Gj = Gh[g_off[j]:g_off[j] + N * N].reshape(N, N)
+        assert st[j] == 0 and sg[j] == rs
+        assert abs(ld[j] - ref) <= 1e-11 * abs(ref)
+        assert np.max(np.abs(Gj - rG)) < 1e-9
+
+
+def test_nonfinite_input_flags_only_that_item():
+    md = _md(4, 20, 5)
+    g = gen(96, 1)
+    xs = [g.normal(size=(20, 16)) for _ in range(3)]
+    xs[1] = xs[1].copy()
+    xs[1][3, 5] = np.nan
+    ld, sg, G, st = _run(md, xs)
+    assert st[1] == 5 and np.isnan(ld[1])
+    assert st[0] == 0 and st[2] == 0
+    for k in (0, 2):
+        assert abs(ld[k] - _ref(md, xs[k])[0]) <= 1e-11 * abs(ld[k])
+
+
+def test_run_twice_bitwise_identical():
+    md = workload_models("W2")[0]
+    xs = [workload_item("W2", b)[1] for b in range(4)]
+    a = _run(md, xs, prec="fp32", chunk=1)
+    b = _run(md, xs, prec="fp32", chunk=1)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+
+
+def test_residual_step_does_not_degrade_G():
+    md = workload_models("W2")[0]
+    xs = [workload_item("W2", b)[1] for b in range(3)]
+    g0 = _check(md, xs, _run(md, xs, resid=0), 1e-11, 1e-9)[1]
+    g1 = _check(md, xs, _run(md, xs, resid=1), 1e-11, 1e-9)[1]
+    assert g1 <= 2 * g0 + 1e-14
+
+
+def test_logdet_only_equals_green_logdet():
+    md = workload_models("W1")[0]
+    xs = [workload_item("W1", b)[1] for b in range(8)]
+    a = _run(md, xs, want_g=False)
+    b = _run(md, xs)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------------- mixed paths
+
+def test_fp32_promoted_meets_1e8_on_8x8():
+    md = workload_models("W2")[0]
+    xs = [workload_item("W2", b)[1] for b in range(0, 256, 64)]
+    _check(md, xs, _run(md, xs, prec="fp32", chunk=1, resid=1), 1e-8, 1e-6)
+
+
+@pytest.mark.parametrize("prec,chunk,rel_bar,g_bar", [("fp32", 0, 2e-6, 1e-4), ("fp32", 4, 1e-7, 1e-5),
+                                                      ("bf16x6", 0, 2e-6, 1e-4),
+                                                      ("bf16x3", 0, 1e-4, 1e-3)])
+def test_mixed_variants_error_bars_8x8(prec, chunk, rel_bar, g_bar):
+    md = workload_models("W2")[0]
+    xs = [workload_item("W2", b)[1] for b in range(0, 256, 64)]
+    _check(md, xs, _run(md, xs, prec=prec, chunk=chunk), rel_bar, g_bar)
+
+
+def test_fp32_promoted_full_size_16x16():
+    md = workload_models("W4", 1)[0]
+    xs = [workload_item("W4", b, 1)[1] for b in (3,)]
+    _check(md, xs, _run(md, xs, prec="fp32", chunk=1, resid=1), 1e-8, 1e-6)
