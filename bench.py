@@ -1,0 +1,167 @@
+"""Benchmark of the fermion-weight hot path on one MI355X.
+
+Workload (the 16x16 configuration): 128 chains of a 16x16 periodic lattice (N = 256),
+beta = 16 (Ltau = 160, dtau = 0.1), stabilization every n_s = 8 slices, lam = 1.5,
+omega0 = 1, Gaussian N(0, 1) phonon fields (seeded), and a seeded symmetric effective
+model (on-site x^2, time-adjacent and spatial NN/NNN/third-neighbour couplings).
+
+One step = one SLMC cumulative update of every chain, i.e. every step of the hot path:
+  copy x -> x'; one checkerboard Metropolis sweep of the effective model on x' (N Ltau
+  site updates); log|det(1 + B...B)| and the Green's function G of every proposal (model
+  setup, fused slice scaling, segment products, stabilized QR/UDV chain, recombination,
+  FP64 residual step); bosonic action, effective energy and the accept/copy of Eq. 6.
+value = chains * steps / time  (fermion log-det + G evaluations per second).
+
+Also printed: a roofline line for the dominant kernel (HIP events around its launches on
+its stream), and the FP64 CPU oracle timed on a bounded sample of the same fields.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense matrix-core TFLOP/s, MI355X
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    ap.add_argument("--acc-chunk", type=int, default=0)
+    ap.add_argument("--residual", type=int, default=1)
+    ap.add_argument("--chains", type=int, default=128)
+    ap.add_argument("--lam", type=float, default=1.5)
+    ap.add_argument("--cpu-sample", type=int, default=6, help="oracle items for cpu_baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(chains shard across GPUs with no exchange; no multi-GPU run is part of it).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1802_06177_amd as slmc
+    from synth import workload_item, workload_models, eff_coefficients
+
+    dev = torch.device("cuda:0")
+    lam_idx = {1.0: 0, 1.5: 1, 2.0: 2}.get(args.lam, 1)
+    md = dict(workload_models("W4", lam_idx)[0])
+    md["lam"] = args.lam
+    N, Lt, n_s, B = md["Lx"] * md["Ly"], md["Ltau"], md["n_s"], args.chains
+    m = slmc.model_from_dict(md)
+    ec = eff_coefficients(4, 0, args.lam, delta=0.6)
+    eff = slmc.eff_model(**ec)
+    opt = slmc.options(args.precision, args.residual, args.acc_chunk)
+
+    xs = np.stack([workload_item("W4", b % 128, lam_idx)[1] for b in range(B)])
+    x_cur = torch.tensor(xs, dtype=torch.float64, device=dev)
+    x_prop = torch.empty_like(x_cur)
+    G = torch.empty((B, N, N), dtype=torch.float64, device=dev)
+    logw = slmc.log_weight(m, x_cur, opt)
+    eeff = slmc.eff_energy(m, eff, x_cur)
+    seed = 20180216
+
+    def step(k):
+        x_prop.copy_(x_cur)
+        slmc.eff_sweep(m, eff, x_prop, 1, seed, k)
+        return slmc.cumulative_accept(m, eff, x_cur, x_prop, logw, eeff, seed, k, opt, G_prop=G)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    slmc.profile_reset()
+    slmc.profile(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    t0 = time.perf_counter()
+    acc_total = 0
+    accs = []
+    for k in range(args.warmup, args.warmup + args.steps):
+        a, _ = step(k)
+        accs.append(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    slmc.profile(False)
+    ms = ev0.elapsed_time(ev1)
+    prof = slmc.profile_read()
+    acc_total = int(sum(int(a.sum().item()) for a in accs))
+    ms_per_step = ms / args.steps
+    value = B * args.steps / (ms / 1e3)
+
+    # dominant kernel and its roofline (algorithmic flops per launch / event-timed duration)
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    nseg = (Lt + n_s - 1) // n_s
+    flops = {
+        "seg_chain": 2.0 * N ** 3 * (Lt - nseg) * B,        # (n_s - 1) products per segment
+        "qr": (4.0 / 3.0) * N ** 3 * B,                      # Householder QR of N x N
+        "wy_apply": 2.0 * N ** 3 * B,                        # S_k Q_{k-1}
+        "vupd": 1.0 * N ** 3 * B,                            # triangular times dense
+        "lu": (2.0 / 3.0) * N ** 3 * B,
+        "lu_solve": 2.0 * N ** 3 * B,
+        "residual": 2.0 * N ** 3 * B,
+    }
+    prec_dtype = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}[args.precision]
+    kern_dtype = prec_dtype if dom == "seg_chain" else "f64"
+    achieved = flops.get(dom, 0.0) / (dom_ms / dom_n / 1e3) / 1e12 if dom_n else 0.0
+    roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
+            "peak": PEAK[kern_dtype], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[kern_dtype], 4), "traffic": None,
+            "avg_launch_ms": round(dom_ms / dom_n, 4) if dom_n else None,
+            "per_class_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]}}
+
+    # CPU oracle on a bounded sample of the same fields (log-det + G), and the error of the
+    # GPU path on those items
+    cpu = None
+    err = None
+    if args.cpu_sample > 0:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count() or 1
+        E = oracle.expk(oracle.hopping_matrix(md["Lx"], md["Ly"], md["t"], md["mu"]), md["dtau"])
+        ns = min(args.cpu_sample, B)
+        xsamp = xs[:ns]
+        ld_g, _, G_g, _ = slmc.green(m, torch.tensor(xsamp, device=dev), opt)
+        torch.cuda.synchronize()
+        ld_g, G_g = ld_g.cpu().numpy(), G_g.cpu().numpy()
+        t1 = time.perf_counter()
+        refs = [oracle.logdet_green(E, xsamp[k], md["dtau"], md["lam"], n_s) for k in range(ns)]
+        tc = time.perf_counter() - t1
+        cpu = {"value": round(ns / tc, 4), "unit": "evals/s", "cores": int(cores), "kind": "oracle",
+               "sample": "%d of the %d fields (16x16, Ltau=160, n_s=8, lam=%.1f), log-det + G, "
+                         "numpy/scipy FP64 (LAPACK QRP + LU)" % (ns, B, md["lam"])}
+        err = {"max_rel_logdet": float(max(abs(ld_g[k] - refs[k][0]) / abs(refs[k][0]) for k in range(ns))),
+               "max_abs_G": float(max(np.max(np.abs(G_g[k] - refs[k][2])) for k in range(ns))),
+               "items": ns}
+
+    out = {
+        "metric": "fermion logdet+G evals/s at N=256,Ltau=160: mixed vs FP64, <=1e-8 rel err",
+        "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec_dtype, "data": "synthetic",
+        "config": {"workload": "16x16 (N=256), beta=16 (Ltau=160), n_s=8, lam=%.1f, omega0=1, "
+                              "%d chains; step = sweep + logdet+G of proposals + accept" % (md["lam"], B),
+                   "precision": args.precision, "acc_chunk": args.acc_chunk,
+                   "residual_steps": args.residual, "global_batch": B, "parallelism": "none"},
+        "roofline": roof, "cpu_baseline": cpu, "error_vs_oracle": err,
+        "accept_rate": round(acc_total / (B * args.steps), 4), "wall_s": round(wall, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,11 +55,15 @@ enum slmc_status {
  * stabilizations.  The stabilization (QR/UDV), recombination, log-det accumulation and
  * the residual step are always FP64. */
 enum slmc_precision {
-  SLMC_FP64 = 0,    /* FP64 matrix cores                                              */
-  SLMC_FP32 = 1,    /* FP32 inputs on FP32 matrix cores; FP32 partial sums promoted to
-                       FP64 every acc_chunk k-steps of 4 (acc_chunk = 0: never)         */
-  SLMC_BF16X3 = 2,  /* two-piece bf16 split (hi + lo), three products, FP32 accumulate  */
-  SLMC_BF16X6 = 3   /* three-piece bf16 split, six products, FP32 accumulate            */
+  SLMC_FP64 = 0,       /* FP64 matrix cores                                           */
+  SLMC_FP32 = 1,       /* FP32 matrix cores on fp32(E) and the FP32 panel, plus the
+                          bf16 product (E - fp32(E)) * bf16(panel) that compensates the
+                          fixed rounding of E; FP32 partial sums promoted to FP64 every
+                          acc_chunk k-steps of 4 (acc_chunk = 0: never)                */
+  SLMC_BF16X3 = 2,     /* two-piece bf16 split (hi + lo), three products, FP32 sums
+                          promoted to FP64 per 32-wide k-block                        */
+  SLMC_BF16X6 = 3,     /* three-piece bf16 split, six products, as above              */
+  SLMC_FP32_PLAIN = 4  /* SLMC_FP32 without the compensation of E (error studies)     */
 };
 
 /* One lattice model.  N = Lx*Ly sites, Ltau slices of width dtau (beta = Ltau*dtau),
@@ -78,7 +82,7 @@ typedef struct {
 typedef struct {
   int32_t precision;       /* enum slmc_precision                                       */
   int32_t residual_steps;  /* FP64 refinement steps on G (0 or 1); ignored by logdet    */
-  int32_t acc_chunk;       /* SLMC_FP32 only: k-steps (of 4) per FP64 promotion, 0=none */
+  int32_t acc_chunk;       /* FP32 kinds: k-steps (of 4) per FP64 promotion: 0,1,2,4   */
   int32_t flags;           /* reserved, must be 0                                        */
 } slmc_options;
 
@@ -171,17 +175,30 @@ size_t slmc_accept_workspace_bytes(const slmc_model* model, int32_t n_chains,
  *   x_cur device [n_chains][Ltau][N] in/out (x_prop copied in on accept);
  *   x_prop device (same shape); logw_cur, eeff_cur device [n_chains] in/out (cached values
  *   of the current state, replaced on accept); accepted device [n_chains] uint8;
- *   log_ratio device [n_chains] double; ws device workspace. */
+ *   log_ratio device [n_chains] double; G_prop device [n_chains][N][N] or NULL: the
+ *   equal-time Green's function of every proposal (for measurements), computed by the
+ *   same evaluation that gives its log-det; ws device workspace. */
 int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff,
                            const slmc_options* opt, int32_t n_chains, double* x_cur,
                            const double* x_prop, double* logw_cur, double* eeff_cur,
                            uint64_t seed, uint64_t proposal_idx, uint8_t* accepted,
-                           double* log_ratio, void* ws, size_t ws_bytes, void* stream);
+                           double* log_ratio, double* G_prop, void* ws, size_t ws_bytes,
+                           void* stream);
 
 /* log w = -dtau S_Bose(x) + 2 logdet for every chain (seeds the cached logw_cur of
  * slmc_cumulative_accept).  Same workspace as slmc_cumulative_accept. */
 int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_chains,
                     const double* x, double* logw, void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel timing with HIP events recorded around each launch on its stream (off by
+ * default; costs two events per launch while on).  Classes: 0 seg_chain, 1 wy_apply,
+ * 2 qr, 3 vupd, 4 lu, 5 lu_solve, 6 residual, 7 eff_sweep.  slmc_profile_read waits for
+ * the recorded events and returns the accumulated milliseconds and launch count of one
+ * class since the last slmc_profile_reset. */
+int slmc_profile(int enable);
+int slmc_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches);
+void slmc_profile_reset(void);
+const char* slmc_profile_name(int32_t kernel_class);
 
 /* Frees the library's device constant cache (e^{-dtau K} copies per model and device).
  * Must not be called while work that uses it is still queued. */

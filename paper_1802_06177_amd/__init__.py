@@ -14,14 +14,15 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
-from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SlmcError, Model, Options,
-                   Batch, Eff)
+from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLAIN, SlmcError,
+                   Model, Options, Batch, Eff)
 
 __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
            "eff_energy", "eff_sweep", "log_weight", "cumulative_accept", "cache_clear",
            "SlmcError", "version"]
 
-PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6}
+PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6,
+              "fp32plain": SLMC_FP32_PLAIN}
 
 
 def version():
@@ -63,6 +64,26 @@ def expk(m):
 
 def cache_clear():
     _abi.lib().slmc_cache_clear()
+
+
+def profile(enable=True):
+    """Turns the library's HIP-event kernel timing on or off (see slmc_profile)."""
+    _abi.check(_abi.lib().slmc_profile(1 if enable else 0))
+
+
+def profile_reset():
+    _abi.lib().slmc_profile_reset()
+
+
+def profile_read():
+    """{kernel class: (total_ms, launches)} accumulated since the last reset."""
+    L = _abi.lib()
+    out = {}
+    for k in range(8):
+        ms, n = C.c_double(), C.c_int64()
+        _abi.check(L.slmc_profile_read(k, C.byref(ms), C.byref(n)))
+        out[L.slmc_profile_name(k).decode()] = (ms.value, n.value)
+    return out
 
 
 def _torch():
@@ -205,9 +226,10 @@ def log_weight(m, x, opt=None, stream=None, ws=None):
 
 
 def cumulative_accept(m, eff, x_cur, x_prop, logw_cur, eeff_cur, seed, proposal_idx, opt=None,
-                      stream=None, ws=None):
+                      stream=None, ws=None, G_prop=None):
     """Eq. 6 for one proposal per chain; x_cur, logw_cur, eeff_cur are updated in place on
-    accept.  Returns (accepted uint8, log_ratio float64)."""
+    accept.  G_prop (optional, [chains, N, N]) receives the proposals' Green's functions.
+    Returns (accepted uint8, log_ratio float64)."""
     torch = _torch()
     opt = opt or options()
     L = _abi.lib()
@@ -221,5 +243,6 @@ def cumulative_accept(m, eff, x_cur, x_prop, logw_cur, eeff_cur, seed, proposal_
         C.byref(m), C.byref(eff), C.byref(opt), n, _dev_f64(x_cur, "x_cur"),
         _dev_f64(x_prop, "x_prop"), _dev_f64(logw_cur, "logw_cur"), _dev_f64(eeff_cur, "eeff_cur"),
         C.c_uint64(seed), C.c_uint64(proposal_idx), vp(acc.data_ptr()), vp(lr.data_ptr()),
-        vp(wsb.data_ptr()), wsb.numel(), _stream(stream)))
+        None if G_prop is None else _dev_f64(G_prop, "G_prop"), vp(wsb.data_ptr()), wsb.numel(),
+        _stream(stream)))
     return acc, lr

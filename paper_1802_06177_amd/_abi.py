@@ -8,11 +8,12 @@ LIB_PATH = os.path.join(HERE, "libslmc.so")
 
 SLMC_OK, SLMC_E_ARG, SLMC_E_SHAPE, SLMC_E_WORKSPACE, SLMC_E_DEVICE, SLMC_E_NONFINITE, \
     SLMC_E_UNSUPPORTED = range(7)
-SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6 = range(4)
+SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLAIN = range(5)
 
 EXPORTS = ("slmc_version", "slmc_last_error", "slmc_expk", "slmc_workspace_bytes", "slmc_logdet",
            "slmc_green", "slmc_eff_energy", "slmc_eff_sweep", "slmc_accept_workspace_bytes",
-           "slmc_cumulative_accept", "slmc_log_weight", "slmc_cache_clear")
+           "slmc_cumulative_accept", "slmc_log_weight", "slmc_profile", "slmc_profile_read",
+           "slmc_profile_reset", "slmc_profile_name", "slmc_cache_clear")
 
 
 class Model(C.Structure):
@@ -62,7 +63,12 @@ def lib():
     L.slmc_accept_workspace_bytes.restype = sz
     L.slmc_accept_workspace_bytes.argtypes = [P(Model), i32, P(Options)]
     L.slmc_cumulative_accept.argtypes = [P(Model), P(Eff), P(Options), i32, vp, vp, vp, vp, u64,
-                                         u64, vp, vp, vp, sz, vp]
+                                         u64, vp, vp, vp, vp, sz, vp]
+    L.slmc_profile.argtypes = [C.c_int]
+    L.slmc_profile_read.argtypes = [i32, P(C.c_double), P(C.c_int64)]
+    L.slmc_profile_reset.restype = None
+    L.slmc_profile_name.restype = C.c_char_p
+    L.slmc_profile_name.argtypes = [i32]
     L.slmc_log_weight.argtypes = [P(Model), P(Options), i32, vp, vp, vp, sz, vp]
     L.slmc_cache_clear.restype = None
     _lib = L

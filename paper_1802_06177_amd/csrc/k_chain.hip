@@ -9,27 +9,15 @@
 // The diagonal phonon factor of the next slice is applied to the panel rows as the
 // matrix-core results are written back to LDS, so no separate scaling pass exists.
 //
-// FP64 variant: v_mfma_f64_16x16x4f64.  FP32 variant: v_mfma_f32_16x16x4f32 on FP32
-// copies of E and of the panel, with the FP32 partial sums promoted to FP64 every CH
-// k-steps (CH = 0: plain FP32 accumulation).  bf16 variants: v_mfma_f32_16x16x32_bf16 on
-// 2- or 3-piece bf16 splits of E and of the panel.
+// This file holds the FP64 variant (v_mfma_f64_16x16x4f64) and the precision dispatch;
+// the FP32 and split-bf16 variants live in k_chain_f32.hip and k_chain_bf16.hip.
 #include "common.h"
 #include "launch.h"
+#include "chain_util.h"
 
 namespace slmc {
 
 namespace {
-
-__device__ __forceinline__ const double* field_of(const FieldRef& f, int b) {
-  return f.x + (f.xoff ? f.xoff[b] : (int64_t)b * f.xstride);
-}
-
-// v[q] = exp(-ldl x[l][q]) for q < N, 1 on padded sites.
-__device__ __forceinline__ void fill_v(double* v, const double* xb, int l, int N, int Np,
-                                       double ldl) {
-  for (int q = threadIdx.x; q < Np; q += blockDim.x)
-    v[q] = q < N ? exp(-ldl * xb[(size_t)l * N + q]) : 1.0;
-}
 
 // Column panel of the first slice, E[:, c0+j] v_l0[c0+j], either scaled by v_next (rows)
 // into the LDS panel (as TP), or written out with its column norms when the segment has
@@ -200,156 +188,6 @@ __global__ __launch_bounds__(256) void seg_chain_f64(const double* __restrict__ 
   }
 }
 
-// ------------------------------------------------------------------------------ FP32
-
-template <int RB, int CB, int CH>
-__global__ __launch_bounds__(256) void seg_chain_f32(const float* __restrict__ E32,
-                                                     const double* __restrict__ E64,
-                                                     FieldRef f, int nb, int N, int Np,
-                                                     int Ltau, int n_s, int m, double ldl,
-                                                     double* __restrict__ S,
-                                                     double* __restrict__ snorm) {
-  constexpr int W = 16 * CB;
-  extern __shared__ double lds[];
-  const int LDP = Np + 4;                                  // floats
-  double* vbuf = lds;                                      // [2][Np]
-  double* red = vbuf + 2 * Np;                             // [256]
-  float* P = (float*)(red + 256);                          // [W][LDP]
-  const int npan = Np / W;
-  const int id = xcd_remap(blockIdx.x, nb * m * npan);
-  if (id < 0) return;
-  const int pan = id % npan, k = (id / npan) % m, b = id / (npan * m);
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
-  const int NRB = Np >> 4, c0 = pan * W;
-  const double* xb = field_of(f, b);
-  const int l0 = k * n_s, len = min(n_s, Ltau - l0);
-  double* Sout = S + ((size_t)b * m + k) * Np * Np;
-  double* nout = snorm + ((size_t)b * m + k) * Np;
-
-  fill_v(vbuf, xb, l0, N, Np, ldl);
-  if (len > 1) fill_v(vbuf + Np, xb, l0 + 1, N, Np, ldl);
-  __syncthreads();
-  // the first slice is exact in FP64 (a column-scaled copy of E), rounded once to FP32
-  first_slice<float>(E64, vbuf, vbuf + Np, P, LDP, W, c0, Np, len == 1, Sout, red, nout);
-  if (len == 1) return;
-  __syncthreads();
-
-  for (int t = 1; t < len; ++t) {
-    const bool last = (t == len - 1);
-    double* vnext = vbuf + ((t + 1) & 1) * Np;
-    if (!last) fill_v(vnext, xb, l0 + t + 1, N, Np, ldl);
-
-    fx4 acc[RB][CB];
-    dx4 acc64[RB][CB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) { acc[r][cb] = zero4f(); acc64[r][cb] = zero4d(); }
-
-    float4 an[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int rb = w + 4 * r;
-      if (rb < NRB) an[r] = *(const float4*)(E32 + (size_t)(16 * rb + c) * Np + 4 * g);
-    }
-    for (int kb = 0; kb < NRB; ++kb) {
-      const int q0 = 16 * kb + 4 * g;
-      float av[RB][4];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        av[r][0] = an[r].x; av[r][1] = an[r].y; av[r][2] = an[r].z; av[r][3] = an[r].w;
-      }
-      if (kb + 1 < NRB) {
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          const int rb = w + 4 * r;
-          if (rb < NRB) an[r] = *(const float4*)(E32 + (size_t)(16 * rb + c) * Np + q0 + 16);
-        }
-      }
-      float bv[CB][4];
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        float4 bb = *(const float4*)(P + (16 * cb + c) * LDP + q0);
-        bv[cb][0] = bb.x; bv[cb][1] = bb.y; bv[cb][2] = bb.z; bv[cb][3] = bb.w;
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-          if (w + 4 * r < NRB) {
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) acc[r][cb] = mfma32(av[r][s], bv[cb][s], acc[r][cb]);
-          }
-        if (CH > 0 && ((4 * kb + s) % CH) == CH - 1) {
-#pragma unroll
-          for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) acc64[r][cb][v] += (double)acc[r][cb][v];
-              acc[r][cb] = zero4f();
-            }
-        }
-      }
-    }
-    // remainder (or everything, when CH == 0)
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[r][cb][v] += (double)acc[r][cb][v];
-    __syncthreads();
-    if (!last) {
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int rb = w + 4 * r;
-        if (rb < NRB) {
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            const int row = 16 * rb + 4 * g;
-            float4 o;
-            o.x = (float)(vnext[row + 0] * acc64[r][cb][0]);
-            o.y = (float)(vnext[row + 1] * acc64[r][cb][1]);
-            o.z = (float)(vnext[row + 2] * acc64[r][cb][2]);
-            o.w = (float)(vnext[row + 3] * acc64[r][cb][3]);
-            *(float4*)(P + (16 * cb + c) * LDP + row) = o;
-          }
-        }
-      }
-    } else {
-      double s2[CB];
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) s2[cb] = 0.0;
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int rb = w + 4 * r;
-        if (rb < NRB) {
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = 16 * rb + drow32(g, v);
-              const double val = acc64[r][cb][v];
-              Sout[(size_t)row * Np + c0 + 16 * cb + c] = val;
-              s2[cb] += val * val;
-            }
-        }
-      }
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        double sv = s2[cb];
-        sv += __shfl_xor(sv, 16, 64);
-        sv += __shfl_xor(sv, 32, 64);
-        if (g == 0) red[w * W + 16 * cb + c] = sv;
-      }
-      __syncthreads();
-      if (tid < W) nout[c0 + tid] = red[tid] + red[W + tid] + red[2 * W + tid] + red[3 * W + tid];
-    }
-    __syncthreads();
-  }
-}
-
 // ------------------------------------------------------------------------------ dispatch
 
 template <int RB, int CB>
@@ -363,17 +201,6 @@ hipError_t run_f64(const double* E, FieldRef f, int nb, int N, int Np, int Ltau,
   return hipGetLastError();
 }
 
-template <int RB, int CB, int CH>
-hipError_t run_f32(const float* E32, const double* E64, FieldRef f, int nb, int N, int Np,
-                   int Ltau, int n_s, int m, double ldl, double* S, double* sn, hipStream_t st) {
-  constexpr int W = 16 * CB;
-  const int count = nb * m * (Np / W);
-  const size_t lds = (size_t)(2 * Np + 256) * sizeof(double) + (size_t)W * (Np + 4) * sizeof(float);
-  hipLaunchKernelGGL((seg_chain_f32<RB, CB, CH>), dim3(xcd_grid(count)), dim3(256), lds, st, E32,
-                     E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn);
-  return hipGetLastError();
-}
-
 template <int RB>
 hipError_t pick_f64(int CB, const double* E, FieldRef f, int nb, int N, int Np, int Ltau,
                     int n_s, int m, double ldl, double* S, double* sn, hipStream_t st) {
@@ -381,36 +208,17 @@ hipError_t pick_f64(int CB, const double* E, FieldRef f, int nb, int N, int Np, 
   return run_f64<RB, 1>(E, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
 }
 
-template <int RB, int CB>
-hipError_t pick_ch(int ch, const float* E32, const double* E64, FieldRef f, int nb, int N, int Np,
-                   int Ltau, int n_s, int m, double ldl, double* S, double* sn, hipStream_t st) {
-  switch (ch) {
-    case 0: return run_f32<RB, CB, 0>(E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    case 1: return run_f32<RB, CB, 1>(E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    case 2: return run_f32<RB, CB, 2>(E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    case 4: return run_f32<RB, CB, 4>(E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    case 8: return run_f32<RB, CB, 8>(E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int RB>
-hipError_t pick_f32(int CB, int ch, const float* E32, const double* E64, FieldRef f, int nb,
-                    int N, int Np, int Ltau, int n_s, int m, double ldl, double* S, double* sn,
-                    hipStream_t st) {
-  if (CB == 4) return pick_ch<RB, 4>(ch, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-  if (CB == 2) return pick_ch<RB, 2>(ch, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-  return pick_ch<RB, 1>(ch, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-}
-
 }  // namespace
 
 hipError_t launch_seg_bf16(int pieces, const double* E64, const uint16_t* Ebf, FieldRef f,
                            int nb, int N, int Np, int Ltau, int n_s, int m, double ldl,
                            double* S, double* snorm, hipStream_t st);
+hipError_t launch_seg_f32(int ecorr, int ch, const float* E32, const uint16_t* Elo,
+                          const double* E64, FieldRef f, int nb, int N, int Np, int Ltau, int n_s,
+                          int m, double ldl, double* S, double* snorm, hipStream_t st);
 
 hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const float* E32,
-                            const uint16_t* Ebf, FieldRef f, int nb, int N, int Np, int Ltau,
+                            const uint16_t* Elo, const uint16_t* Ebf, FieldRef f, int nb, int N, int Np, int Ltau,
                             int n_s, int m, double ldl, double* S, double* snorm,
                             hipStream_t st) {
   const int NRB = Np / 16;
@@ -430,19 +238,9 @@ hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const fl
       default: return pick_f64<8>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
     }
   }
-  if (prec == 1) {
-    const int CB = (Np % 64 == 0 && Np <= 256) ? 4 : ((Np % 32 == 0) ? 2 : 1);
-    switch (RB) {
-      case 1: return pick_f32<1>(CB, acc_chunk, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 2: return pick_f32<2>(CB, acc_chunk, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 3: return pick_f32<3>(CB, acc_chunk, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 4: return pick_f32<4>(CB, acc_chunk, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 5: return pick_f32<5>(CB, acc_chunk, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 6: return pick_f32<6>(CB, acc_chunk, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 7: return pick_f32<7>(CB, acc_chunk, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      default: return pick_f32<8>(CB, acc_chunk, E32, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    }
-  }
+  if (prec == 1 || prec == 4)
+    return launch_seg_f32(prec == 1, acc_chunk, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S,
+                          snorm, st);
   if (prec == 2 || prec == 3)
     return launch_seg_bf16(prec == 2 ? 2 : 3, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
   return hipErrorInvalidValue;

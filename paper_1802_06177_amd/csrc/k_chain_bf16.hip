@@ -6,19 +6,11 @@
 // and FP32 segment kernels: one workgroup carries one column panel of one segment.
 #include "common.h"
 #include "launch.h"
+#include "chain_util.h"
 
 namespace slmc {
 
 namespace {
-
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(r >> 16);
-}
-__device__ __forceinline__ double bf16_to_d(uint16_t h) {
-  return (double)__uint_as_float(((uint32_t)h) << 16);
-}
 
 // Split val into PIECES bf16 parts: each part is the bf16 rounding of what remains.
 template <int PIECES>
@@ -30,16 +22,6 @@ __device__ __forceinline__ void split_bf(double val, uint16_t* out) {
     out[p] = h;
     r -= bf16_to_d(h);
   }
-}
-
-__device__ __forceinline__ const double* field_of(const FieldRef& f, int b) {
-  return f.x + (f.xoff ? f.xoff[b] : (int64_t)b * f.xstride);
-}
-
-__device__ __forceinline__ void fill_v(double* v, const double* xb, int l, int N, int Np,
-                                       double ldl) {
-  for (int q = threadIdx.x; q < Np; q += blockDim.x)
-    v[q] = q < N ? exp(-ldl * xb[(size_t)l * N + q]) : 1.0;
 }
 
 // pairs (A piece, B piece) of the split product

@@ -1,0 +1,286 @@
+// FP32 segment products on v_mfma_f32_16x16x4f32 (structure as the FP64 segment kernel:
+// one workgroup carries one column panel of one segment through every slice in LDS).
+//
+// Accuracy notes (measured; they decide the design):
+//  * E = e^{-dtau K} is the same in every slice, so its FP32 rounding acts as a fixed
+//    perturbation of the hopping matrix and shifts log|det| coherently (~7e-8 relative at
+//    8x8, Ltau=80).  ECORR adds the missing part E - fp32(E), held in bf16, as a second
+//    product on v_mfma_f32_16x16x16_bf16 into its own accumulator (one small MFMA per four
+//    FP32 ones), which takes E to ~2^-33 relative.
+//  * The FP32 matrix-core accumulation aligns and truncates (it drops low bits rather than
+//    rounding), so long FP32 sums drift coherently; the partial sums are therefore
+//    promoted to FP64 every CH k-steps (CH = 0: never).
+//  * The panel itself is rounded to FP32 between slices; that error is different in every
+//    slice and averages out (~1e-10 relative).
+#include "common.h"
+#include "launch.h"
+#include "chain_util.h"
+
+namespace slmc {
+
+namespace {
+
+typedef short sx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ fx4 mfmabf16(sx4 a, sx4 b, fx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+template <int RB, int CB, int CH, bool ECORR>
+__global__ __launch_bounds__(256) void seg_chain_f32(const float* __restrict__ E32,
+                                                     const uint16_t* __restrict__ Elo,
+                                                     const double* __restrict__ E64,
+                                                     FieldRef f, int nb, int N, int Np,
+                                                     int Ltau, int n_s, int m, double ldl,
+                                                     double* __restrict__ S,
+                                                     double* __restrict__ snorm) {
+  constexpr int W = 16 * CB;
+  extern __shared__ double lds[];
+  const int LDP = Np + 4;                                  // floats
+  const int LDB = Np + 8;                                  // bf16
+  double* vbuf = lds;                                      // [2][Np]
+  double* red = vbuf + 2 * Np;                             // [256]
+  float* P = (float*)(red + 256);                          // [W][LDP]
+  uint16_t* Pb = (uint16_t*)(P + W * LDP);                 // [W][LDB] (ECORR)
+  const int npan = Np / W;
+  const int id = xcd_remap(blockIdx.x, nb * m * npan);
+  if (id < 0) return;
+  const int pan = id % npan, k = (id / npan) % m, b = id / (npan * m);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+  const int NRB = Np >> 4, c0 = pan * W;
+  const double* xb = field_of(f, b);
+  const int l0 = k * n_s, len = min(n_s, Ltau - l0);
+  double* Sout = S + ((size_t)b * m + k) * Np * Np;
+  double* nout = snorm + ((size_t)b * m + k) * Np;
+
+  fill_v(vbuf, xb, l0, N, Np, ldl);
+  if (len > 1) fill_v(vbuf + Np, xb, l0 + 1, N, Np, ldl);
+  __syncthreads();
+  if (len == 1) {
+    const int j = tid % W, part = tid / W, nparts = 256 / W;
+    double s2 = 0.0;
+    for (int q = part; q < Np; q += nparts) {
+      const double val = E64[(size_t)q * Np + c0 + j] * vbuf[c0 + j];
+      Sout[(size_t)q * Np + c0 + j] = val;
+      s2 += val * val;
+    }
+    red[part * W + j] = s2;
+    __syncthreads();
+    if (tid < W) {
+      double s = 0.0;
+      for (int p = 0; p < nparts; ++p) s += red[p * W + tid];
+      nout[c0 + tid] = s;
+    }
+    return;
+  }
+  // first slice exactly in FP64 (a column-scaled copy of E), rounded once
+  for (int idx = tid; idx < W * Np; idx += 256) {
+    const int q = idx / W, j = idx - q * W;
+    const float fv = (float)(vbuf[Np + q] * E64[(size_t)q * Np + c0 + j] * vbuf[c0 + j]);
+    P[j * LDP + q] = fv;
+    if (ECORR) Pb[j * LDB + q] = bf16_rne(fv);
+  }
+  __syncthreads();
+
+  for (int t = 1; t < len; ++t) {
+    const bool last = (t == len - 1);
+    double* vnext = vbuf + ((t + 1) & 1) * Np;
+    if (!last) fill_v(vnext, xb, l0 + t + 1, N, Np, ldl);
+
+    fx4 acc[RB][CB];
+    fx4 accc[RB][CB];
+    dx4 acc64[RB][CB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        acc[r][cb] = zero4f();
+        accc[r][cb] = zero4f();
+        acc64[r][cb] = zero4d();
+      }
+
+    float4 an[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int rb = w + 4 * r;
+      if (rb < NRB) an[r] = *(const float4*)(E32 + (size_t)(16 * rb + c) * Np + 4 * g);
+    }
+    for (int kb = 0; kb < NRB; ++kb) {
+      const int q0 = 16 * kb + 4 * g;
+      float av[RB][4];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        av[r][0] = an[r].x; av[r][1] = an[r].y; av[r][2] = an[r].z; av[r][3] = an[r].w;
+      }
+      if (kb + 1 < NRB) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int rb = w + 4 * r;
+          if (rb < NRB) an[r] = *(const float4*)(E32 + (size_t)(16 * rb + c) * Np + q0 + 16);
+        }
+      }
+      float bv[CB][4];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const float4 bb = *(const float4*)(P + (16 * cb + c) * LDP + q0);
+        bv[cb][0] = bb.x; bv[cb][1] = bb.y; bv[cb][2] = bb.z; bv[cb][3] = bb.w;
+      }
+      if (ECORR) {
+        sx4 lo[RB], pb[CB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int rb = w + 4 * r;
+          if (rb < NRB) lo[r] = *(const sx4*)(Elo + (size_t)(16 * rb + c) * Np + q0);
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) pb[cb] = *(const sx4*)(Pb + (16 * cb + c) * LDB + q0);
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+          if (w + 4 * r < NRB) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) accc[r][cb] = mfmabf16(lo[r], pb[cb], accc[r][cb]);
+          }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+          if (w + 4 * r < NRB) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[r][cb] = mfma32(av[r][s], bv[cb][s], acc[r][cb]);
+          }
+        if (CH > 0 && ((4 * kb + s) % CH) == CH - 1) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc64[r][cb][v] += (double)acc[r][cb][v];
+              acc[r][cb] = zero4f();
+            }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          acc64[r][cb][v] += (double)acc[r][cb][v] + (ECORR ? (double)accc[r][cb][v] : 0.0);
+    __syncthreads();
+    if (!last) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int rb = w + 4 * r;
+        if (rb < NRB) {
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int row = 16 * rb + 4 * g;
+            float4 o;
+            o.x = (float)(vnext[row + 0] * acc64[r][cb][0]);
+            o.y = (float)(vnext[row + 1] * acc64[r][cb][1]);
+            o.z = (float)(vnext[row + 2] * acc64[r][cb][2]);
+            o.w = (float)(vnext[row + 3] * acc64[r][cb][3]);
+            *(float4*)(P + (16 * cb + c) * LDP + row) = o;
+            if (ECORR) {
+              sx4 h;
+              h.x = (short)bf16_rne(o.x); h.y = (short)bf16_rne(o.y);
+              h.z = (short)bf16_rne(o.z); h.w = (short)bf16_rne(o.w);
+              *(sx4*)(Pb + (16 * cb + c) * LDB + row) = h;
+            }
+          }
+        }
+      }
+    } else {
+      double s2[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) s2[cb] = 0.0;
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int rb = w + 4 * r;
+        if (rb < NRB) {
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = 16 * rb + drow32(g, v);
+              const double val = acc64[r][cb][v];
+              Sout[(size_t)row * Np + c0 + 16 * cb + c] = val;
+              s2[cb] += val * val;
+            }
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        double sv = s2[cb];
+        sv += __shfl_xor(sv, 16, 64);
+        sv += __shfl_xor(sv, 32, 64);
+        if (g == 0) red[w * W + 16 * cb + c] = sv;
+      }
+      __syncthreads();
+      if (tid < W) nout[c0 + tid] = red[tid] + red[W + tid] + red[2 * W + tid] + red[3 * W + tid];
+    }
+    __syncthreads();
+  }
+}
+
+template <int RB, int CB, int CH, bool EC>
+hipError_t run_f32(const float* E32, const uint16_t* Elo, const double* E64, FieldRef f, int nb,
+                   int N, int Np, int Ltau, int n_s, int m, double ldl, double* S, double* sn,
+                   hipStream_t st) {
+  constexpr int W = 16 * CB;
+  const int count = nb * m * (Np / W);
+  const size_t lds = (size_t)(2 * Np + 256) * sizeof(double) + (size_t)W * (Np + 4) * sizeof(float) +
+                     (EC ? (size_t)W * (Np + 8) * sizeof(uint16_t) : 0);
+  hipLaunchKernelGGL((seg_chain_f32<RB, CB, CH, EC>), dim3(xcd_grid(count)), dim3(256), lds, st,
+                     E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn);
+  return hipGetLastError();
+}
+
+template <int RB, int CB, bool EC>
+hipError_t pick_ch(int ch, const float* E32, const uint16_t* Elo, const double* E64, FieldRef f,
+                   int nb, int N, int Np, int Ltau, int n_s, int m, double ldl, double* S,
+                   double* sn, hipStream_t st) {
+  switch (ch) {
+    case 0: return run_f32<RB, CB, 0, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+    case 1: return run_f32<RB, CB, 1, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+    case 2: return run_f32<RB, CB, 2, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+    case 4: return run_f32<RB, CB, 4, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int RB>
+hipError_t pick_f32(int ec, int ch, const float* E32, const uint16_t* Elo, const double* E64,
+                    FieldRef f, int nb, int N, int Np, int Ltau, int n_s, int m, double ldl,
+                    double* S, double* sn, hipStream_t st) {
+  const int CB = (Np % 32 == 0) ? 2 : 1;
+  if (ec) {
+    if (CB == 2) return pick_ch<RB, 2, true>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+    return pick_ch<RB, 1, true>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+  }
+  if (CB == 2) return pick_ch<RB, 2, false>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+  return pick_ch<RB, 1, false>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+}
+
+}  // namespace
+
+hipError_t launch_seg_f32(int ecorr, int ch, const float* E32, const uint16_t* Elo,
+                          const double* E64, FieldRef f, int nb, int N, int Np, int Ltau, int n_s,
+                          int m, double ldl, double* S, double* snorm, hipStream_t st) {
+  const int RB = (Np / 16 + 3) / 4;
+  switch (RB) {
+    case 1: return pick_f32<1>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 2: return pick_f32<2>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 3: return pick_f32<3>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 4: return pick_f32<4>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 5: return pick_f32<5>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 6: return pick_f32<6>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 7: return pick_f32<7>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 8: return pick_f32<8>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace slmc

@@ -77,6 +77,7 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
       // pivot search over local rows >= cc (largest |a|, lowest row on ties)
       double bv = -1.0;
       int bi = 0x7fffffff;
+#pragma unroll 2
       for (int r = cc + tid; r < K; r += 256) {
         const double a = fabs(Pn[r * LDY + cc]);
         if (a > bv) { bv = a; bi = r; }
@@ -112,10 +113,16 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
       {
         const double u = ud[j0 + cc];
         const double ui = (u != 0.0) ? 1.0 / u : 0.0;
+        double pv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) pv[j] = (j > cc) ? Pn[cc * LDY + j] : 0.0;
         for (int r = cc + 1 + tid; r < K; r += 256) {
-          const double l = Pn[r * LDY + cc] * ui;
-          Pn[r * LDY + cc] = l;
-          for (int j = cc + 1; j < 16; ++j) Pn[r * LDY + j] -= l * Pn[cc * LDY + j];
+          double* row = Pn + r * LDY;
+          const double l = row[cc] * ui;
+          row[cc] = l;
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (j > cc) row[j] -= l * pv[j];
         }
       }
       __syncthreads();

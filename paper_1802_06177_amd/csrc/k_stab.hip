@@ -212,6 +212,7 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
         const int j = tid >> 4, part = tid & 15;
         double dj = 0.0, ss = 0.0;
         if (j >= cc) {
+#pragma unroll 4
           for (int r = cc + 1 + part; r < K; r += 16) {
             const double a = Pn[r * LDY + cc];
             dj += a * Pn[r * LDY + j];
@@ -240,11 +241,17 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
       __syncthreads();
       {
         const double sc = scl[cc], tau = tauA[j0 + cc];
+        double wv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) wv[j] = (j > cc) ? wsh[j] : 0.0;
         for (int r = cc + 1 + tid; r < K; r += 256) {
-          const double vr = Pn[r * LDY + cc] * sc;
-          Pn[r * LDY + cc] = vr;
+          double* row = Pn + r * LDY;
+          const double vr = row[cc] * sc;
+          row[cc] = vr;
           const double tv = tau * vr;
-          for (int j = cc + 1; j < 16; ++j) Pn[r * LDY + j] -= tv * wsh[j];
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (j > cc) row[j] -= tv * wv[j];
         }
         if (tid == 0)
           for (int j = cc; j < 16; ++j) Pn[cc * LDY + j] = rc[j];
@@ -254,33 +261,36 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
 
     // ---- T of the compact-WY form: Q_p = I - Y T Y^T (wave 0)
     if (w == 0) {
-      dx4 gacc = zero4d();
+      dx4 ga[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
       for (int rb = 0; rb < nrbK; ++rb) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int kr = 16 * rb + 4 * g + s;
           const double y = yval(Pn, kr, c);
-          gacc = mfma64(y, y, gacc);
+          ga[s] = mfma64(y, y, ga[s]);
         }
       }
+      const dx4 gacc = ga[0] + ga[1] + ga[2] + ga[3];
 #pragma unroll
       for (int v = 0; v < 4; ++v) gram[drow64(g, v) * LDY + c] = gacc[v];
-      // lanes 0..15: row j of T, built column by column
+      // lanes 0..15: row j of T (kept in registers), built column by column
       if (lane < 16) {
         const int j = lane;
+        double trow[16];
+#pragma unroll
         for (int i = 0; i < 16; ++i) {
           const double ti = tauA[j0 + i];
-          double t;
-          if (j < i) {
-            double s = 0.0;
-            for (int l = j; l < i; ++l) s += Tl[j * LDY + l] * gram[l * LDY + i];
-            t = -ti * s;
-          } else {
-            t = (j == i) ? ti : 0.0;
-          }
-          Tl[j * LDY + i] = t;
+          double s = 0.0;
+#pragma unroll
+          for (int l = 0; l < i; ++l)
+            if (l >= j) s += trow[l] * gram[l * LDY + i];
+          trow[i] = (j < i) ? -ti * s : ((j == i) ? ti : 0.0);
         }
-        for (int i = 0; i < 16; ++i) Tg[(size_t)p * 256 + j * 16 + i] = Tl[j * LDY + i];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          Tl[j * LDY + i] = trow[i];
+          Tg[(size_t)p * 256 + j * 16 + i] = trow[i];
+        }
       }
     }
     __syncthreads();
@@ -313,7 +323,6 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
             aw[rb & 3] = mfma64(yval(Pn, kr, c), blk[rb][s], aw[rb & 3]);
           }
         }
-        __builtin_amdgcn_sched_barrier(0);
       }
       dx4 W = aw[0] + aw[1] + aw[2] + aw[3];
       dx4 Wt = zero4d();
@@ -326,7 +335,6 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
           for (int s = 0; s < 4; ++s)
             blk[rb] = mfma64(-yval(Pn, 16 * rb + c, drow64(g, s)), Wt[s], blk[rb]);
         }
-        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int rb = 0; rb < NRBMAX; ++rb) {

@@ -22,6 +22,33 @@ using namespace slmc;
 
 namespace {
 
+// Optional per-kernel-class timing with HIP events recorded on the launch stream.
+struct ProfRec { int cls; hipEvent_t a, b; };
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+double g_prof_ms[8] = {0};
+int64_t g_prof_n[8] = {0};
+const char* const g_prof_names[8] = {"seg_chain", "wy_apply", "qr", "vupd", "lu", "lu_solve",
+                                     "residual", "eff_sweep"};
+
+struct ProfScope {
+  int cls;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int c, hipStream_t s) : cls(c), st(s) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(ProfRec{cls, a, b});
+  }
+};
+
 thread_local std::string g_err;
 
 int fail(int code, const char* fmt, ...) {
@@ -59,10 +86,10 @@ int check_model(const slmc_model* m) {
 
 int check_opt(const slmc_options* o) {
   if (!o) return fail(SLMC_E_ARG, "options is NULL");
-  if (o->precision < 0 || o->precision > 3) return fail(SLMC_E_ARG, "unknown precision %d", o->precision);
+  if (o->precision < 0 || o->precision > 4) return fail(SLMC_E_ARG, "unknown precision %d", o->precision);
   if (o->residual_steps < 0 || o->residual_steps > 1) return fail(SLMC_E_ARG, "residual_steps must be 0 or 1");
-  if (!(o->acc_chunk == 0 || o->acc_chunk == 1 || o->acc_chunk == 2 || o->acc_chunk == 4 || o->acc_chunk == 8))
-    return fail(SLMC_E_ARG, "acc_chunk must be one of 0, 1, 2, 4, 8");
+  if (!(o->acc_chunk == 0 || o->acc_chunk == 1 || o->acc_chunk == 2 || o->acc_chunk == 4))
+    return fail(SLMC_E_ARG, "acc_chunk must be one of 0, 1, 2, 4");
   if (o->flags != 0) return fail(SLMC_E_ARG, "flags must be 0");
   return SLMC_OK;
 }
@@ -111,6 +138,7 @@ struct ModelConsts {
   float* E32 = nullptr;
   uint16_t* Ebf2 = nullptr;   // [2][Np][Np]
   uint16_t* Ebf3 = nullptr;   // [3][Np][Np]
+  uint16_t* Elo = nullptr;    // [Np][Np] bf16 of E64 - fp32(E64)
 };
 
 std::mutex g_cache_mu;
@@ -132,7 +160,8 @@ int get_consts(const slmc_model* m, ModelConsts** out) {
       Ep[(size_t)i * Np + j] = (i < N && j < N) ? E[(size_t)i * N + j] : (i == j ? 1.0 : 0.0);
   std::vector<float> E32(Ep.size());
   for (size_t k = 0; k < Ep.size(); ++k) E32[k] = (float)Ep[k];
-  std::vector<uint16_t> b2(2 * Ep.size()), b3(3 * Ep.size());
+  std::vector<uint16_t> b2(2 * Ep.size()), b3(3 * Ep.size()), lo(Ep.size());
+  for (size_t k = 0; k < Ep.size(); ++k) lo[k] = bf16_rne_host((float)(Ep[k] - (double)E32[k]));
   for (size_t k = 0; k < Ep.size(); ++k) {
     double r = Ep[k];
     for (int p = 0; p < 3; ++p) {
@@ -148,6 +177,8 @@ int get_consts(const slmc_model* m, ModelConsts** out) {
   HIPCHK(hipMalloc(&mc.E32, E32.size() * sizeof(float)));
   HIPCHK(hipMalloc(&mc.Ebf2, b2.size() * sizeof(uint16_t)));
   HIPCHK(hipMalloc(&mc.Ebf3, b3.size() * sizeof(uint16_t)));
+  HIPCHK(hipMalloc(&mc.Elo, lo.size() * sizeof(uint16_t)));
+  HIPCHK(hipMemcpy(mc.Elo, lo.data(), lo.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(mc.E64, Ep.data(), Ep.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(mc.E32, E32.data(), E32.size() * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(mc.Ebf2, b2.data(), b2.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
@@ -283,9 +314,12 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
 
   HIPCHK(launch_fill_i32(w.status, nb, 0, st));
   // a2: segment products (a1 fused: the phonon factors scale the panel rows)
-  HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32,
+  {
+  ProfScope ps(0, st);
+  HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo,
                           o->precision == 2 ? mc->Ebf2 : mc->Ebf3, f, nb, N, Np, m->Ltau, m->n_s,
                           mseg, ldl, w.S, w.snorm, st));
+  }
   // a3: stabilized accumulation
   double* logD[2] = {w.logD0, w.logD1};
   double* Vb[2] = {w.V0, w.V1};
@@ -302,6 +336,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
       nstride = (int64_t)mseg * Np;
       nparts = 1;
     } else {
+      ProfScope ps(1, st);
       HIPCHK(launch_wy_apply(w.S + (size_t)k * n2, (int64_t)mseg * n2, w.QRW, w.Tb, w.A, w.npart, 0,
                              nb, Np, st));
       Ain = w.A;
@@ -310,8 +345,12 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
       nparts = Np / 16;
       nstride = (int64_t)nparts * Np;
     }
+    {
+    ProfScope ps(2, st);
     HIPCHK(launch_qr(Ain, astride, nrm, nstride, nparts, k == 0 ? nullptr : logD[(k + 1) & 1], w.QRW, w.Tb,
                      w.perm, logD[k & 1], w.qsign, w.status, nb, Np, st));
+    }
+    ProfScope ps(3, st);
     HIPCHK(launch_vupd(w.QRW, w.perm, k == 0 ? nullptr : Vb[(k + 1) & 1], Vb[k & 1], nb, Np, st));
   }
   const double* logDf = logD[(mseg - 1) & 1];
@@ -321,15 +360,20 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   double* LU = w.S;
   // U^T = Q_m^T explicitly, then a4: recombination
   HIPCHK(launch_wy_apply(nullptr, 0, w.QRW, w.Tb, QT, nullptr, 1, nb, Np, st));
+  {
+  ProfScope ps(4, st);
   HIPCHK(launch_lu(QT, Vf, logDf, w.qsign, w.status, LU, w.prow, w.DI, item_of, ld_out, sg_out,
                    st_out, nb, N, Np, st));
+  }
   if (G) {
+    ProfScope ps(5, st);
     const bool resid = o->residual_steps > 0;
     HIPCHK(launch_lu_solve(0, QT, logDf, nullptr, LU, w.prow, w.DI, Gint, 0, resid ? nullptr : g_out,
                            goff, nb, N, Np, st));
     if (resid) {
       // a5: R = Db^-1 U^T - X G, G += X^-1 R
       double* R = w.QRW;
+      ProfScope pr(6, st);
       HIPCHK(launch_residual(QT, Vf, logDf, Gint, R, nb, Np, st));
       HIPCHK(launch_lu_solve(1, QT, logDf, R, LU, w.prow, w.DI, Gint, 1, g_out, goff, nb, N, Np, st));
     }
@@ -457,6 +501,7 @@ int slmc_eff_sweep(const slmc_model* model, const slmc_eff* eff, int32_t n_chain
   rc = colour_mod(model, eff, &mod);
   if (rc) return rc;
   if (n_chains == 0) return SLMC_OK;
+  ProfScope ps(7, (hipStream_t)stream);
   HIPCHK(launch_eff_sweep(x, n_chains, model->Lx, model->Ly, model->Ltau, eff_params(eff), mod,
                           n_sweeps, seed, proposal_idx, n_accepted, (hipStream_t)stream));
   return SLMC_OK;
@@ -501,8 +546,8 @@ int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_
 int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff, const slmc_options* opt,
                            int32_t n_chains, double* x_cur, const double* x_prop, double* logw_cur,
                            double* eeff_cur, uint64_t seed, uint64_t proposal_idx,
-                           uint8_t* accepted, double* log_ratio, void* ws, size_t ws_bytes,
-                           void* stream) {
+                           uint8_t* accepted, double* log_ratio, double* G_prop, void* ws,
+                           size_t ws_bytes, void* stream) {
   g_err.clear();
   int rc = check_model(model);
   if (rc) return rc;
@@ -529,7 +574,7 @@ int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff, const s
   for (int c = 0; c < n_chains; ++c) grp.items.push_back(c);
   slmc_batch bt{n_chains, nullptr, nullptr, nullptr};
   hipStream_t st = (hipStream_t)stream;
-  rc = run_group(model, opt, grp, &bt, x_prop, ld, sg, nullptr, stt, w, st);
+  rc = run_group(model, opt, grp, &bt, x_prop, ld, sg, G_prop, stt, w, st);
   if (rc) return rc;
   HIPCHK(launch_eff_energy(x_prop, n_chains, model->Lx, model->Ly, model->Ltau, eff_params(eff), eep, st));
   HIPCHK(launch_log_weight(x_prop, ld, n_chains, N, model->Ltau, model->lambda, model->omega0,
@@ -537,6 +582,43 @@ int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff, const s
   HIPCHK(launch_accept(x_cur, x_prop, logw_cur, eeff_cur, lwp, eep, n_chains,
                        (int64_t)N * model->Ltau, seed, proposal_idx, accepted, log_ratio, st));
   return SLMC_OK;
+}
+
+int slmc_profile(int enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = enable != 0;
+  return SLMC_OK;
+}
+
+int slmc_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches) {
+  g_err.clear();
+  if (kernel_class < 0 || kernel_class >= 8 || !total_ms || !launches)
+    return fail(SLMC_E_ARG, "kernel_class out of range or NULL output");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      return fail(SLMC_E_DEVICE, "event query failed");
+    g_prof_ms[r.cls] += ms;
+    g_prof_n[r.cls] += 1;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+  *total_ms = g_prof_ms[kernel_class];
+  *launches = g_prof_n[kernel_class];
+  return SLMC_OK;
+}
+
+void slmc_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  g_prof_pending.clear();
+  for (int k = 0; k < 8; ++k) { g_prof_ms[k] = 0.0; g_prof_n[k] = 0; }
+}
+
+const char* slmc_profile_name(int32_t kernel_class) {
+  return (kernel_class >= 0 && kernel_class < 8) ? g_prof_names[kernel_class] : "";
 }
 
 void slmc_cache_clear(void) {
@@ -549,6 +631,7 @@ void slmc_cache_clear(void) {
     (void)hipFree(kv.second.E32);
     (void)hipFree(kv.second.Ebf2);
     (void)hipFree(kv.second.Ebf3);
+    (void)hipFree(kv.second.Elo);
     (void)hipSetDevice(cur);
   }
   g_cache.clear();

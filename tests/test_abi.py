@@ -91,10 +91,10 @@ def test_sweep_and_accept_validation():
     need = L.slmc_accept_workspace_bytes(C.byref(ok), 4, C.byref(opt))
     assert need > 0
     rc = L.slmc_cumulative_accept(C.byref(ok), C.byref(eff), C.byref(opt), 4, vp, vp, vp, vp, 1, 0,
-                                  vp, vp, vp, need - 1, None)
+                                  vp, vp, None, vp, need - 1, None)
     assert rc == _abi.SLMC_E_WORKSPACE
     rc = L.slmc_cumulative_accept(C.byref(ok), C.byref(eff), C.byref(opt), 0, vp, vp, vp, vp, 1, 0,
-                                  vp, vp, vp, need, None)
+                                  vp, vp, None, vp, need, None)
     assert rc == _abi.SLMC_E_ARG
 
 
@@ -106,6 +106,17 @@ def test_workspace_grows_with_batch_and_sums_over_models():
     both = slmc.workspace_bytes([m1, m2], 30, model_idx=[0] * 10 + [1] * 20,
                                 x_off=np.arange(30) * 20000)
     assert both == a + slmc.workspace_bytes(m2, 20)
+
+
+def test_profile_hooks_without_gpu_work():
+    slmc.profile_reset()
+    out = slmc.profile_read()
+    assert set(out) == {"seg_chain", "wy_apply", "qr", "vupd", "lu", "lu_solve", "residual",
+                        "eff_sweep"}
+    assert all(v == (0.0, 0) for v in out.values())
+    L = _abi.lib()
+    ms, n = C.c_double(), C.c_int64()
+    assert L.slmc_profile_read(9, C.byref(ms), C.byref(n)) == _abi.SLMC_E_ARG
 
 
 def test_binding_refuses_cpu_tensors():
