@@ -68,7 +68,7 @@ enum slmc_precision {
 
 /* One lattice model.  N = Lx*Ly sites, Ltau slices of width dtau (beta = Ltau*dtau),
  * stabilization every n_s slices (the last block may be shorter).
- * Limits: 2 <= Lx, Ly; N <= 512; 1 <= n_s <= Ltau. */
+ * Limits: 2 <= Lx, Ly; N <= 448 (the QR workgroup keeps two N x 16 panels in LDS); 1 <= n_s <= Ltau. */
 typedef struct {
   int32_t Lx, Ly, Ltau, n_s;
   double t;       /* nearest-neighbour hopping (Eq. 2)                                  */

@@ -51,12 +51,21 @@ __device__ __forceinline__ int xcd_remap(int bid, int count) {
   return logical < count ? logical : -1;
 }
 
-// Sum over the 16 lanes of a row group (lanes c..c+15 share g) of a double.
+// Row rotation of a double inside each 16-lane row (DPP row_ror:K).
+template <int K>
+__device__ __forceinline__ double ror16(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x120 + K, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x120 + K, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a row (lanes 16g .. 16g+15); every lane gets the total.
 __device__ __forceinline__ double sum16(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
+  v += ror16<8>(v);
+  v += ror16<4>(v);
+  v += ror16<2>(v);
+  v += ror16<1>(v);
   return v;
 }
 __device__ __forceinline__ double sum64(double v) {
@@ -66,8 +75,5 @@ __device__ __forceinline__ double sum64(double v) {
   return v;
 }
 
-// 1 ulp-accurate-enough log/exp are taken from the device math library.
-__device__ __forceinline__ double dexp(double x) { return exp(x); }
-__device__ __forceinline__ double dlog(double x) { return log(x); }
 
 }  // namespace slmc

@@ -115,14 +115,15 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
         const double ui = (u != 0.0) ? 1.0 / u : 0.0;
         double pv[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) pv[j] = (j > cc) ? Pn[cc * LDY + j] : 0.0;
+        for (int j = 0; j < 16; ++j) {
+          pv[j] = Pn[cc * LDY + j] * (double)(j > cc);
+        }
         for (int r = cc + 1 + tid; r < K; r += 256) {
           double* row = Pn + r * LDY;
           const double l = row[cc] * ui;
-          row[cc] = l;
 #pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (j > cc) row[j] -= l * pv[j];
+          for (int j = 0; j < 16; ++j) row[j] -= l * pv[j];
+          row[cc] = l;
         }
       }
       __syncthreads();
@@ -183,11 +184,10 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
       for (int s = 0; s < 4; ++s) u12 = mfma64(Li[c * LDY + drow64(g, s)], blk[0][s], u12);
       blk[0] = u12;
 #pragma unroll
-      for (int rb = 1; rb < NRBMAX; ++rb) {
-        if (rb < nrbK) {
+      for (int s = 0; s < 4; ++s) {
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            blk[rb] = mfma64(-Pn[(16 * rb + c) * LDY + drow64(g, s)], u12[s], blk[rb]);
+        for (int rb = 1; rb < NRBMAX; ++rb) {
+          if (rb < nrbK) blk[rb] = mfma64(-Pn[(16 * rb + c) * LDY + drow64(g, s)], u12[s], blk[rb]);
         }
       }
 #pragma unroll

@@ -18,12 +18,16 @@ namespace slmc {
 
 namespace {
 
-constexpr int LDY = 17;   // row stride of 16-column LDS panels (bank spread)
+constexpr int LDY = 18;   // row stride of 16-column LDS panels (16-byte aligned rows)
 
 // Householder vector entry Y[r][i] of a panel whose rows/columns are local to the panel:
 // unit diagonal, zero above, stored value below.
+// Arithmetic masking instead of a select: a select lets the compiler sink the LDS read
+// into a divergent branch (one wait per matrix-core instruction); v*m + d keeps the read
+// unconditional (the address is always inside the panel, whose entries are finite).
 __device__ __forceinline__ double yval(const double* Pn, int r, int i) {
-  return r > i ? Pn[r * LDY + i] : (r == i ? 1.0 : 0.0);
+  const double v = Pn[r * LDY + i];
+  return fma(v, (double)(r > i), (double)(r == i));
 }
 
 // ------------------------------------------------------------------------------ wy_apply
@@ -142,29 +146,245 @@ __global__ __launch_bounds__(256) void wy_apply_k(const double* __restrict__ Bsr
 
 // ------------------------------------------------------------------------------ QR
 
+// Workgroup of 8 waves per item.  Wave 0 owns the panels: it updates the next panel's
+// column block with the current reflectors first and then factors it on its own (no
+// workgroup barrier per column), while waves 1-7 apply the current reflectors to the
+// remaining column blocks (look-ahead by one panel).  One barrier per panel step.
+constexpr int QR_THREADS = 512;
+constexpr int QR_UPD_WAVES = QR_THREADS / 64 - 1;
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Unblocked Householder factorization (LAPACK convention: beta = -sign(alpha)||x||,
+// v_0 = 1, tau = (beta - alpha)/beta) of the K x 16 panel Pn held in LDS, by one wave.
+// Row r is handled by lane r mod 64; column sums go through a transposing LDS buffer.
+// Branch-free: columns left of the pivot are masked, not skipped.  Must stay inlined so
+// that Pn, red and dsum are addressed as LDS.
+__device__ __forceinline__ void panel_factor_wave(double* Pn, int K, double* red, double* dsum,
+                                                  double* tau_out, double* beta_out, int lane) {
+  for (int cc = 0; cc < 16; ++cc) {
+    double pj[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) pj[j] = 0.0;
+    for (int r = lane; r < K; r += 64) {
+      const double2* row2 = (const double2*)(Pn + r * LDY);
+      double rv[16];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) { const double2 t = row2[q]; rv[2 * q] = t.x; rv[2 * q + 1] = t.y; }
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) a += rv[j] * (double)(j == cc);
+      a *= (double)(r > cc);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) pj[j] += a * rv[j];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) *(double2*)(red + lane * LDY + 2 * q) = make_double2(pj[2 * q], pj[2 * q + 1]);
+    wave_fence();
+    {
+      const int jj = lane & 15, qq = lane >> 4;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s += red[(qq * 16 + i) * LDY + jj];
+      s += __shfl_xor(s, 16, 64);
+      s += __shfl_xor(s, 32, 64);
+      if (qq == 0) dsum[jj] = s;
+    }
+    wave_fence();
+    double dv[16], rc[16];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double2 t = ((const double2*)dsum)[q]; dv[2 * q] = t.x; dv[2 * q + 1] = t.y;
+      const double2 u = ((const double2*)(Pn + cc * LDY))[q]; rc[2 * q] = u.x; rc[2 * q + 1] = u.y;
+    }
+    double alpha = 0.0, ss = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) { alpha += rc[j] * (double)(j == cc); ss += dv[j] * (double)(j == cc); }
+    double tau, bt, sc;
+    if (ss == 0.0) { tau = 0.0; bt = alpha; sc = 0.0; }
+    else {
+      bt = -copysign(sqrt(alpha * alpha + ss), alpha);
+      tau = (bt - alpha) / bt;
+      sc = 1.0 / (alpha - bt);
+    }
+    double wv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) wv[j] = (rc[j] + sc * dv[j]) * (double)(j > cc);
+    for (int r = lane; r < K; r += 64) {
+      double2* row2 = (double2*)(Pn + r * LDY);
+      double rv[16];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) { const double2 t = row2[q]; rv[2 * q] = t.x; rv[2 * q + 1] = t.y; }
+      double x = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x += rv[j] * (double)(j == cc);
+      const double below = (double)(r > cc), piv = (double)(r == cc);
+      const double v = x * sc * below + piv;
+      const double tv = tau * v * (below + piv);
+      const double nx = below * v + piv * bt + (1.0 - below - piv) * x;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double upd = rv[j] - tv * wv[j];
+        rv[j] = (j == cc) ? nx : upd;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) row2[q] = make_double2(rv[2 * q], rv[2 * q + 1]);
+    }
+    if (lane == 0) { tau_out[cc] = tau; beta_out[cc] = bt; }
+    wave_fence();
+  }
+}
+
 template <int NRBMAX>
-__global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_t astride,
-                                            const double* __restrict__ norm2, int64_t nstride,
-                                            int nparts,
-                                            const double* __restrict__ logDp,
-                                            double* __restrict__ QRW, double* __restrict__ Tb,
-                                            int* __restrict__ perm, double* __restrict__ logD,
-                                            int* __restrict__ qsign, int* __restrict__ status,
-                                            int Np) {
+__device__ __forceinline__ void panel_factor(double* Pn, int K, double* red, double* dsum,
+                                             double* tau_out, double* beta_out, int lane) {
+  panel_factor_wave(Pn, K, red, dsum, tau_out, beta_out, lane);
+}
+
+// T of the compact-WY form I - Y T Y^T of a factored K x 16 panel (one wave): Gram
+// Y^T Y on the matrix cores, then T column by column, row j of T in lane j's registers.
+__device__ __forceinline__ void build_T(const double* Pn, int K, const double* tau, double* gram, double* Tl,
+                        double* Tg, int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  dx4 ga[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
+  for (int rb = 0; rb < (K >> 4); ++rb) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double y = yval(Pn, 16 * rb + 4 * g + s, c);
+      ga[s] = mfma64(y, y, ga[s]);
+    }
+  }
+  const dx4 gacc = ga[0] + ga[1] + ga[2] + ga[3];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) gram[drow64(g, v) * LDY + c] = gacc[v];
+  wave_fence();
+  if (lane < 16) {
+    const int j = lane;
+    double trow[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const double ti = tau[i];
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < i; ++l) {
+        s += trow[l] * gram[l * LDY + i] * (double)(l >= j);
+      }
+      trow[i] = (j < i) ? -ti * s : ((j == i) ? ti : 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      Tl[j * LDY + i] = trow[i];
+      Tg[j * 16 + i] = trow[i];
+    }
+  }
+  wave_fence();
+}
+
+// Rows j0.. of column block cb (16 columns), lane (g, c) register v = row g + 4v of each
+// 16-row block; from A through the column permutation on the first panel step.
+template <int NRBMAX>
+__device__ __forceinline__ void load_block(dx4 (&blk)[NRBMAX], int nrbK, int j0, int cb,
+                                           bool from_a, const double* Ab, const int* iperm,
+                                           const double* Q, int Np, int g, int c) {
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < nrbK) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = j0 + 16 * rb + drow64(g, v);
+        blk[rb][v] = from_a ? Ab[(size_t)row * Np + iperm[16 * cb + c]]
+                            : Q[(size_t)row * Np + 16 * cb + c];
+      }
+    }
+  }
+}
+
+// blk <- (I - Y T Y^T)^T blk for the panel (Y in Pn, T in Tl).
+template <int NRBMAX>
+__device__ __forceinline__ void apply_panel(dx4 (&blk)[NRBMAX], int nrbK, const double* Pn,
+                                            const double* Tl, int g, int c) {
+  // W = Y^T blk: four independent accumulators (one per k-step) keep the pipe full
+  dx4 aw[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < nrbK) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        aw[s] = mfma64(yval(Pn, 16 * rb + drow64(g, s), c), blk[rb][s], aw[s]);
+    }
+  }
+  const dx4 W = aw[0] + aw[1] + aw[2] + aw[3];
+  double tv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) tv[s] = Tl[drow64(g, s) * LDY + c];
+  dx4 Wt = zero4d();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) Wt = mfma64(tv[s], W[s], Wt);
+  // blk -= Y W': consecutive instructions go to different row blocks
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+#pragma unroll
+    for (int rb = 0; rb < NRBMAX; ++rb) {
+      if (rb < nrbK) blk[rb] = mfma64(-yval(Pn, 16 * rb + c, drow64(g, s)), Wt[s], blk[rb]);
+    }
+  }
+}
+
+// One column block of the trailing update, self-contained (load, apply, store) so that
+// no block-sized register array lives across the panel/update branches of the kernel.
+// Rows j0 .. j0+15 go to Q; rows below go to Q, or to the next panel buffer Px when given.
+template <int NRBMAX>
+__device__ __forceinline__ void update_block(int nrbK, int j0, int cb, int from_a,
+                                          const double* __restrict__ Ab,
+                                          const int* __restrict__ iperm, double* __restrict__ Q,
+                                          int Np, const double* Pc, const double* Tc, double* Px,
+                                          int lane) {
+  int c = lane & 15, g = lane >> 4;
+  __asm__ volatile("" : "+v"(c), "+v"(g));
+  dx4 blk[NRBMAX];
+  load_block<NRBMAX>(blk, nrbK, j0, cb, from_a != 0, Ab, iperm, Q, Np, g, c);
+  apply_panel<NRBMAX>(blk, nrbK, Pc, Tc, g, c);
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < nrbK) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = 16 * rb + drow64(g, v);
+        if (Px && rb >= 1) Px[(lr - 16) * LDY + c] = blk[rb][v];
+        else Q[(size_t)(j0 + lr) * Np + 16 * cb + c] = blk[rb][v];
+      }
+    }
+  }
+}
+
+template <int NRBMAX>
+__global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A, int64_t astride,
+                                                   const double* __restrict__ norm2,
+                                                   int64_t nstride, int nparts,
+                                                   const double* __restrict__ logDp,
+                                                   double* __restrict__ QRW,
+                                                   double* __restrict__ Tb,
+                                                   int* __restrict__ perm,
+                                                   double* __restrict__ logD,
+                                                   int* __restrict__ qsign,
+                                                   int* __restrict__ status, int Np) {
   extern __shared__ double lds[];
   const int b = blockIdx.x;
   const int NRB = Np >> 4;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
-  double* Pn0 = lds;                        // [2][Np][LDY]
-  double* key = Pn0 + 2 * Np * LDY;         // [Np]
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  double* Pn0 = lds;                        // [2][Np][LDY] panel buffers
+  double* Tl0 = Pn0 + 2 * Np * LDY;         // [2][16][LDY]
+  double* gram = Tl0 + 2 * 16 * LDY;        // [16][LDY]
+  double* red = gram + 16 * LDY;            // [64][LDY]
+  double* dsum = red + 64 * LDY;            // [16]
+  double* key = dsum + 16;                  // [Np]
   double* beta = key + Np;                  // [Np]
   double* tauA = beta + Np;                 // [Np]
-  double* Tl = tauA + Np;                   // [16][LDY]
-  double* gram = Tl + 16 * LDY;             // [16][LDY]
-  double* wsh = gram + 16 * LDY;            // [16]
-  double* rc = wsh + 16;                    // [16]
-  double* scl = rc + 16;                    // [16]
-  int* iperm = (int*)(scl + 16);            // [Np]
+  double* nt = tauA + Np;                   // [8]
+  int* iperm = (int*)(nt + 8);              // [Np]
   int* flag = iperm + Np;                   // [1]
 
   const double* Ab = A + (size_t)b * astride;
@@ -174,7 +394,7 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
   __syncthreads();
 
   // ---- pre-pivoting: order columns by log ||A e_j|| + log D_prev[j], descending
-  for (int j = tid; j < Np; j += 256) {
+  for (int j = tid; j < Np; j += QR_THREADS) {
     double s = 0.0;
     for (int p = 0; p < nparts; ++p) s += norm2[(size_t)b * nstride + (size_t)p * Np + j];
     double kj = 0.5 * log(s) + (logDp ? logDp[(size_t)b * Np + j] : 0.0);
@@ -182,7 +402,7 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
     key[j] = kj;
   }
   __syncthreads();
-  for (int j = tid; j < Np; j += 256) {
+  for (int j = tid; j < Np; j += QR_THREADS) {
     const double kj = key[j];
     int r = 0;
     for (int jj = 0; jj < Np; ++jj) {
@@ -193,165 +413,44 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
   }
   __syncthreads();
   // key now holds log D_prev in pivot order (the V-update factor needs it)
-  for (int j = tid; j < Np; j += 256) key[j] = logDp ? logDp[(size_t)b * Np + iperm[j]] : 0.0;
-  // panel 0 from A (gathered columns)
-  for (int idx = tid; idx < Np * 16; idx += 256) {
-    int r = idx >> 4, jj = idx & 15;
+  for (int j = tid; j < Np; j += QR_THREADS) key[j] = logDp ? logDp[(size_t)b * Np + iperm[j]] : 0.0;
+  for (int idx = tid; idx < Np * 16; idx += QR_THREADS) {
+    const int r = idx >> 4, jj = idx & 15;
     Pn0[r * LDY + jj] = Ab[(size_t)r * Np + iperm[jj]];
+  }
+  __syncthreads();
+  if (w == 0) {
+    panel_factor<NRBMAX>(Pn0, Np, red, dsum, tauA, beta, lane);
+    build_T(Pn0, Np, tauA, gram, Tl0, Tg, lane);
   }
   __syncthreads();
 
   for (int p = 0; p < NRB; ++p) {
     const int j0 = 16 * p, K = Np - j0, nrbK = NRB - p;
-    double* Pn = Pn0 + (p & 1) * Np * LDY;
-    double* Pnx = Pn0 + ((p + 1) & 1) * Np * LDY;
-
-    // ---- panel factorization (unblocked Householder on K x 16 in LDS)
-    for (int cc = 0; cc < 16; ++cc) {
-      {
-        const int j = tid >> 4, part = tid & 15;
-        double dj = 0.0, ss = 0.0;
-        if (j >= cc) {
-#pragma unroll 4
-          for (int r = cc + 1 + part; r < K; r += 16) {
-            const double a = Pn[r * LDY + cc];
-            dj += a * Pn[r * LDY + j];
-            ss += a * a;
-          }
-        }
-        dj = sum16(dj);
-        ss = sum16(ss);
-        if (j >= cc && part == 0) {
-          const double alpha = Pn[cc * LDY + cc];
-          double tau, bt, sc;
-          if (ss == 0.0) { tau = 0.0; bt = alpha; sc = 0.0; }
-          else {
-            bt = -copysign(sqrt(alpha * alpha + ss), alpha);
-            tau = (bt - alpha) / bt;
-            sc = 1.0 / (alpha - bt);
-          }
-          if (j == cc) { rc[cc] = bt; scl[cc] = sc; tauA[j0 + cc] = tau; beta[j0 + cc] = bt; }
-          else {
-            const double wj = Pn[cc * LDY + j] + sc * dj;
-            wsh[j] = wj;
-            rc[j] = Pn[cc * LDY + j] - tau * wj;
-          }
-        }
-      }
-      __syncthreads();
-      {
-        const double sc = scl[cc], tau = tauA[j0 + cc];
-        double wv[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) wv[j] = (j > cc) ? wsh[j] : 0.0;
-        for (int r = cc + 1 + tid; r < K; r += 256) {
-          double* row = Pn + r * LDY;
-          const double vr = row[cc] * sc;
-          row[cc] = vr;
-          const double tv = tau * vr;
-#pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (j > cc) row[j] -= tv * wv[j];
-        }
-        if (tid == 0)
-          for (int j = cc; j < 16; ++j) Pn[cc * LDY + j] = rc[j];
-      }
-      __syncthreads();
+    double* Pc = Pn0 + (p & 1) * Np * LDY;
+    double* Px = Pn0 + ((p + 1) & 1) * Np * LDY;
+    const double* Tc = Tl0 + (p & 1) * 16 * LDY;
+    double* Tx = Tl0 + ((p + 1) & 1) * 16 * LDY;
+    {
+      // wave 0 updates only the next panel's block (into Px); waves 1-7 the rest
+      const int cb0 = (w == 0) ? p + 1 : p + 2 + (w - 1);
+      const int cbs = (w == 0) ? NRB : QR_UPD_WAVES;
+      for (int cb = cb0; cb < NRB; cb += cbs)
+        update_block<NRBMAX>(nrbK, j0, cb, p == 0, Ab, iperm, Q, Np, Pc, Tc,
+                             cb == p + 1 ? Px : nullptr, lane);
     }
-
-    // ---- T of the compact-WY form: Q_p = I - Y T Y^T (wave 0)
     if (w == 0) {
-      dx4 ga[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
-      for (int rb = 0; rb < nrbK; ++rb) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int kr = 16 * rb + 4 * g + s;
-          const double y = yval(Pn, kr, c);
-          ga[s] = mfma64(y, y, ga[s]);
-        }
+      if (p + 1 < NRB) {
+        wave_fence();
+        panel_factor<NRBMAX>(Px, K - 16, red, dsum, tauA + j0 + 16, beta + j0 + 16, lane);
+        build_T(Px, K - 16, tauA + j0 + 16, gram, Tx, Tg + (size_t)(p + 1) * 256, lane);
       }
-      const dx4 gacc = ga[0] + ga[1] + ga[2] + ga[3];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) gram[drow64(g, v) * LDY + c] = gacc[v];
-      // lanes 0..15: row j of T (kept in registers), built column by column
-      if (lane < 16) {
-        const int j = lane;
-        double trow[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const double ti = tauA[j0 + i];
-          double s = 0.0;
-#pragma unroll
-          for (int l = 0; l < i; ++l)
-            if (l >= j) s += trow[l] * gram[l * LDY + i];
-          trow[i] = (j < i) ? -ti * s : ((j == i) ? ti : 0.0);
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          Tl[j * LDY + i] = trow[i];
-          Tg[(size_t)p * 256 + j * 16 + i] = trow[i];
-        }
+    } else {
+      // the factored panel p: R rows j0..j0+15 and Householder vectors below
+      for (int idx = tid - 64; idx < K * 16; idx += QR_THREADS - 64) {
+        const int r = idx >> 4, jj = idx & 15;
+        Q[(size_t)(j0 + r) * Np + j0 + jj] = Pc[r * LDY + jj];
       }
-    }
-    __syncthreads();
-
-    // ---- trailing update: each wave owns whole 16-column blocks in registers
-    for (int cb = p + 1 + w; cb < NRB; cb += 4) {
-      // opaque copies of the lane coordinates: keeps the per-row addresses from being
-      // hoisted out of this loop (they would pin hundreds of registers)
-      int c = lane & 15, g = lane >> 4;
-      __asm__ volatile("" : "+v"(c), "+v"(g));
-      dx4 blk[NRBMAX];
-#pragma unroll
-      for (int rb = 0; rb < NRBMAX; ++rb) {
-        if (rb < nrbK) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = j0 + 16 * rb + drow64(g, v);
-            blk[rb][v] = (p == 0) ? Ab[(size_t)row * Np + iperm[16 * cb + c]]
-                                  : Q[(size_t)row * Np + 16 * cb + c];
-          }
-        }
-      }
-      dx4 aw[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
-#pragma unroll
-      for (int rb = 0; rb < NRBMAX; ++rb) {
-        if (rb < nrbK) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int kr = 16 * rb + drow64(g, s);
-            aw[rb & 3] = mfma64(yval(Pn, kr, c), blk[rb][s], aw[rb & 3]);
-          }
-        }
-      }
-      dx4 W = aw[0] + aw[1] + aw[2] + aw[3];
-      dx4 Wt = zero4d();
-#pragma unroll
-      for (int s = 0; s < 4; ++s) Wt = mfma64(Tl[drow64(g, s) * LDY + c], W[s], Wt);
-#pragma unroll
-      for (int rb = 0; rb < NRBMAX; ++rb) {
-        if (rb < nrbK) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-            blk[rb] = mfma64(-yval(Pn, 16 * rb + c, drow64(g, s)), Wt[s], blk[rb]);
-        }
-      }
-#pragma unroll
-      for (int rb = 0; rb < NRBMAX; ++rb) {
-        if (rb < nrbK) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int lr = 16 * rb + drow64(g, v);
-            Q[(size_t)(j0 + lr) * Np + 16 * cb + c] = blk[rb][v];
-            if (cb == p + 1 && rb >= 1) Pnx[(lr - 16) * LDY + c] = blk[rb][v];
-          }
-        }
-      }
-    }
-    // ---- the factored panel: R rows j0..j0+15 and Householder vectors below
-    for (int idx = tid; idx < K * 16; idx += 256) {
-      int r = idx >> 4, jj = idx & 15;
-      Q[(size_t)(j0 + r) * Np + j0 + jj] = Pn[r * LDY + jj];
     }
     __threadfence_block();
     __syncthreads();
@@ -359,22 +458,21 @@ __global__ __launch_bounds__(256) void qr_k(const double* __restrict__ A, int64_
 
   // ---- outputs: log D, det Q, perm, and the V-update factor in the upper triangle
   int ntau = 0;
-  for (int i = tid; i < Np; i += 256) {
+  for (int i = tid; i < Np; i += QR_THREADS) {
     logD[(size_t)b * Np + i] = log(fabs(beta[i])) + key[i];
     perm[(size_t)b * Np + i] = iperm[i];
     ntau += tauA[i] != 0.0;
   }
   for (int off = 32; off >= 1; off >>= 1) ntau += __shfl_xor(ntau, off, 64);
-  double* nt = wsh;   // reuse: per-wave counts
-  __syncthreads();
   if (lane == 0) nt[w] = (double)ntau;
   __syncthreads();
   if (tid == 0) {
-    const int tot = (int)(nt[0] + nt[1] + nt[2] + nt[3]);
+    int tot = 0;
+    for (int k = 0; k < QR_THREADS / 64; ++k) tot += (int)nt[k];
     qsign[b] = (tot & 1) ? -1 : 1;
     if (flag[0]) status[b] |= 1;
   }
-  for (int idx = tid; idx < Np * Np; idx += 256) {
+  for (int idx = tid; idx < Np * Np; idx += QR_THREADS) {
     const int i = idx / Np, j = idx - i * Np;
     if (j >= i) {
       const double bi = beta[i];
@@ -456,9 +554,9 @@ template <int NRBMAX>
 hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride, int nparts,
                   const double* logDp, double* QRW, double* Tb, int* perm, double* logD,
                   int* qsign, int* status, int nb, int Np, hipStream_t st) {
-  const size_t lds = (size_t)(2 * Np * LDY + 3 * Np + 2 * 16 * LDY + 48) * sizeof(double) +
-                     (size_t)(Np + 2) * sizeof(int);
-  hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(256), lds, st, A, astride, norm2, nstride, nparts,
+  const size_t lds = (size_t)(2 * Np * LDY + 3 * 16 * LDY + 64 * LDY + 16 + 3 * Np + 8) *
+                         sizeof(double) + (size_t)(Np + 2) * sizeof(int);
+  hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(QR_THREADS), lds, st, A, astride, norm2, nstride, nparts,
                      logDp, QRW, Tb, perm, logD, qsign, status, Np);
   return hipGetLastError();
 }

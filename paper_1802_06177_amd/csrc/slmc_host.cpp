@@ -74,7 +74,7 @@ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 int check_model(const slmc_model* m) {
   if (!m) return fail(SLMC_E_ARG, "model is NULL");
   if (m->Lx < 2 || m->Ly < 2) return fail(SLMC_E_SHAPE, "Lx, Ly must be >= 2 (got %d, %d)", m->Lx, m->Ly);
-  if ((int64_t)m->Lx * m->Ly > 512) return fail(SLMC_E_SHAPE, "N = Lx*Ly must be <= 512");
+  if ((int64_t)m->Lx * m->Ly > 448) return fail(SLMC_E_SHAPE, "N = Lx*Ly must be <= 448");
   if (m->Ltau < 1) return fail(SLMC_E_SHAPE, "Ltau must be >= 1");
   if (m->n_s < 1 || m->n_s > m->Ltau) return fail(SLMC_E_ARG, "n_s must be in [1, Ltau]");
   if (!(m->dtau > 0.0) || !std::isfinite(m->dtau)) return fail(SLMC_E_ARG, "dtau must be > 0");

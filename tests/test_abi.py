@@ -58,7 +58,7 @@ def test_validation_errors_are_synchronous_codes():
     good = slmc.model(4, 4, 40, 10)
     assert _call_logdet([slmc.model(1, 4, 40, 10)], 2) == _abi.SLMC_E_SHAPE
     assert b"Lx" in L.slmc_last_error()
-    assert _call_logdet([slmc.model(32, 32, 40, 10)], 2) == _abi.SLMC_E_SHAPE      # N > 512
+    assert _call_logdet([slmc.model(32, 32, 40, 10)], 2) == _abi.SLMC_E_SHAPE      # N > 448
     assert _call_logdet([slmc.model(4, 4, 40, 0)], 2) == _abi.SLMC_E_ARG          # n_s < 1
     assert _call_logdet([slmc.model(4, 4, 40, 41)], 2) == _abi.SLMC_E_ARG         # n_s > Ltau
     assert _call_logdet([slmc.model(4, 4, 40, 10, dtau=-0.1)], 2) == _abi.SLMC_E_ARG

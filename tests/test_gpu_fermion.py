@@ -125,6 +125,15 @@ def test_fp64_free_fermion_16x16():
     assert np.max(np.abs(G[0] - pins.free_green(16, 16, 1.0, 0.0, 16.0))) < 1e-9
 
 
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s", [(20, 20, 24, 8), (21, 21, 18, 6)])
+def test_fp64_largest_lattices(Lx, Ly, Ltau, n_s):
+    # N = 400 and N = 441 (padded to 448, the largest size the library accepts)
+    md = _md(Lx, Ltau, n_s, 1.5, Ly=Ly)
+    g = gen(95, Lx * Ly)
+    xs = [g.normal(0.0, 1.0, size=(Ltau, Lx * Ly)) for _ in range(2)]
+    _check(md, xs, _run(md, xs), 1e-11, 1e-9)
+
+
 def test_fp64_full_size_16x16_sampled_items():
     md = workload_models("W4", 1)[0]
     xs = [workload_item("W4", b, 1)[1] for b in (0, 77)]
