@@ -38,6 +38,8 @@ def main():
     ap.add_argument("--residual", type=int, default=1)
     ap.add_argument("--chains", type=int, default=128)
     ap.add_argument("--lam", type=float, default=1.5)
+    ap.add_argument("--serial", action="store_true",
+                    help="keep the segment products on the caller's stream (no overlap)")
     ap.add_argument("--cpu-sample", type=int, default=6, help="oracle items for cpu_baseline (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -60,7 +62,7 @@ def main():
     m = slmc.model_from_dict(md)
     ec = eff_coefficients(4, 0, args.lam, delta=0.6)
     eff = slmc.eff_model(**ec)
-    opt = slmc.options(args.precision, args.residual, args.acc_chunk)
+    opt = slmc.options(args.precision, args.residual, args.acc_chunk, serial=args.serial)
 
     xs = np.stack([workload_item("W4", b % 128, lam_idx)[1] for b in range(B)])
     x_cur = torch.tensor(xs, dtype=torch.float64, device=dev)
@@ -156,7 +158,8 @@ def main():
         "config": {"workload": "16x16 (N=256), beta=16 (Ltau=160), n_s=8, lam=%.1f, omega0=1, "
                               "%d chains; step = sweep + logdet+G of proposals + accept" % (md["lam"], B),
                    "precision": args.precision, "acc_chunk": args.acc_chunk,
-                   "residual_steps": args.residual, "global_batch": B, "parallelism": "none"},
+                   "residual_steps": args.residual, "global_batch": B, "parallelism": "none",
+                   "schedule": "serial" if args.serial else "overlapped"},
         "roofline": roof, "cpu_baseline": cpu, "error_vs_oracle": err,
         "accept_rate": round(acc_total / (B * args.steps), 4), "wall_s": round(wall, 3),
     }

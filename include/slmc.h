@@ -83,8 +83,18 @@ typedef struct {
   int32_t precision;       /* enum slmc_precision                                       */
   int32_t residual_steps;  /* FP64 refinement steps on G (0 or 1); ignored by logdet    */
   int32_t acc_chunk;       /* FP32 kinds: k-steps (of 4) per FP64 promotion: 0,1,2,4   */
-  int32_t flags;           /* reserved, must be 0                                        */
+  int32_t flags;           /* bit set of enum slmc_flags; other bits must be 0         */
 } slmc_options;
+
+/* Scheduling flags.  By default, when a model has more than one stabilization block, the
+ * segment products run on a stream the library owns (one per device, default priority,
+ * created on first use, destroyed by slmc_cache_clear), forked from and joined back to
+ * the caller's stream with events, so that the sequential stabilization chain overlaps
+ * the remaining segment products.  Results are identical either way; calls from several
+ * host threads on one device serialize while they enqueue. */
+enum slmc_flags {
+  SLMC_FLAG_SERIAL = 1  /* run every kernel on the caller's stream, in order            */
+};
 
 /* A batch of items, possibly of different models (uneven sizes in one call).
  * model_idx, x_off, g_off are HOST arrays of n_items entries, or NULL:
@@ -200,8 +210,9 @@ int slmc_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches)
 void slmc_profile_reset(void);
 const char* slmc_profile_name(int32_t kernel_class);
 
-/* Frees the library's device constant cache (e^{-dtau K} copies per model and device).
- * Must not be called while work that uses it is still queued. */
+/* Frees the library's device constant cache (e^{-dtau K} copies per model and device)
+ * and its side streams (after waiting for them).  Must not be called while work that
+ * uses them is still queued on other streams. */
 void slmc_cache_clear(void);
 
 #ifdef __cplusplus

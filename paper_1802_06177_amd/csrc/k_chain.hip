@@ -58,7 +58,7 @@ __device__ void first_slice(const double* __restrict__ E, const double* vl0,
 template <int RB, int CB>
 __global__ __launch_bounds__(256) void seg_chain_f64(const double* __restrict__ E, FieldRef f,
                                                      int nb, int N, int Np, int Ltau, int n_s,
-                                                     int m, double ldl,
+                                                     int m, int k0, int kc, double ldl,
                                                      double* __restrict__ S,
                                                      double* __restrict__ snorm) {
   constexpr int W = 16 * CB;
@@ -68,9 +68,9 @@ __global__ __launch_bounds__(256) void seg_chain_f64(const double* __restrict__ 
   double* vbuf = P + W * LDP;           // [2][Np]
   double* red = vbuf + 2 * Np;          // [256] reduction scratch
   const int npan = Np / W;
-  const int id = xcd_remap(blockIdx.x, nb * m * npan);
+  const int id = xcd_remap(blockIdx.x, nb * kc * npan);
   if (id < 0) return;
-  const int pan = id % npan, k = (id / npan) % m, b = id / (npan * m);
+  const int pan = id % npan, k = k0 + (id / npan) % kc, b = id / (npan * kc);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
   const int NRB = Np >> 4, c0 = pan * W;
   const double* xb = field_of(f, b);
@@ -191,35 +191,35 @@ __global__ __launch_bounds__(256) void seg_chain_f64(const double* __restrict__ 
 // ------------------------------------------------------------------------------ dispatch
 
 template <int RB, int CB>
-hipError_t run_f64(const double* E, FieldRef f, int nb, int N, int Np, int Ltau, int n_s, int m,
+hipError_t run_f64(const double* E, FieldRef f, int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc,
                    double ldl, double* S, double* sn, hipStream_t st) {
   constexpr int W = 16 * CB;
-  const int count = nb * m * (Np / W);
+  const int count = nb * kc * (Np / W);
   const size_t lds = (size_t)(W * (Np + 2) + 2 * Np + 256) * sizeof(double);
   hipLaunchKernelGGL((seg_chain_f64<RB, CB>), dim3(xcd_grid(count)), dim3(256), lds, st, E, f,
-                     nb, N, Np, Ltau, n_s, m, ldl, S, sn);
+                     nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn);
   return hipGetLastError();
 }
 
 template <int RB>
 hipError_t pick_f64(int CB, const double* E, FieldRef f, int nb, int N, int Np, int Ltau,
-                    int n_s, int m, double ldl, double* S, double* sn, hipStream_t st) {
-  if (CB == 2) return run_f64<RB, 2>(E, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-  return run_f64<RB, 1>(E, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+                    int n_s, int m, int k0, int kc, double ldl, double* S, double* sn, hipStream_t st) {
+  if (CB == 2) return run_f64<RB, 2>(E, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+  return run_f64<RB, 1>(E, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
 }
 
 }  // namespace
 
 hipError_t launch_seg_bf16(int pieces, const double* E64, const uint16_t* Ebf, FieldRef f,
-                           int nb, int N, int Np, int Ltau, int n_s, int m, double ldl,
+                           int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl,
                            double* S, double* snorm, hipStream_t st);
 hipError_t launch_seg_f32(int ecorr, int ch, const float* E32, const uint16_t* Elo,
                           const double* E64, FieldRef f, int nb, int N, int Np, int Ltau, int n_s,
-                          int m, double ldl, double* S, double* snorm, hipStream_t st);
+                          int m, int k0, int kc, double ldl, double* S, double* snorm, hipStream_t st);
 
 hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const float* E32,
                             const uint16_t* Elo, const uint16_t* Ebf, FieldRef f, int nb, int N, int Np, int Ltau,
-                            int n_s, int m, double ldl, double* S, double* snorm,
+                            int n_s, int m, int k0, int kc, double ldl, double* S, double* snorm,
                             hipStream_t st) {
   const int NRB = Np / 16;
   const int RB = (NRB + 3) / 4;
@@ -228,21 +228,21 @@ hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const fl
     // panel width: 32 columns when it divides Np and the LDS panel stays small
     const int CB = (Np % 32 == 0 && Np <= 256) ? 2 : 1;
     switch (RB) {
-      case 1: return pick_f64<1>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 2: return pick_f64<2>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 3: return pick_f64<3>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 4: return pick_f64<4>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 5: return pick_f64<5>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 6: return pick_f64<6>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      case 7: return pick_f64<7>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-      default: return pick_f64<8>(CB, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+      case 1: return pick_f64<1>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+      case 2: return pick_f64<2>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+      case 3: return pick_f64<3>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+      case 4: return pick_f64<4>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+      case 5: return pick_f64<5>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+      case 6: return pick_f64<6>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+      case 7: return pick_f64<7>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+      default: return pick_f64<8>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
     }
   }
   if (prec == 1 || prec == 4)
-    return launch_seg_f32(prec == 1, acc_chunk, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S,
+    return launch_seg_f32(prec == 1, acc_chunk, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S,
                           snorm, st);
   if (prec == 2 || prec == 3)
-    return launch_seg_bf16(prec == 2 ? 2 : 3, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    return launch_seg_bf16(prec == 2 ? 2 : 3, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
   return hipErrorInvalidValue;
 }
 

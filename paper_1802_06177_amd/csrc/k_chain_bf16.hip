@@ -42,7 +42,7 @@ template <int RB, int CB, int PIECES>
 __global__ __launch_bounds__(256) void seg_chain_bf(const double* __restrict__ E64,
                                                     const uint16_t* __restrict__ Ebf, FieldRef f,
                                                     int nb, int N, int Np, int Ltau, int n_s,
-                                                    int m, double ldl, double* __restrict__ S,
+                                                    int m, int k0, int kc, double ldl, double* __restrict__ S,
                                                     double* __restrict__ snorm) {
   constexpr int W = 16 * CB;
   extern __shared__ double lds[];
@@ -51,9 +51,9 @@ __global__ __launch_bounds__(256) void seg_chain_bf(const double* __restrict__ E
   double* red = vbuf + 2 * Np;                             // [256]
   uint16_t* P = (uint16_t*)(red + 256);                    // [PIECES][W][LDP]
   const int npan = Np / W;
-  const int id = xcd_remap(blockIdx.x, nb * m * npan);
+  const int id = xcd_remap(blockIdx.x, nb * kc * npan);
   if (id < 0) return;
-  const int pan = id % npan, k = (id / npan) % m, b = id / (npan * m);
+  const int pan = id % npan, k = k0 + (id / npan) % kc, b = id / (npan * kc);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
   const int NRB = Np >> 4, NKB = Np >> 5, c0 = pan * W;
   const size_t plane = (size_t)W * LDP, eplane = (size_t)Np * Np;
@@ -189,45 +189,45 @@ __global__ __launch_bounds__(256) void seg_chain_bf(const double* __restrict__ E
 
 template <int RB, int CB, int PIECES>
 hipError_t run_bf(const double* E64, const uint16_t* Ebf, FieldRef f, int nb, int N, int Np,
-                  int Ltau, int n_s, int m, double ldl, double* S, double* sn, hipStream_t st) {
+                  int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S, double* sn, hipStream_t st) {
   constexpr int W = 16 * CB;
-  const int count = nb * m * (Np / W);
+  const int count = nb * kc * (Np / W);
   const size_t lds = (size_t)(2 * Np + 256) * sizeof(double) +
                      (size_t)PIECES * W * (Np + 8) * sizeof(uint16_t);
   hipLaunchKernelGGL((seg_chain_bf<RB, CB, PIECES>), dim3(xcd_grid(count)), dim3(256), lds, st,
-                     E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn);
+                     E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn);
   return hipGetLastError();
 }
 
 template <int RB>
 hipError_t pick_bf(int pieces, int CB, const double* E64, const uint16_t* Ebf, FieldRef f, int nb,
-                   int N, int Np, int Ltau, int n_s, int m, double ldl, double* S, double* sn,
+                   int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S, double* sn,
                    hipStream_t st) {
   if (pieces == 2) {
-    if (CB == 2) return run_bf<RB, 2, 2>(E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    return run_bf<RB, 1, 2>(E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+    if (CB == 2) return run_bf<RB, 2, 2>(E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+    return run_bf<RB, 1, 2>(E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
   }
-  if (CB == 2) return run_bf<RB, 2, 3>(E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-  return run_bf<RB, 1, 3>(E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+  if (CB == 2) return run_bf<RB, 2, 3>(E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+  return run_bf<RB, 1, 3>(E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
 }
 
 }  // namespace
 
 hipError_t launch_seg_bf16(int pieces, const double* E64, const uint16_t* Ebf, FieldRef f,
-                           int nb, int N, int Np, int Ltau, int n_s, int m, double ldl,
+                           int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl,
                            double* S, double* snorm, hipStream_t st) {
   if (Np % 32 != 0) return hipErrorInvalidValue;   // k-blocks of 32
   const int NRB = Np / 16, RB = (NRB + 3) / 4;
   const int CB = (Np % 32 == 0) ? 2 : 1;
   switch (RB) {
-    case 1: return pick_bf<1>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 2: return pick_bf<2>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 3: return pick_bf<3>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 4: return pick_bf<4>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 5: return pick_bf<5>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 6: return pick_bf<6>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 7: return pick_bf<7>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    default: return pick_bf<8>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 1: return pick_bf<1>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 2: return pick_bf<2>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 3: return pick_bf<3>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 4: return pick_bf<4>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 5: return pick_bf<5>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 6: return pick_bf<6>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 7: return pick_bf<7>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    default: return pick_bf<8>(pieces, CB, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
   }
 }
 

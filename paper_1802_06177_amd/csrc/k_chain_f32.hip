@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void seg_chain_f32(const float* __restrict__ E
                                                      const uint16_t* __restrict__ Elo,
                                                      const double* __restrict__ E64,
                                                      FieldRef f, int nb, int N, int Np,
-                                                     int Ltau, int n_s, int m, double ldl,
+                                                     int Ltau, int n_s, int m, int k0, int kc, double ldl,
                                                      double* __restrict__ S,
                                                      double* __restrict__ snorm) {
   constexpr int W = 16 * CB;
@@ -43,9 +43,9 @@ __global__ __launch_bounds__(256) void seg_chain_f32(const float* __restrict__ E
   float* P = (float*)(red + 256);                          // [W][LDP]
   uint16_t* Pb = (uint16_t*)(P + W * LDP);                 // [W][LDB] (ECORR)
   const int npan = Np / W;
-  const int id = xcd_remap(blockIdx.x, nb * m * npan);
+  const int id = xcd_remap(blockIdx.x, nb * kc * npan);
   if (id < 0) return;
-  const int pan = id % npan, k = (id / npan) % m, b = id / (npan * m);
+  const int pan = id % npan, k = k0 + (id / npan) % kc, b = id / (npan * kc);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
   const int NRB = Np >> 4, c0 = pan * W;
   const double* xb = field_of(f, b);
@@ -227,58 +227,58 @@ __global__ __launch_bounds__(256) void seg_chain_f32(const float* __restrict__ E
 
 template <int RB, int CB, int CH, bool EC>
 hipError_t run_f32(const float* E32, const uint16_t* Elo, const double* E64, FieldRef f, int nb,
-                   int N, int Np, int Ltau, int n_s, int m, double ldl, double* S, double* sn,
+                   int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S, double* sn,
                    hipStream_t st) {
   constexpr int W = 16 * CB;
-  const int count = nb * m * (Np / W);
+  const int count = nb * kc * (Np / W);
   const size_t lds = (size_t)(2 * Np + 256) * sizeof(double) + (size_t)W * (Np + 4) * sizeof(float) +
                      (EC ? (size_t)W * (Np + 8) * sizeof(uint16_t) : 0);
   hipLaunchKernelGGL((seg_chain_f32<RB, CB, CH, EC>), dim3(xcd_grid(count)), dim3(256), lds, st,
-                     E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn);
+                     E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn);
   return hipGetLastError();
 }
 
 template <int RB, int CB, bool EC>
 hipError_t pick_ch(int ch, const float* E32, const uint16_t* Elo, const double* E64, FieldRef f,
-                   int nb, int N, int Np, int Ltau, int n_s, int m, double ldl, double* S,
+                   int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
                    double* sn, hipStream_t st) {
   switch (ch) {
-    case 0: return run_f32<RB, CB, 0, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    case 1: return run_f32<RB, CB, 1, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    case 2: return run_f32<RB, CB, 2, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    case 4: return run_f32<RB, CB, 4, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+    case 0: return run_f32<RB, CB, 0, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+    case 1: return run_f32<RB, CB, 1, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+    case 2: return run_f32<RB, CB, 2, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+    case 4: return run_f32<RB, CB, 4, EC>(E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int RB>
 hipError_t pick_f32(int ec, int ch, const float* E32, const uint16_t* Elo, const double* E64,
-                    FieldRef f, int nb, int N, int Np, int Ltau, int n_s, int m, double ldl,
+                    FieldRef f, int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl,
                     double* S, double* sn, hipStream_t st) {
   const int CB = (Np % 32 == 0) ? 2 : 1;
   if (ec) {
-    if (CB == 2) return pick_ch<RB, 2, true>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-    return pick_ch<RB, 1, true>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+    if (CB == 2) return pick_ch<RB, 2, true>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+    return pick_ch<RB, 1, true>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
   }
-  if (CB == 2) return pick_ch<RB, 2, false>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
-  return pick_ch<RB, 1, false>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, sn, st);
+  if (CB == 2) return pick_ch<RB, 2, false>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+  return pick_ch<RB, 1, false>(ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
 }
 
 }  // namespace
 
 hipError_t launch_seg_f32(int ecorr, int ch, const float* E32, const uint16_t* Elo,
                           const double* E64, FieldRef f, int nb, int N, int Np, int Ltau, int n_s,
-                          int m, double ldl, double* S, double* snorm, hipStream_t st) {
+                          int m, int k0, int kc, double ldl, double* S, double* snorm, hipStream_t st) {
   const int RB = (Np / 16 + 3) / 4;
   switch (RB) {
-    case 1: return pick_f32<1>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 2: return pick_f32<2>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 3: return pick_f32<3>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 4: return pick_f32<4>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 5: return pick_f32<5>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 6: return pick_f32<6>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 7: return pick_f32<7>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
-    case 8: return pick_f32<8>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, ldl, S, snorm, st);
+    case 1: return pick_f32<1>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 2: return pick_f32<2>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 3: return pick_f32<3>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 4: return pick_f32<4>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 5: return pick_f32<5>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 6: return pick_f32<6>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 7: return pick_f32<7>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 8: return pick_f32<8>(ecorr, ch, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
     default: return hipErrorInvalidValue;
   }
 }

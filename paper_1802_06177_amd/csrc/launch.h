@@ -17,14 +17,15 @@ struct FieldRef {
 
 // Segment products S_k = B_{k n_s + len-1} ... B_{k n_s}, B_l = E diag(exp(-ldl x_l)),
 // for all items b < nb and segments k < m, into S[(b*m + k)][Np][Np] (FP64), and the
-// squared column norms of every S_k into snorm[(b*m + k)][Np].
+// squared column norms of every S_k into snorm[(b*m + k)][Np].  Only the segments
+// k0 .. k0+kc-1 are computed (m stays the segment count of the S and snorm layout).
 // prec: 0 FP64; 1 FP32 with the bf16 correction of E's FP32 rounding; 4 FP32 without it;
 // (acc_chunk = k-steps of 4 per FP64 promotion of the FP32 sums, 0 = none); 2 bf16x3;
 // 3 bf16x6.  E64/E32/Elo/Ebf point at the padded exponential in each format
 // (Elo: bf16 of E64 - E32; Ebf: [pieces][Np][Np] bf16 bit patterns).
 hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const float* E32,
                             const uint16_t* Elo, const uint16_t* Ebf, FieldRef f, int nb, int N, int Np, int Ltau,
-                            int n_s, int m, double ldl, double* S, double* snorm,
+                            int n_s, int m, int k0, int kc, double ldl, double* S, double* snorm,
                             hipStream_t st);
 
 // A[b] = Bsrc[b] Q[b] (Q = H_0 ... H_{Np-1} in compact-WY blocks: Householder vectors

@@ -51,6 +51,16 @@ struct ProfScope {
 
 thread_local std::string g_err;
 
+// Library-owned side stream per device (default priority) and the events that order it
+// against the caller's stream.  g_side_mu is held while a call enqueues on it, so the
+// events are never re-recorded before the waits on them are enqueued.
+struct SideStream {
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+};
+std::mutex g_side_mu;
+std::map<int, SideStream> g_side;
+
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -67,6 +77,21 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess)                                                            \
       return fail(SLMC_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
   } while (0)
+
+// The current device's side stream with at least nev events; g_side_mu must be held.
+int side_stream_locked(int nev, SideStream** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  SideStream& ss = g_side[dev];
+  if (!ss.s) HIPCHK(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+  while ((int)ss.ev.size() < nev) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ss.ev.push_back(e);
+  }
+  *out = &ss;
+  return SLMC_OK;
+}
 
 inline int roundup16(int n) { return (n + 15) / 16 * 16; }
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -90,7 +115,7 @@ int check_opt(const slmc_options* o) {
   if (o->residual_steps < 0 || o->residual_steps > 1) return fail(SLMC_E_ARG, "residual_steps must be 0 or 1");
   if (!(o->acc_chunk == 0 || o->acc_chunk == 1 || o->acc_chunk == 2 || o->acc_chunk == 4))
     return fail(SLMC_E_ARG, "acc_chunk must be one of 0, 1, 2, 4");
-  if (o->flags != 0) return fail(SLMC_E_ARG, "flags must be 0");
+  if (o->flags & ~SLMC_FLAG_SERIAL) return fail(SLMC_E_ARG, "unknown flags 0x%x", o->flags);
   return SLMC_OK;
 }
 
@@ -313,17 +338,36 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   }
 
   HIPCHK(launch_fill_i32(w.status, nb, 0, st));
-  // a2: segment products (a1 fused: the phonon factors scale the panel rows)
-  {
-  ProfScope ps(0, st);
-  HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo,
-                          o->precision == 2 ? mc->Ebf2 : mc->Ebf3, f, nb, N, Np, m->Ltau, m->n_s,
-                          mseg, ldl, w.S, w.snorm, st));
+  // a2: segment products (a1 fused: the phonon factors scale the panel rows).  With more
+  // than one block they go to the side stream, one launch per block, and step k of the
+  // chain below waits only for block k: the chain (one workgroup per item, latency-bound)
+  // then runs while the later segment products fill the compute units it leaves idle.
+  const uint16_t* Ebf = o->precision == 2 ? mc->Ebf2 : mc->Ebf3;
+  const bool overlap = !(o->flags & SLMC_FLAG_SERIAL) && mseg > 1;
+  std::unique_lock<std::mutex> side_lock(g_side_mu, std::defer_lock);
+  SideStream* ss = nullptr;
+  if (overlap) {
+    side_lock.lock();
+    rc = side_stream_locked(mseg + 1, &ss);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(ss->ev[mseg], st));
+    HIPCHK(hipStreamWaitEvent(ss->s, ss->ev[mseg], 0));
+    for (int k = 0; k < mseg; ++k) {
+      ProfScope ps(0, ss->s);
+      HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, f, nb, N,
+                              Np, m->Ltau, m->n_s, mseg, k, 1, ldl, w.S, w.snorm, ss->s));
+      HIPCHK(hipEventRecord(ss->ev[k], ss->s));
+    }
+  } else {
+    ProfScope ps(0, st);
+    HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, f, nb, N,
+                            Np, m->Ltau, m->n_s, mseg, 0, mseg, ldl, w.S, w.snorm, st));
   }
   // a3: stabilized accumulation
   double* logD[2] = {w.logD0, w.logD1};
   double* Vb[2] = {w.V0, w.V1};
   for (int k = 0; k < mseg; ++k) {
+    if (overlap) HIPCHK(hipStreamWaitEvent(st, ss->ev[k], 0));
     const double* Ain;
     int64_t astride, nstride;
     const double* nrm;
@@ -635,6 +679,17 @@ void slmc_cache_clear(void) {
     (void)hipSetDevice(cur);
   }
   g_cache.clear();
+  std::lock_guard<std::mutex> lk2(g_side_mu);
+  for (auto& kv : g_side) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(kv.first);
+    if (kv.second.s) (void)hipStreamSynchronize(kv.second.s);
+    for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
+    if (kv.second.s) (void)hipStreamDestroy(kv.second.s);
+    (void)hipSetDevice(cur);
+  }
+  g_side.clear();
 }
 
 }  // extern "C"

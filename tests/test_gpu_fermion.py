@@ -186,6 +186,22 @@ def test_run_twice_bitwise_identical():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_overlapped_and_serial_schedules_are_bitwise_identical(prec):
+    # segment products on the library's side stream (default) or on the caller's stream
+    md = workload_models("W2")[0]
+    xs = [workload_item("W2", b)[1] for b in range(5)]
+    m = slmc.model_from_dict(md)
+    x = torch.tensor(np.stack(xs), dtype=torch.float64, device=DEV)
+    outs = []
+    for serial in (False, True, False):
+        ld, sg, G, st = slmc.green(m, x, slmc.options(prec, 1, 1, serial=serial))
+        torch.cuda.synchronize()
+        outs.append((ld.cpu().numpy(), G.cpu().numpy()))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
 def test_residual_step_does_not_degrade_G():
     md = workload_models("W2")[0]
     xs = [workload_item("W2", b)[1] for b in range(3)]
