@@ -146,158 +146,185 @@ __global__ __launch_bounds__(256) void wy_apply_k(const double* __restrict__ Bsr
 
 // ------------------------------------------------------------------------------ QR
 
-// Workgroup of 8 waves per item.  Wave 0 owns the panels: it updates the next panel's
-// column block with the current reflectors first and then factors it on its own (no
-// workgroup barrier per column), while waves 1-7 apply the current reflectors to the
-// remaining column blocks (look-ahead by one panel).  One barrier per panel step.
+// Workgroup of 8 waves per item.  Each 16-column panel is factored by waves 0-3 (one per
+// SIMD), every thread holding one or two rows of the panel in registers; the column
+// steps exchange their 16 sums through a wave reduce-scatter and one barrier each.  The
+// trailing column blocks are then updated by all 8 waves on the matrix cores.
 constexpr int QR_THREADS = 512;
-constexpr int QR_UPD_WAVES = QR_THREADS / 64 - 1;
+constexpr int QR_WAVES = QR_THREADS / 64;
 
-__device__ __forceinline__ void wave_fence() {
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// (x, y) <- lanes 32-63 of x exchanged with lanes 0-31 of y (v_permlane32_swap), and
+// the same for odd/even 16-lane rows (v_permlane16_swap).
+__device__ __forceinline__ void swap32(double& x, double& y) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+  x = __hiloint2double(hi[0], lo[0]);
+  y = __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ void swap16(double& x, double& y) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+  x = __hiloint2double(hi[0], lo[0]);
+  y = __hiloint2double(hi[1], lo[1]);
+}
+
+// Reduce-scatter of 16 values over the 64 lanes of a wave: on return lanes 4v .. 4v+3
+// hold the wave total of value v.  Each halving stage pairs lanes that differ in one bit
+// (5 and 4 by the permlane swaps, 3 and 2 by the row mirrors), the last two add quads.
+__device__ __forceinline__ double reduce_scatter16(const double (&v)[16], int lane) {
+  double a[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double x = v[i], y = v[i + 8];
+    swap32(x, y);
+    a[i] = x + y;            // value i + 8 * bit5
+  }
+  double b[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double x = a[i], y = a[i + 4];
+    swap16(x, y);
+    b[i] = x + y;            // value ... + 4 * bit4
+  }
+  const bool h3 = (lane & 8) != 0, h2 = (lane & 4) != 0;
+  double c[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = h3 ? b[i] : b[i + 2];
+    const double keep = h3 ? b[i + 2] : b[i];
+    c[i] = keep + dpp64<0x140>(send);    // row_mirror: partner 15 - l
+  }
+  const double send = h2 ? c[0] : c[1];
+  double d = (h2 ? c[1] : c[0]) + dpp64<0x141>(send);   // row_half_mirror: partner 7 - l
+  d += dpp64<0xB1>(d);                                 // quad_perm [1,0,3,2]
+  d += dpp64<0x4E>(d);                                 // quad_perm [2,3,0,1]
+  return d;
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
-// Unblocked Householder factorization (LAPACK convention: beta = -sign(alpha)||x||,
-// v_0 = 1, tau = (beta - alpha)/beta) of the K x 16 panel Pn held in LDS, by one wave.
-// Row r is handled by lane r mod 64; column sums go through a transposing LDS buffer.
-// Branch-free: columns left of the pivot are masked, not skipped.  Must stay inlined so
-// that Pn, red and dsum are addressed as LDS.
-__device__ __forceinline__ void panel_factor_wave(double* Pn, int K, double* red, double* dsum,
-                                                  double* tau_out, double* beta_out, int lane) {
+// Householder factorization (LAPACK convention: beta = -sign(alpha)||x||, v_0 = 1,
+// tau = (beta - alpha)/beta) of the K x 16 panel held in registers by the first 4 waves
+// (one per SIMD): thread t < 256 owns local rows t (row0) and t + 256 (row1, only when
+// TWO); rows >= K are zero.  Column step cc needs P_j = sum_{r > cc} row_r[cc] row_r[j]
+// for all 16 j: j = cc gives ||x||^2 below the pivot, j > cc the reflector's product with
+// the remaining columns, and j < cc (the earlier Householder vectors) gives Y^T v, from
+// which column cc of the compact-WY factor T follows (T_cc,cc = tau,
+// T_l,cc = -tau sum_m T_l,m (Y^T v)_m); lane l & 15 keeps row l & 15 of T in trow and
+// threads 0-15 store it to Tl.  The sums go through a wave reduce-scatter and one
+// workgroup barrier per column (waves 4-7 only take part in the barriers); red [2][4][16]
+// and prow [2][16] are double-buffered by column parity, wsum [4][16] is a per-wave
+// broadcast slot.
+constexpr int QR_PANEL_WAVES = 4;
+
+template <bool TWO>
+__device__ __forceinline__ void panel_factor_all(double (&row0)[16], double (&row1)[16],
+                                                 double (&trow)[16], int t, int K, double* red,
+                                                 double* prow, double* wsum, double* Tl,
+                                                 double* tau_out, double* beta_out) {
+  const int lane = t & 63, w = t >> 6, tl = lane & 15;
+  const bool act = w < QR_PANEL_WAVES;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) trow[j] = 0.0;
+#pragma unroll
   for (int cc = 0; cc < 16; ++cc) {
-    double pj[16];
+    double* rb = red + (cc & 1) * QR_PANEL_WAVES * 16;
+    double* pb = prow + (cc & 1) * 16;
+    if (act) {
+      const double am0 = row0[cc] * (double)(t > cc && t < K);
+      const double am1 = TWO ? row1[cc] * (double)(t + 256 < K) : 0.0;
+      double pj[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) pj[j] = 0.0;
-    for (int r = lane; r < K; r += 64) {
-      const double2* row2 = (const double2*)(Pn + r * LDY);
-      double rv[16];
+      for (int j = 0; j < 16; ++j) pj[j] = TWO ? am0 * row0[j] + am1 * row1[j] : am0 * row0[j];
+      if (t == cc) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) { const double2 t = row2[q]; rv[2 * q] = t.x; rv[2 * q + 1] = t.y; }
-      double a = 0.0;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) a += rv[j] * (double)(j == cc);
-      a *= (double)(r > cc);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) pj[j] += a * rv[j];
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) *(double2*)(red + lane * LDY + 2 * q) = make_double2(pj[2 * q], pj[2 * q + 1]);
-    wave_fence();
-    {
-      const int jj = lane & 15, qq = lane >> 4;
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) s += red[(qq * 16 + i) * LDY + jj];
-      s += __shfl_xor(s, 16, 64);
-      s += __shfl_xor(s, 32, 64);
-      if (qq == 0) dsum[jj] = s;
-    }
-    wave_fence();
-    double dv[16], rc[16];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double2 t = ((const double2*)dsum)[q]; dv[2 * q] = t.x; dv[2 * q + 1] = t.y;
-      const double2 u = ((const double2*)(Pn + cc * LDY))[q]; rc[2 * q] = u.x; rc[2 * q + 1] = u.y;
-    }
-    double alpha = 0.0, ss = 0.0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) { alpha += rc[j] * (double)(j == cc); ss += dv[j] * (double)(j == cc); }
-    double tau, bt, sc;
-    if (ss == 0.0) { tau = 0.0; bt = alpha; sc = 0.0; }
-    else {
-      bt = -copysign(sqrt(alpha * alpha + ss), alpha);
-      tau = (bt - alpha) / bt;
-      sc = 1.0 / (alpha - bt);
-    }
-    double wv[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) wv[j] = (rc[j] + sc * dv[j]) * (double)(j > cc);
-    for (int r = lane; r < K; r += 64) {
-      double2* row2 = (double2*)(Pn + r * LDY);
-      double rv[16];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) { const double2 t = row2[q]; rv[2 * q] = t.x; rv[2 * q + 1] = t.y; }
-      double x = 0.0;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) x += rv[j] * (double)(j == cc);
-      const double below = (double)(r > cc), piv = (double)(r == cc);
-      const double v = x * sc * below + piv;
-      const double tv = tau * v * (below + piv);
-      const double nx = below * v + piv * bt + (1.0 - below - piv) * x;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const double upd = rv[j] - tv * wv[j];
-        rv[j] = (j == cc) ? nx : upd;
+        for (int q = 0; q < 8; ++q) ((double2*)pb)[q] = make_double2(row0[2 * q], row0[2 * q + 1]);
       }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) row2[q] = make_double2(rv[2 * q], rv[2 * q + 1]);
+      const double ws = reduce_scatter16(pj, lane);
+      if ((lane & 3) == 0) rb[w * 16 + (lane >> 2)] = ws;
     }
-    if (lane == 0) { tau_out[cc] = tau; beta_out[cc] = bt; }
-    wave_fence();
-  }
-}
-
-template <int NRBMAX>
-__device__ __forceinline__ void panel_factor(double* Pn, int K, double* red, double* dsum,
-                                             double* tau_out, double* beta_out, int lane) {
-  panel_factor_wave(Pn, K, red, dsum, tau_out, beta_out, lane);
-}
-
-// T of the compact-WY form I - Y T Y^T of a factored K x 16 panel (one wave): Gram
-// Y^T Y on the matrix cores, then T column by column, row j of T in lane j's registers.
-__device__ __forceinline__ void build_T(const double* Pn, int K, const double* tau, double* gram, double* Tl,
-                        double* Tg, int lane) {
-  const int g = lane >> 4, c = lane & 15;
-  dx4 ga[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
-  for (int rb = 0; rb < (K >> 4); ++rb) {
+    __syncthreads();
+    if (act) {
+      // column totals: lanes 0-15 of each panel wave add the wave partials and pass them
+      // to the whole wave through the wave's own LDS slot (LDS is in order within a wave)
+      double tot = 0.0;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const double y = yval(Pn, 16 * rb + 4 * g + s, c);
-      ga[s] = mfma64(y, y, ga[s]);
-    }
-  }
-  const dx4 gacc = ga[0] + ga[1] + ga[2] + ga[3];
+      for (int ww = 0; ww < QR_PANEL_WAVES; ++ww) tot += rb[ww * 16 + tl];
+      double* wsm = wsum + w * 16;
+      if (lane < 16) wsm[lane] = tot;
+      wave_lds_fence();
+      double P[16], rc[16];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) gram[drow64(g, v) * LDY + c] = gacc[v];
-  wave_fence();
-  if (lane < 16) {
-    const int j = lane;
-    double trow[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const double ti = tau[i];
-      double s = 0.0;
-#pragma unroll
-      for (int l = 0; l < i; ++l) {
-        s += trow[l] * gram[l * LDY + i] * (double)(l >= j);
+      for (int q = 0; q < 8; ++q) {
+        const double2 u = ((const double2*)pb)[q];
+        const double2 z = ((const double2*)wsm)[q];
+        rc[2 * q] = u.x;
+        rc[2 * q + 1] = u.y;
+        P[2 * q] = z.x;
+        P[2 * q + 1] = z.y;
       }
-      trow[i] = (j < i) ? -ti * s : ((j == i) ? ti : 0.0);
-    }
+      const double alpha = rc[cc], ss = P[cc];
+      double tau, bt, sc;
+      if (ss == 0.0) {
+        tau = 0.0; bt = alpha; sc = 0.0;
+      } else {
+        bt = -copysign(sqrt(alpha * alpha + ss), alpha);
+        tau = (bt - alpha) / bt;
+        sc = 1.0 / (alpha - bt);
+      }
+      // g_j = v^T row_j: Y^T v for j < cc, the reflector's product with column j for j > cc
+      double gv[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      Tl[j * LDY + i] = trow[i];
-      Tg[j * 16 + i] = trow[i];
+      for (int j = 0; j < 16; ++j) gv[j] = rc[j] + sc * P[j];
+      double tl_cc = 0.0;
+#pragma unroll
+      for (int m = 0; m < cc; ++m) tl_cc += trow[m] * gv[m];
+      trow[cc] = (tl < cc) ? -tau * tl_cc : (tl == cc ? tau : 0.0);
+      // stored right away (a store cannot be postponed past the next barrier, so the T
+      // recurrence is not sunk to the end of the panel with all its operands kept live)
+      if (t < 16) Tl[t * LDY + cc] = trow[cc];
+      // apply the reflector to this thread's rows
+      {
+        const double a = row0[cc];
+        const double v = (t > cc && t < K) ? sc * a : (t == cc ? 1.0 : 0.0);
+        const double tv = tau * v;
+#pragma unroll
+        for (int j = cc + 1; j < 16; ++j) row0[j] -= tv * gv[j];
+        row0[cc] = (t > cc) ? sc * a : (t == cc ? bt : a);
+      }
+      if (TWO) {
+        const double a = row1[cc];
+        const double tv = tau * sc * a;
+#pragma unroll
+        for (int j = cc + 1; j < 16; ++j) row1[j] -= tv * gv[j];
+        row1[cc] = sc * a;
+      }
+      if (t == 0) { tau_out[cc] = tau; beta_out[cc] = bt; }
     }
   }
-  wave_fence();
 }
 
-// Rows j0.. of column block cb (16 columns), lane (g, c) register v = row g + 4v of each
-// 16-row block; from A through the column permutation on the first panel step.
+// Rows j0.. of one 16-column block, lane (g, c) register v = row g + 4v of each 16-row
+// block; src points at row j0 of this lane's column (rows at stride Np).
 template <int NRBMAX>
-__device__ __forceinline__ void load_block(dx4 (&blk)[NRBMAX], int nrbK, int j0, int cb,
-                                           bool from_a, const double* Ab, const int* iperm,
-                                           const double* Q, int Np, int g, int c) {
+__device__ __forceinline__ void load_block(dx4 (&blk)[NRBMAX], int nrbK, const double* src,
+                                           int Np, int g) {
 #pragma unroll
   for (int rb = 0; rb < NRBMAX; ++rb) {
     if (rb < nrbK) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = j0 + 16 * rb + drow64(g, v);
-        blk[rb][v] = from_a ? Ab[(size_t)row * Np + iperm[16 * cb + c]]
-                            : Q[(size_t)row * Np + 16 * cb + c];
-      }
+      for (int v = 0; v < 4; ++v) blk[rb][v] = src[(16 * rb + drow64(g, v)) * Np];
     }
   }
 }
@@ -334,27 +361,40 @@ __device__ __forceinline__ void apply_panel(dx4 (&blk)[NRBMAX], int nrbK, const 
 }
 
 // One column block of the trailing update, self-contained (load, apply, store) so that
-// no block-sized register array lives across the panel/update branches of the kernel.
-// Rows j0 .. j0+15 go to Q; rows below go to Q, or to the next panel buffer Px when given.
+// no block-sized register array lives across the panel/update phases of the kernel.
+// The block comes from A through the column order on the first panel step (from_a) and
+// from Q after; rows j0 .. j0+15 go back to Q, rows below to Q or, for the next panel, to
+// the LDS buffer Px.
 template <int NRBMAX>
-__device__ __forceinline__ void update_block(int nrbK, int j0, int cb, int from_a,
-                                          const double* __restrict__ Ab,
-                                          const int* __restrict__ iperm, double* __restrict__ Q,
-                                          int Np, const double* Pc, const double* Tc, double* Px,
-                                          int lane) {
+__device__ __forceinline__ void update_block(int nrbK, int j0, int cb, bool from_a,
+                                             const double* __restrict__ Ab,
+                                             const int* __restrict__ iperm, double* __restrict__ Q,
+                                             int Np, const double* Pc, const double* Tc, double* Px,
+                                             int lane) {
   int c = lane & 15, g = lane >> 4;
   __asm__ volatile("" : "+v"(c), "+v"(g));
+  const int col = 16 * cb + c;
+  const double* src = from_a ? Ab + iperm[col] : Q + (size_t)j0 * Np + col;
+  double* dst = Q + (size_t)j0 * Np + col;
   dx4 blk[NRBMAX];
-  load_block<NRBMAX>(blk, nrbK, j0, cb, from_a != 0, Ab, iperm, Q, Np, g, c);
+  load_block<NRBMAX>(blk, nrbK, src, Np, g);
   apply_panel<NRBMAX>(blk, nrbK, Pc, Tc, g, c);
+  if (Px) {
 #pragma unroll
-  for (int rb = 0; rb < NRBMAX; ++rb) {
-    if (rb < nrbK) {
+    for (int v = 0; v < 4; ++v) dst[drow64(g, v) * Np] = blk[0][v];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int lr = 16 * rb + drow64(g, v);
-        if (Px && rb >= 1) Px[(lr - 16) * LDY + c] = blk[rb][v];
-        else Q[(size_t)(j0 + lr) * Np + 16 * cb + c] = blk[rb][v];
+    for (int rb = 1; rb < NRBMAX; ++rb) {
+      if (rb < nrbK) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Px[(16 * (rb - 1) + drow64(g, v)) * LDY + c] = blk[rb][v];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < NRBMAX; ++rb) {
+      if (rb < nrbK) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(16 * rb + drow64(g, v)) * Np] = blk[rb][v];
       }
     }
   }
@@ -375,12 +415,12 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   const int b = blockIdx.x;
   const int NRB = Np >> 4;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  double* Pn0 = lds;                        // [2][Np][LDY] panel buffers
-  double* Tl0 = Pn0 + 2 * Np * LDY;         // [2][16][LDY]
-  double* gram = Tl0 + 2 * 16 * LDY;        // [16][LDY]
-  double* red = gram + 16 * LDY;            // [64][LDY]
-  double* dsum = red + 64 * LDY;            // [16]
-  double* key = dsum + 16;                  // [Np]
+  double* Pn0 = lds;                        // [2][Np][LDY] factored panel / next panel
+  double* Tl = Pn0 + 2 * Np * LDY;          // [16][LDY]
+  double* red = Tl + 16 * LDY;              // [2][4][16]
+  double* prow = red + 2 * QR_PANEL_WAVES * 16;   // [2][16]
+  double* wsum = prow + 32;                 // [4][16]
+  double* key = wsum + QR_PANEL_WAVES * 16; // [Np]
   double* beta = key + Np;                  // [Np]
   double* tauA = beta + Np;                 // [Np]
   double* nt = tauA + Np;                   // [8]
@@ -414,46 +454,62 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   __syncthreads();
   // key now holds log D_prev in pivot order (the V-update factor needs it)
   for (int j = tid; j < Np; j += QR_THREADS) key[j] = logDp ? logDp[(size_t)b * Np + iperm[j]] : 0.0;
-  for (int idx = tid; idx < Np * 16; idx += QR_THREADS) {
-    const int r = idx >> 4, jj = idx & 15;
-    Pn0[r * LDY + jj] = Ab[(size_t)r * Np + iperm[jj]];
+
+  // first panel straight from A through the column order (panel waves only)
+  constexpr bool TWO = NRBMAX > 16;
+  double row0[16], row1[16], trow[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    row0[j] = (tid < 256 && tid < Np) ? Ab[(size_t)tid * Np + iperm[j]] : 0.0;
+    row1[j] = (TWO && tid + 256 < Np) ? Ab[(size_t)(tid + 256) * Np + iperm[j]] : 0.0;
   }
-  __syncthreads();
-  if (w == 0) {
-    panel_factor<NRBMAX>(Pn0, Np, red, dsum, tauA, beta, lane);
-    build_T(Pn0, Np, tauA, gram, Tl0, Tg, lane);
-  }
-  __syncthreads();
 
   for (int p = 0; p < NRB; ++p) {
     const int j0 = 16 * p, K = Np - j0, nrbK = NRB - p;
     double* Pc = Pn0 + (p & 1) * Np * LDY;
     double* Px = Pn0 + ((p + 1) & 1) * Np * LDY;
-    const double* Tc = Tl0 + (p & 1) * 16 * LDY;
-    double* Tx = Tl0 + ((p + 1) & 1) * 16 * LDY;
-    {
-      // wave 0 updates only the next panel's block (into Px); waves 1-7 the rest
-      const int cb0 = (w == 0) ? p + 1 : p + 2 + (w - 1);
-      const int cbs = (w == 0) ? NRB : QR_UPD_WAVES;
-      for (int cb = cb0; cb < NRB; cb += cbs)
-        update_block<NRBMAX>(nrbK, j0, cb, p == 0, Ab, iperm, Q, Np, Pc, Tc,
-                             cb == p + 1 ? Px : nullptr, lane);
-    }
-    if (w == 0) {
-      if (p + 1 < NRB) {
-        wave_fence();
-        panel_factor<NRBMAX>(Px, K - 16, red, dsum, tauA + j0 + 16, beta + j0 + 16, lane);
-        build_T(Px, K - 16, tauA + j0 + 16, gram, Tx, Tg + (size_t)(p + 1) * 256, lane);
-      }
-    } else {
-      // the factored panel p: R rows j0..j0+15 and Householder vectors below
-      for (int idx = tid - 64; idx < K * 16; idx += QR_THREADS - 64) {
-        const int r = idx >> 4, jj = idx & 15;
-        Q[(size_t)(j0 + r) * Np + j0 + jj] = Pc[r * LDY + jj];
+    panel_factor_all<TWO>(row0, row1, trow, tid, K, red, prow, wsum, Tl, tauA + j0, beta + j0);
+    // the factored panel: R rows and Householder vectors to Q, Y to LDS; T (already in
+    // LDS) to Q's T blocks
+    if (tid < 256 && tid < K) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double2 u = make_double2(row0[2 * q], row0[2 * q + 1]);
+        ((double2*)(Pc + tid * LDY))[q] = u;
+        ((double2*)(Q + (size_t)(j0 + tid) * Np + j0))[q] = u;
       }
     }
-    __threadfence_block();
+    if (TWO && tid + 256 < K) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double2 u = make_double2(row1[2 * q], row1[2 * q + 1]);
+        ((double2*)(Pc + (tid + 256) * LDY))[q] = u;
+        ((double2*)(Q + (size_t)(j0 + tid + 256) * Np + j0))[q] = u;
+      }
+    }
+    if (tid < 16) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) Tg[(size_t)p * 256 + tid * 16 + j] = trow[j];
+    }
     __syncthreads();
+    // trailing column blocks; block p+1 (the next panel) goes to Px below its R rows
+    for (int cb = p + 1 + w; cb < NRB; cb += QR_WAVES)
+      update_block<NRBMAX>(nrbK, j0, cb, p == 0, Ab, iperm, Q, Np, Pc, Tl,
+                           cb == p + 1 ? Px : nullptr, lane);
+    __syncthreads();
+    if (p + 1 < NRB) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double2 u = (tid < 256 && tid < K - 16) ? ((const double2*)(Px + tid * LDY))[q]
+                                                      : make_double2(0.0, 0.0);
+        row0[2 * q] = u.x;
+        row0[2 * q + 1] = u.y;
+        const double2 u1 = (TWO && tid + 256 < K - 16) ? ((const double2*)(Px + (tid + 256) * LDY))[q]
+                                                       : make_double2(0.0, 0.0);
+        row1[2 * q] = u1.x;
+        row1[2 * q + 1] = u1.y;
+      }
+    }
   }
 
   // ---- outputs: log D, det Q, perm, and the V-update factor in the upper triangle
@@ -554,7 +610,7 @@ template <int NRBMAX>
 hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride, int nparts,
                   const double* logDp, double* QRW, double* Tb, int* perm, double* logD,
                   int* qsign, int* status, int nb, int Np, hipStream_t st) {
-  const size_t lds = (size_t)(2 * Np * LDY + 3 * 16 * LDY + 64 * LDY + 16 + 3 * Np + 8) *
+  const size_t lds = (size_t)(2 * Np * LDY + 16 * LDY + 3 * QR_PANEL_WAVES * 16 + 32 + 3 * Np + 8) *
                          sizeof(double) + (size_t)(Np + 2) * sizeof(int);
   hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(QR_THREADS), lds, st, A, astride, norm2, nstride, nparts,
                      logDp, QRW, Tb, perm, logD, qsign, status, Np);
