@@ -28,7 +28,9 @@
  *   - Argument validation is synchronous: a nonzero return means nothing was enqueued,
  *     and slmc_last_error() (thread-local) explains it.  No C++ exception crosses the ABI.
  *   - Per-item numerical failures (non-finite input or output) are reported in status[b]
- *     with logdet[b] = NaN; the call itself still returns SLMC_OK.
+ *     with logdet[b] = NaN; the call itself still returns SLMC_OK.  status[b] =
+ *     SLMC_E_DEVICE marks an item whose QR workgroup hit the spin limit of its internal
+ *     wait (a device fault, not expected in normal operation).
  *   - Doubles are IEEE binary64; x, G are row-major and packed per item.
  */
 #ifndef SLMC_H
@@ -87,10 +89,10 @@ typedef struct {
 } slmc_options;
 
 /* Scheduling flags.  By default, when a model has more than one stabilization block, the
- * segment products run on a stream the library owns (one per device, default priority,
- * created on first use, destroyed by slmc_cache_clear), forked from and joined back to
- * the caller's stream with events, so that the sequential stabilization chain overlaps
- * the remaining segment products.  Results are identical either way; calls from several
+ * segment products and the V updates run on two streams the library owns (per device,
+ * default priority, created on first use, destroyed by slmc_cache_clear), forked from and
+ * joined back to the caller's stream with events, so that the sequential QR chain
+ * overlaps the remaining segment products and the V updates.  Results are identical either way; calls from several
  * host threads on one device serialize while they enqueue. */
 enum slmc_flags {
   SLMC_FLAG_SERIAL = 1  /* run every kernel on the caller's stream, in order            */
@@ -139,7 +141,7 @@ size_t slmc_workspace_bytes(const slmc_model* models, int32_t n_models,
  *   models[n_models]  host;  batch, opt host;
  *   x       device, fields (layout above);
  *   logdet  device [n_items] double;  sign device [n_items] int8 (+1/-1);
- *   status  device [n_items] int32 (SLMC_OK or SLMC_E_NONFINITE);
+ *   status  device [n_items] int32 (SLMC_OK, SLMC_E_NONFINITE, or SLMC_E_DEVICE);
  *   ws      device workspace of ws_bytes >= slmc_workspace_bytes(). */
 int slmc_logdet(const slmc_model* models, int32_t n_models, const slmc_batch* batch,
                 const slmc_options* opt, const double* x, double* logdet, int8_t* sign,

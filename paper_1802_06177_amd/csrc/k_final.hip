@@ -232,7 +232,11 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
     double ld = lb + lx - (double)(Np - N) * LN2;
     const int sgn = qsign[b] * (((nn + cnt[0]) & 1) ? -1 : 1);
     int stt = 0;
-    if (st_in[b] != 0 || cnt[1] != 0 || !isfinite(ld)) { stt = 5; ld = __longlong_as_double(0x7ff8000000000000LL); }
+    if (st_in[b] != 0 || cnt[1] != 0 || !isfinite(ld)) {
+      // bit 3 of the QR status: a bounded wait inside the QR ran out (device fault)
+      stt = (st_in[b] & 8) ? 4 : 5;
+      ld = __longlong_as_double(0x7ff8000000000000LL);
+    }
     const int item = item_of ? item_of[b] : b;
     logdet_out[item] = ld;
     sign_out[item] = (int8_t)sgn;

@@ -148,8 +148,9 @@ __global__ __launch_bounds__(256) void wy_apply_k(const double* __restrict__ Bsr
 
 // Workgroup of 8 waves per item.  Each 16-column panel is factored by waves 0-3 (one per
 // SIMD), every thread holding one or two rows of the panel in registers; the column
-// steps exchange their 16 sums through a wave reduce-scatter and one barrier each.  The
-// trailing column blocks are then updated by all 8 waves on the matrix cores.
+// steps exchange their 16 sums through a wave reduce-scatter and an LDS-counter sync of
+// those 4 waves.  Meanwhile waves 4-7 apply the previous panel to the trailing column
+// blocks on the matrix cores (look-ahead by one panel); one workgroup barrier per panel.
 constexpr int QR_THREADS = 512;
 constexpr int QR_WAVES = QR_THREADS / 64;
 
@@ -222,26 +223,45 @@ __device__ __forceinline__ void wave_lds_fence() {
 // the remaining columns, and j < cc (the earlier Householder vectors) gives Y^T v, from
 // which column cc of the compact-WY factor T follows (T_cc,cc = tau,
 // T_l,cc = -tau sum_m T_l,m (Y^T v)_m); lane l & 15 keeps row l & 15 of T in trow and
-// threads 0-15 store it to Tl.  The sums go through a wave reduce-scatter and one
-// workgroup barrier per column (waves 4-7 only take part in the barriers); red [2][4][16]
-// and prow [2][16] are double-buffered by column parity, wsum [4][16] is a per-wave
-// broadcast slot.
+// threads 0-15 store it to Tl.  The sums go through a wave reduce-scatter and one sync of
+// the 4 panel waves per column (panel_sync); red [2][4][16] and prow [2][16] are
+// double-buffered by column parity, wsum [4][16] is a per-wave broadcast slot.
 constexpr int QR_PANEL_WAVES = 4;
+constexpr int QR_SPIN_LIMIT = 1 << 16;   // about 2 ms of s_sleep(1) polls
+
+// Arrive-and-wait among the 4 panel waves through a monotonically increasing LDS counter
+// (the other waves keep working meanwhile).  The release on arrival orders the wave's
+// earlier LDS writes before the count, the acquire on the wait orders later reads after
+// it.  The wait is bounded: past the spin limit it sets *timeout and goes on, so every
+// wave always reaches the end of the kernel.
+__device__ __forceinline__ void panel_sync(int* cnt, int& epoch, int lane, int* timeout) {
+  ++epoch;
+  if (lane == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int target = QR_PANEL_WAVES * epoch;
+  int spins = 0;
+  while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > QR_SPIN_LIMIT) {
+      *timeout = 1;
+      break;
+    }
+  }
+}
 
 template <bool TWO>
 __device__ __forceinline__ void panel_factor_all(double (&row0)[16], double (&row1)[16],
                                                  double (&trow)[16], int t, int K, double* red,
                                                  double* prow, double* wsum, double* Tl,
-                                                 double* tau_out, double* beta_out) {
+                                                 double* tau_out, double* beta_out, int* cnt,
+                                                 int& epoch, int* timeout) {
   const int lane = t & 63, w = t >> 6, tl = lane & 15;
-  const bool act = w < QR_PANEL_WAVES;
 #pragma unroll
   for (int j = 0; j < 16; ++j) trow[j] = 0.0;
 #pragma unroll
   for (int cc = 0; cc < 16; ++cc) {
     double* rb = red + (cc & 1) * QR_PANEL_WAVES * 16;
     double* pb = prow + (cc & 1) * 16;
-    if (act) {
+    {
       const double am0 = row0[cc] * (double)(t > cc && t < K);
       const double am1 = TWO ? row1[cc] * (double)(t + 256 < K) : 0.0;
       double pj[16];
@@ -254,8 +274,8 @@ __device__ __forceinline__ void panel_factor_all(double (&row0)[16], double (&ro
       const double ws = reduce_scatter16(pj, lane);
       if ((lane & 3) == 0) rb[w * 16 + (lane >> 2)] = ws;
     }
-    __syncthreads();
-    if (act) {
+    panel_sync(cnt, epoch, lane, timeout);
+    {
       // column totals: lanes 0-15 of each panel wave add the wave partials and pass them
       // to the whole wave through the wave's own LDS slot (LDS is in order within a wave)
       double tot = 0.0;
@@ -287,11 +307,12 @@ __device__ __forceinline__ void panel_factor_all(double (&row0)[16], double (&ro
       double gv[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) gv[j] = rc[j] + sc * P[j];
-      double tl_cc = 0.0;
+      double tp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int m = 0; m < cc; ++m) tl_cc += trow[m] * gv[m];
+      for (int m = 0; m < cc; ++m) tp[m & 3] += trow[m] * gv[m];
+      const double tl_cc = (tp[0] + tp[1]) + (tp[2] + tp[3]);
       trow[cc] = (tl < cc) ? -tau * tl_cc : (tl == cc ? tau : 0.0);
-      // stored right away (a store cannot be postponed past the next barrier, so the T
+      // stored right away (a store cannot be postponed past the next sync, so the T
       // recurrence is not sunk to the end of the panel with all its operands kept live)
       if (t < 16) Tl[t * LDY + cc] = trow[cc];
       // apply the reflector to this thread's rows
@@ -415,9 +436,9 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   const int b = blockIdx.x;
   const int NRB = Np >> 4;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  double* Pn0 = lds;                        // [2][Np][LDY] factored panel / next panel
-  double* Tl = Pn0 + 2 * Np * LDY;          // [16][LDY]
-  double* red = Tl + 16 * LDY;              // [2][4][16]
+  double* Pn0 = lds;                        // [2][Np][LDY] Y of panel p / panel p+1
+  double* Tl0 = Pn0 + 2 * Np * LDY;         // [2][16][LDY] T of panel p / panel p+1
+  double* red = Tl0 + 2 * 16 * LDY;         // [2][4][16]
   double* prow = red + 2 * QR_PANEL_WAVES * 16;   // [2][16]
   double* wsum = prow + 32;                 // [4][16]
   double* key = wsum + QR_PANEL_WAVES * 16; // [Np]
@@ -425,12 +446,13 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   double* tauA = beta + Np;                 // [Np]
   double* nt = tauA + Np;                   // [8]
   int* iperm = (int*)(nt + 8);              // [Np]
-  int* flag = iperm + Np;                   // [1]
+  int* flag = iperm + Np;                   // [2]: non-finite input, sync timeout
+  int* cnt = flag + 2;                      // [1] panel-wave sync counter
 
   const double* Ab = A + (size_t)b * astride;
   double* Q = QRW + (size_t)b * Np * Np;
   double* Tg = Tb + (size_t)b * NRB * 256;
-  if (tid == 0) flag[0] = 0;
+  if (tid == 0) { flag[0] = 0; flag[1] = 0; cnt[0] = 0; }
   __syncthreads();
 
   // ---- pre-pivoting: order columns by log ||A e_j|| + log D_prev[j], descending
@@ -455,61 +477,78 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   // key now holds log D_prev in pivot order (the V-update factor needs it)
   for (int j = tid; j < Np; j += QR_THREADS) key[j] = logDp ? logDp[(size_t)b * Np + iperm[j]] : 0.0;
 
-  // first panel straight from A through the column order (panel waves only)
+  // Panel waves (0-3) factor panel 0, then for every step p update column block p+1 with
+  // panel p and factor it as panel p+1; waves 4-7 meanwhile apply panel p to the column
+  // blocks p+2 ..  One workgroup barrier per step publishes panel p+1.
   constexpr bool TWO = NRBMAX > 16;
+  const bool panel_wave = w < QR_PANEL_WAVES;
+  int epoch = 0;
   double row0[16], row1[16], trow[16];
+  if (panel_wave) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    row0[j] = (tid < 256 && tid < Np) ? Ab[(size_t)tid * Np + iperm[j]] : 0.0;
-    row1[j] = (TWO && tid + 256 < Np) ? Ab[(size_t)(tid + 256) * Np + iperm[j]] : 0.0;
+    for (int j = 0; j < 16; ++j) {
+      row0[j] = (tid < Np) ? Ab[(size_t)tid * Np + iperm[j]] : 0.0;
+      row1[j] = (TWO && tid + 256 < Np) ? Ab[(size_t)(tid + 256) * Np + iperm[j]] : 0.0;
+    }
   }
-
-  for (int p = 0; p < NRB; ++p) {
-    const int j0 = 16 * p, K = Np - j0, nrbK = NRB - p;
-    double* Pc = Pn0 + (p & 1) * Np * LDY;
-    double* Px = Pn0 + ((p + 1) & 1) * Np * LDY;
-    panel_factor_all<TWO>(row0, row1, trow, tid, K, red, prow, wsum, Tl, tauA + j0, beta + j0);
-    // the factored panel: R rows and Householder vectors to Q, Y to LDS; T (already in
-    // LDS) to Q's T blocks
-    if (tid < 256 && tid < K) {
+  for (int p = -1; p < NRB - 1; ++p) {
+    // this step factors panel q = p + 1; panel p (if any) is published in buffer p & 1
+    const int q = p + 1, jq = 16 * q, Kq = Np - jq;
+    double* Yq = Pn0 + (q & 1) * Np * LDY;
+    double* Tq = Tl0 + (q & 1) * 16 * LDY;
+    if (panel_wave) {
+      if (p >= 0) {
+        // column block q, updated with panel p, lands in Yq (rows below its R part)
+        const int j0 = 16 * p;
+        if (w == 0)
+          update_block<NRBMAX>(NRB - p, j0, q, p == 0, Ab, iperm, Q, Np, Pn0 + (p & 1) * Np * LDY,
+                               Tl0 + (p & 1) * 16 * LDY, Yq, lane);
+        panel_sync(cnt, epoch, lane, flag + 1);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double2 u = make_double2(row0[2 * q], row0[2 * q + 1]);
-        ((double2*)(Pc + tid * LDY))[q] = u;
-        ((double2*)(Q + (size_t)(j0 + tid) * Np + j0))[q] = u;
+        for (int h = 0; h < 8; ++h) {
+          const double2 u = (tid < Kq) ? ((const double2*)(Yq + tid * LDY))[h] : make_double2(0.0, 0.0);
+          row0[2 * h] = u.x;
+          row0[2 * h + 1] = u.y;
+          const double2 u1 = (TWO && tid + 256 < Kq) ? ((const double2*)(Yq + (tid + 256) * LDY))[h]
+                                                     : make_double2(0.0, 0.0);
+          row1[2 * h] = u1.x;
+          row1[2 * h + 1] = u1.y;
+        }
+        // every panel wave has its rows before any overwrites them with the factored panel
+        panel_sync(cnt, epoch, lane, flag + 1);
       }
-    }
-    if (TWO && tid + 256 < K) {
+      panel_factor_all<TWO>(row0, row1, trow, tid, Kq, red, prow, wsum, Tq, tauA + jq, beta + jq,
+                            cnt, epoch, flag + 1);
+      // the factored panel: R rows and Householder vectors to Q, Y to LDS; T (already in
+      // LDS) to Q's T blocks
+      if (tid < Kq) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double2 u = make_double2(row1[2 * q], row1[2 * q + 1]);
-        ((double2*)(Pc + (tid + 256) * LDY))[q] = u;
-        ((double2*)(Q + (size_t)(j0 + tid + 256) * Np + j0))[q] = u;
+        for (int h = 0; h < 8; ++h) {
+          const double2 u = make_double2(row0[2 * h], row0[2 * h + 1]);
+          ((double2*)(Yq + tid * LDY))[h] = u;
+          ((double2*)(Q + (size_t)(jq + tid) * Np + jq))[h] = u;
+        }
       }
-    }
-    if (tid < 16) {
+      if (TWO && tid + 256 < Kq) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) Tg[(size_t)p * 256 + tid * 16 + j] = trow[j];
+        for (int h = 0; h < 8; ++h) {
+          const double2 u = make_double2(row1[2 * h], row1[2 * h + 1]);
+          ((double2*)(Yq + (tid + 256) * LDY))[h] = u;
+          ((double2*)(Q + (size_t)(jq + tid + 256) * Np + jq))[h] = u;
+        }
+      }
+      if (tid < 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) Tg[(size_t)q * 256 + tid * 16 + j] = trow[j];
+      }
+    } else if (p >= 0) {
+      // trailing column blocks q+1 .. with panel p
+      for (int cb = q + 1 + (w - QR_PANEL_WAVES); cb < NRB; cb += QR_THREADS / 64 - QR_PANEL_WAVES)
+        update_block<NRBMAX>(NRB - p, 16 * p, cb, p == 0, Ab, iperm, Q, Np, Pn0 + (p & 1) * Np * LDY,
+                             Tl0 + (p & 1) * 16 * LDY, nullptr, lane);
     }
+    __threadfence_block();
     __syncthreads();
-    // trailing column blocks; block p+1 (the next panel) goes to Px below its R rows
-    for (int cb = p + 1 + w; cb < NRB; cb += QR_WAVES)
-      update_block<NRBMAX>(nrbK, j0, cb, p == 0, Ab, iperm, Q, Np, Pc, Tl,
-                           cb == p + 1 ? Px : nullptr, lane);
-    __syncthreads();
-    if (p + 1 < NRB) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double2 u = (tid < 256 && tid < K - 16) ? ((const double2*)(Px + tid * LDY))[q]
-                                                      : make_double2(0.0, 0.0);
-        row0[2 * q] = u.x;
-        row0[2 * q + 1] = u.y;
-        const double2 u1 = (TWO && tid + 256 < K - 16) ? ((const double2*)(Px + (tid + 256) * LDY))[q]
-                                                       : make_double2(0.0, 0.0);
-        row1[2 * q] = u1.x;
-        row1[2 * q + 1] = u1.y;
-      }
-    }
   }
 
   // ---- outputs: log D, det Q, perm, and the V-update factor in the upper triangle
@@ -527,6 +566,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
     for (int k = 0; k < QR_THREADS / 64; ++k) tot += (int)nt[k];
     qsign[b] = (tot & 1) ? -1 : 1;
     if (flag[0]) status[b] |= 1;
+    if (flag[1]) status[b] |= 8;
   }
   for (int idx = tid; idx < Np * Np; idx += QR_THREADS) {
     const int i = idx / Np, j = idx - i * Np;
@@ -610,8 +650,8 @@ template <int NRBMAX>
 hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride, int nparts,
                   const double* logDp, double* QRW, double* Tb, int* perm, double* logD,
                   int* qsign, int* status, int nb, int Np, hipStream_t st) {
-  const size_t lds = (size_t)(2 * Np * LDY + 16 * LDY + 3 * QR_PANEL_WAVES * 16 + 32 + 3 * Np + 8) *
-                         sizeof(double) + (size_t)(Np + 2) * sizeof(int);
+  const size_t lds = (size_t)(2 * Np * LDY + 2 * 16 * LDY + 3 * QR_PANEL_WAVES * 16 + 32 + 3 * Np + 8) *
+                         sizeof(double) + (size_t)(Np + 4) * sizeof(int);
   hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(QR_THREADS), lds, st, A, astride, norm2, nstride, nparts,
                      logDp, QRW, Tb, perm, logD, qsign, status, Np);
   return hipGetLastError();

@@ -51,11 +51,12 @@ struct ProfScope {
 
 thread_local std::string g_err;
 
-// Library-owned side stream per device (default priority) and the events that order it
-// against the caller's stream.  g_side_mu is held while a call enqueues on it, so the
-// events are never re-recorded before the waits on them are enqueued.
+// Library-owned side streams per device (default priority) and the events that order
+// them against the caller's stream: s runs the segment products, s2 the V updates.
+// g_side_mu is held while a call enqueues on them, so the events are never re-recorded
+// before the waits on them are enqueued.
 struct SideStream {
-  hipStream_t s = nullptr;
+  hipStream_t s = nullptr, s2 = nullptr;
   std::vector<hipEvent_t> ev;
 };
 std::mutex g_side_mu;
@@ -84,6 +85,7 @@ int side_stream_locked(int nev, SideStream** out) {
   HIPCHK(hipGetDevice(&dev));
   SideStream& ss = g_side[dev];
   if (!ss.s) HIPCHK(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+  if (!ss.s2) HIPCHK(hipStreamCreateWithFlags(&ss.s2, hipStreamNonBlocking));
   while ((int)ss.ev.size() < nev) {
     hipEvent_t e = nullptr;
     HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -226,8 +228,8 @@ struct Arena {
 };
 
 struct GroupBufs {
-  double *S, *snorm, *A, *npart, *QRW, *Tb, *logD0, *logD1, *V0, *V1, *DI;
-  int *perm, *qsign, *status, *prow, *item_of;
+  double *S, *snorm, *A, *npart, *QRW[2], *Tb[2], *logD0, *logD1, *V0, *V1, *DI;
+  int *perm[2], *qsign, *status, *prow, *item_of;
   int64_t *xoff, *goff;
 };
 
@@ -237,14 +239,16 @@ void carve(Arena& a, int nb, int Np, int m, GroupBufs& g) {
   g.snorm = a.take<double>((size_t)nb * m * Np);
   g.A = a.take<double>((size_t)nb * n2);
   g.npart = a.take<double>((size_t)nb * Np * (Np / 16));
-  g.QRW = a.take<double>((size_t)nb * n2);
-  g.Tb = a.take<double>((size_t)nb * Np * 16);
+  for (int h = 0; h < 2; ++h) {
+    g.QRW[h] = a.take<double>((size_t)nb * n2);
+    g.Tb[h] = a.take<double>((size_t)nb * Np * 16);
+    g.perm[h] = a.take<int>((size_t)nb * Np);
+  }
   g.logD0 = a.take<double>((size_t)nb * Np);
   g.logD1 = a.take<double>((size_t)nb * Np);
   g.V0 = a.take<double>((size_t)nb * n2);
   g.V1 = a.take<double>((size_t)nb * n2);
   g.DI = a.take<double>((size_t)nb * Np * 32);
-  g.perm = a.take<int>((size_t)nb * Np);
   g.qsign = a.take<int>(nb);
   g.status = a.take<int>(nb);
   g.prow = a.take<int>((size_t)nb * Np);
@@ -348,10 +352,11 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   SideStream* ss = nullptr;
   if (overlap) {
     side_lock.lock();
-    rc = side_stream_locked(mseg + 1, &ss);
+    rc = side_stream_locked(3 * mseg + 1, &ss);
     if (rc) return rc;
     HIPCHK(hipEventRecord(ss->ev[mseg], st));
     HIPCHK(hipStreamWaitEvent(ss->s, ss->ev[mseg], 0));
+    HIPCHK(hipStreamWaitEvent(ss->s2, ss->ev[mseg], 0));
     for (int k = 0; k < mseg; ++k) {
       ProfScope ps(0, ss->s);
       HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, f, nb, N,
@@ -366,8 +371,16 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   // a3: stabilized accumulation
   double* logD[2] = {w.logD0, w.logD1};
   double* Vb[2] = {w.V0, w.V1};
+  // events: ev[k] segment k done (s), ev[mseg+1+k] QR k done (st), ev[2 mseg+1+k] V update k
+  // done (s2).  QR k+2 reuses the buffers that V update k reads, so it waits for it.
+  hipEvent_t* ev_qr = overlap ? &ss->ev[mseg + 1] : nullptr;
+  hipEvent_t* ev_vu = overlap ? &ss->ev[2 * mseg + 1] : nullptr;
   for (int k = 0; k < mseg; ++k) {
+    double* QRWk = w.QRW[k & 1];
+    double* Tbk = w.Tb[k & 1];
+    int* permk = w.perm[k & 1];
     if (overlap) HIPCHK(hipStreamWaitEvent(st, ss->ev[k], 0));
+    if (overlap && k >= 2) HIPCHK(hipStreamWaitEvent(st, ev_vu[k - 2], 0));
     const double* Ain;
     int64_t astride, nstride;
     const double* nrm;
@@ -381,8 +394,8 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
       nparts = 1;
     } else {
       ProfScope ps(1, st);
-      HIPCHK(launch_wy_apply(w.S + (size_t)k * n2, (int64_t)mseg * n2, w.QRW, w.Tb, w.A, w.npart, 0,
-                             nb, Np, st));
+      HIPCHK(launch_wy_apply(w.S + (size_t)k * n2, (int64_t)mseg * n2, w.QRW[(k + 1) & 1],
+                             w.Tb[(k + 1) & 1], w.A, w.npart, 0, nb, Np, st));
       Ain = w.A;
       astride = (int64_t)n2;
       nrm = w.npart;
@@ -391,19 +404,31 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     }
     {
     ProfScope ps(2, st);
-    HIPCHK(launch_qr(Ain, astride, nrm, nstride, nparts, k == 0 ? nullptr : logD[(k + 1) & 1], w.QRW, w.Tb,
-                     w.perm, logD[k & 1], w.qsign, w.status, nb, Np, st));
+    HIPCHK(launch_qr(Ain, astride, nrm, nstride, nparts, k == 0 ? nullptr : logD[(k + 1) & 1], QRWk,
+                     Tbk, permk, logD[k & 1], w.qsign, w.status, nb, Np, st));
     }
-    ProfScope ps(3, st);
-    HIPCHK(launch_vupd(w.QRW, w.perm, k == 0 ? nullptr : Vb[(k + 1) & 1], Vb[k & 1], nb, Np, st));
+    // V_k = F P^T V_{k-1} is needed only by the recombination: off the chain's critical
+    // path on s2 when overlapping
+    hipStream_t sv = overlap ? ss->s2 : st;
+    if (overlap) {
+      HIPCHK(hipEventRecord(ev_qr[k], st));
+      HIPCHK(hipStreamWaitEvent(sv, ev_qr[k], 0));
+    }
+    {
+    ProfScope ps(3, sv);
+    HIPCHK(launch_vupd(QRWk, permk, k == 0 ? nullptr : Vb[(k + 1) & 1], Vb[k & 1], nb, Np, sv));
+    }
+    if (overlap) HIPCHK(hipEventRecord(ev_vu[k], sv));
   }
+  if (overlap) HIPCHK(hipStreamWaitEvent(st, ev_vu[mseg - 1], 0));
   const double* logDf = logD[(mseg - 1) & 1];
   const double* Vf = Vb[(mseg - 1) & 1];
   double* Gint = Vb[mseg & 1];   // the other V buffer is free now
   double* QT = w.A;
   double* LU = w.S;
   // U^T = Q_m^T explicitly, then a4: recombination
-  HIPCHK(launch_wy_apply(nullptr, 0, w.QRW, w.Tb, QT, nullptr, 1, nb, Np, st));
+  HIPCHK(launch_wy_apply(nullptr, 0, w.QRW[(mseg - 1) & 1], w.Tb[(mseg - 1) & 1], QT, nullptr, 1,
+                         nb, Np, st));
   {
   ProfScope ps(4, st);
   HIPCHK(launch_lu(QT, Vf, logDf, w.qsign, w.status, LU, w.prow, w.DI, item_of, ld_out, sg_out,
@@ -416,7 +441,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
                            goff, nb, N, Np, st));
     if (resid) {
       // a5: R = Db^-1 U^T - X G, G += X^-1 R
-      double* R = w.QRW;
+      double* R = w.QRW[mseg & 1];   // the other QR buffer is free now
       ProfScope pr(6, st);
       HIPCHK(launch_residual(QT, Vf, logDf, Gint, R, nb, Np, st));
       HIPCHK(launch_lu_solve(1, QT, logDf, R, LU, w.prow, w.DI, Gint, 1, g_out, goff, nb, N, Np, st));
@@ -685,8 +710,10 @@ void slmc_cache_clear(void) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(kv.first);
     if (kv.second.s) (void)hipStreamSynchronize(kv.second.s);
+    if (kv.second.s2) (void)hipStreamSynchronize(kv.second.s2);
     for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
     if (kv.second.s) (void)hipStreamDestroy(kv.second.s);
+    if (kv.second.s2) (void)hipStreamDestroy(kv.second.s2);
     (void)hipSetDevice(cur);
   }
   g_side.clear();
