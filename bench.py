@@ -25,7 +25,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense matrix-core TFLOP/s, MI355X
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "i8": 5000.0}   # dense matrix-core T(FL)OP/s, MI355X
 
 
 def main():
@@ -33,7 +33,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6", "int8x5"])
     ap.add_argument("--acc-chunk", type=int, default=0)
     ap.add_argument("--residual", type=int, default=1)
     ap.add_argument("--chains", type=int, default=128)
@@ -114,7 +114,7 @@ def main():
         "lu_solve": 2.0 * N ** 3 * B,
         "residual": 2.0 * N ** 3 * B,
     }
-    prec_dtype = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}[args.precision]
+    prec_dtype = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "int8x5": "i8"}[args.precision]
     kern_dtype = prec_dtype if dom == "seg_chain" else "f64"
     achieved = flops.get(dom, 0.0) / (dom_ms / dom_n / 1e3) / 1e12 if dom_n else 0.0
     roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),

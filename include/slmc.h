@@ -65,7 +65,13 @@ enum slmc_precision {
   SLMC_BF16X3 = 2,     /* two-piece bf16 split (hi + lo), three products, FP32 sums
                           promoted to FP64 per 32-wide k-block                        */
   SLMC_BF16X6 = 3,     /* three-piece bf16 split, six products, as above              */
-  SLMC_FP32_PLAIN = 4  /* SLMC_FP32 without the compensation of E (error studies)     */
+  SLMC_FP32_PLAIN = 4, /* SLMC_FP32 without the compensation of E (error studies)     */
+  SLMC_INT8X5 = 5      /* E and the panel each split into 5 int8 slices of 7 bits
+                          (power-of-two scale per row of E / column of the panel,
+                          round to nearest); the 15 slice products with exponent sum
+                          <= 6 accumulate exactly in int32 on the int8 matrix cores and
+                          are recombined in FP64 (about 2^-36 relative to the row and
+                          column maxima per product)                                   */
 };
 
 /* One lattice model.  N = Lx*Ly sites, Ltau slices of width dtau (beta = Ltau*dtau),

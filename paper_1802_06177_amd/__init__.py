@@ -14,7 +14,8 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
-from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLAIN, SlmcError,
+from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLAIN, SLMC_INT8X5,
+                   SlmcError,
                    Model, Options, Batch, Eff)
 
 __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
@@ -22,7 +23,7 @@ __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet",
            "SlmcError", "version"]
 
 PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6,
-              "fp32plain": SLMC_FP32_PLAIN}
+              "fp32plain": SLMC_FP32_PLAIN, "int8x5": SLMC_INT8X5}
 
 
 def version():

@@ -1,0 +1,335 @@
+// Segment products (SM Eq. S2: B_l = e^{-dtau K} diag(e^{-dtau lam x_l})) on the int8
+// matrix cores with exact integer accumulation.
+//
+// Every product E P is split into integer pieces: E is scaled per row by a power of two
+// 2^{ea_i} (|E_ik 2^{-ea_i}| < 1/2) and cut into 5 slices of 7 bits each, rounded to
+// nearest (|slice| <= 64), so E = 2^{ea} sum_p A_p 2^{-7p} up to 2^{-36} of the row
+// maximum; the panel P is cut the same way per column.  The products A_p B_q with
+// p + q <= 6 (15 of the 25) are accumulated in int32 on v_mfma_i32_16x16x64_i8, exactly
+// (|entries| <= 64 and K <= 448 keep every sum below 2^31), one accumulator per p + q,
+// and recombined in FP64.  Relative to the row/column maxima the result carries an error
+// of about 2^-36 per product, well below the FP32 matrix cores' rounding, and it is not
+// biased (round-to-nearest slices).
+//
+// Workgroup (8 waves) = one (item, segment, 32- or 16-column panel), as in the FP64 kernel: the
+// panel's int8 slices live in LDS, the E slices stream from L2 as the A operand, and the
+// phonon factors of the next slice are applied when the FP64 result is recombined.  The
+// values are never stored in FP64 between slices: the new column scales come from a
+// column-maximum pass over the accumulators, then the slices are cut from the same
+// accumulators.
+#include "common.h"
+#include "launch.h"
+#include "chain_util.h"
+
+namespace slmc {
+
+namespace {
+
+typedef int ix4 __attribute__((ext_vector_type(4)));
+
+constexpr int NSL = 5;          // slices per operand
+constexpr int NDIAG = NSL;      // accumulators: p + q = 0 .. 4 (0-based slices)
+
+__device__ __forceinline__ ix4 mfma_i8(ix4 a, ix4 b, ix4 c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
+// FP64 value of one output element from its 5 diagonal sums (2^-14 .. 2^-42 weights).
+__device__ __forceinline__ double recombine5(int d0, int d1, int d2, int d3, int d4) {
+  double s = (double)d4 * 0x1p-42;
+  s += (double)d3 * 0x1p-35;
+  s += (double)d2 * 0x1p-28;
+  s += (double)d1 * 0x1p-21;
+  s += (double)d0 * 0x1p-14;
+  return s;
+}
+
+// 2^{e+1} with |m| < 2^e (frexp convention), so |value / scale| < 1/2; 1 for zero.
+__device__ __forceinline__ double pow2_above(double m) {
+  if (!(m > 0.0)) return 1.0;
+  int e;
+  (void)frexp(m, &e);
+  return ldexp(1.0, e + 1);
+}
+
+// 5 round-to-nearest 7-bit slices of y (|y| < 64), one byte each, packed per slice into
+// the byte `shift` of out[p].
+__device__ __forceinline__ void slice5(double y, int shift, uint32_t (&out)[NSL]) {
+#pragma unroll
+  for (int p = 0; p < NSL; ++p) {
+    const double a = rint(y);
+    y = (y - a) * 128.0;
+    out[p] |= ((uint32_t)((int)a) & 0xFFu) << shift;
+  }
+}
+
+constexpr int I8_WAVES = 8;   // two waves per SIMD: one computes while the other waits
+
+template <int RB, int CB>
+__global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __restrict__ Eq,
+                                                    const double* __restrict__ Esc,
+                                                    const double* __restrict__ E64, FieldRef f,
+                                                    int nb, int N, int Np, int Npk, int Ltau,
+                                                    int n_s, int m, int k0, int kc, double ldl,
+                                                    double* __restrict__ S,
+                                                    double* __restrict__ snorm) {
+  constexpr int W = 16 * CB;
+  extern __shared__ double lds[];
+  const int LDK = Npk + 16;                     // bytes per slice column (bank spread)
+  double* vbuf = lds;                           // [2][Np]
+  double* red = vbuf + 2 * Np;                  // [I8_WAVES][W]
+  int8_t* Bsl = (int8_t*)(red + I8_WAVES * W);  // [NSL][W][LDK]
+  const int npan = Np / W;
+  const int id = xcd_remap(blockIdx.x, nb * kc * npan);
+  if (id < 0) return;
+  const int pan = id % npan, k = k0 + (id / npan) % kc, b = id / (npan * kc);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+  const int NRB = Np >> 4, c0 = pan * W;
+  const double* xb = field_of(f, b);
+  const int l0 = k * n_s, len = min(n_s, Ltau - l0);
+  double* Sout = S + ((size_t)b * m + k) * Np * Np;
+  double* nout = snorm + ((size_t)b * m + k) * Np;
+
+  fill_v(vbuf, xb, l0, N, Np, ldl);
+  if (len > 1) fill_v(vbuf + Np, xb, l0 + 1, N, Np, ldl);
+  // zero the k padding of the slices once (rows Np .. Npk-1 are never written later)
+  for (int idx = tid; idx < NSL * W * (Npk - Np); idx += 64 * I8_WAVES) {
+    const int pc = idx / (Npk - Np), r = Np + idx - pc * (Npk - Np);
+    Bsl[pc * LDK + r] = 0;
+  }
+  __syncthreads();
+
+  if (len == 1) {
+    // S_k = E diag(v_l0) on this panel's columns, and its column norms
+    double s2[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) s2[cb] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int rb = w + I8_WAVES * r;
+      if (rb < NRB) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 16 * rb + drow32(g, i), col = c0 + 16 * cb + c;
+            const double val = E64[(size_t)row * Np + col] * vbuf[col];
+            Sout[(size_t)row * Np + col] = val;
+            s2[cb] += val * val;
+          }
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      double sv = s2[cb];
+      sv += __shfl_xor(sv, 16, 64);
+      sv += __shfl_xor(sv, 32, 64);
+      if (g == 0) red[w * W + 16 * cb + c] = sv;
+    }
+    __syncthreads();
+    if (tid < W) {
+      double t2 = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < I8_WAVES; ++ww) t2 += red[ww * W + tid];
+      nout[c0 + tid] = t2;
+    }
+    return;
+  }
+
+  ix4 acc[RB][CB][NDIAG];
+  double vals[RB][CB][4];   // the panel about to be sliced, in the accumulator layout
+  double fcur[CB];          // column scales 2^f of the panel in Bsl (this lane's columns)
+
+  // Cut the panel in vals into slices: column maxima over the waves, new scales, then
+  // the bytes.  Ends with a barrier (slices ready).
+  auto make_slices = [&]() {
+    double mx[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) mx[cb] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (w + I8_WAVES * r < NRB) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) mx[cb] = fmax(mx[cb], fabs(vals[r][cb][i]));
+      }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      double v = mx[cb];
+      v = fmax(v, __shfl_xor(v, 16, 64));
+      v = fmax(v, __shfl_xor(v, 32, 64));
+      if (g == 0) red[w * W + 16 * cb + c] = v;
+    }
+    __syncthreads();
+    double inv[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int col = 16 * cb + c;
+      double v = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < I8_WAVES; ++ww) v = fmax(v, red[ww * W + col]);
+      fcur[cb] = pow2_above(v);
+      inv[cb] = 128.0 / fcur[cb];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int rb = w + I8_WAVES * r;
+      if (rb < NRB) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          uint32_t packed[NSL] = {0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) slice5(vals[r][cb][i] * inv[cb], 8 * i, packed);
+#pragma unroll
+          for (int p = 0; p < NSL; ++p)
+            *(uint32_t*)(Bsl + (p * W + 16 * cb + c) * LDK + 16 * rb + 4 * g) = packed[p];
+        }
+      }
+    }
+    __syncthreads();
+  };
+
+  // first panel: v_{l0+1} E diag(v_l0)
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * (w + I8_WAVES * r) + drow32(g, i), col = c0 + 16 * cb + c;
+        vals[r][cb][i] = (w + I8_WAVES * r < NRB) ? vbuf[Np + row] * E64[(size_t)row * Np + col] * vbuf[col] : 0.0;
+      }
+  make_slices();
+
+  const int nkb = Npk >> 6;
+  for (int t = 1; t < len; ++t) {
+    const bool last = (t == len - 1);
+    double* vnext = vbuf + ((t + 1) & 1) * Np;   // v of slice l0+t+1 (unused when last)
+    if (!last) fill_v(vnext, xb, l0 + t + 1, N, Np, ldl);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int d = 0; d < NDIAG; ++d) acc[r][cb][d] = ix4{0, 0, 0, 0};
+    for (int kb = 0; kb < nkb; ++kb) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int rb = w + I8_WAVES * r;
+        if (rb < NRB) {
+          // E slices laid out [row][k block][slice][64 bytes]: one address per row block
+          const int8_t* ep = Eq + ((size_t)(16 * rb + c) * nkb + kb) * (NSL * 64) + 16 * g;
+          ix4 ap[NSL];
+#pragma unroll
+          for (int p = 0; p < NSL; ++p) ap[p] = *(const ix4*)(ep + 64 * p);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            // the panel's slices are re-read from LDS per row block (registers are the
+            // scarcer resource)
+            ix4 bq[NSL];
+#pragma unroll
+            for (int q = 0; q < NSL; ++q)
+              bq[q] = *(const ix4*)(Bsl + (q * W + 16 * cb + c) * LDK + 64 * kb + 16 * g);
+#pragma unroll
+            for (int p = 0; p < NSL; ++p)
+#pragma unroll
+              for (int q = 0; q + p < NSL; ++q)
+                acc[r][cb][p + q] = mfma_i8(ap[p], bq[q], acc[r][cb][p + q]);
+          }
+        }
+      }
+    }
+    __syncthreads();   // every wave is done with the slices; vnext is filled
+    if (!last) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 16 * (w + I8_WAVES * r) + drow32(g, i);
+            const double x = recombine5(acc[r][cb][0][i], acc[r][cb][1][i], acc[r][cb][2][i],
+                                        acc[r][cb][3][i], acc[r][cb][4][i]);
+            vals[r][cb][i] = (w + I8_WAVES * r < NRB) ? vnext[row] * (Esc[row] * fcur[cb] * x) : 0.0;
+          }
+      make_slices();
+    } else {
+      double s2[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) s2[cb] = 0.0;
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int rb = w + I8_WAVES * r;
+        if (rb < NRB) {
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = 16 * rb + drow32(g, i);
+              const double x = recombine5(acc[r][cb][0][i], acc[r][cb][1][i], acc[r][cb][2][i],
+                                          acc[r][cb][3][i], acc[r][cb][4][i]);
+              const double val = Esc[row] * fcur[cb] * x;
+              Sout[(size_t)row * Np + c0 + 16 * cb + c] = val;
+              s2[cb] += val * val;
+            }
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        double sv = s2[cb];
+        sv += __shfl_xor(sv, 16, 64);
+        sv += __shfl_xor(sv, 32, 64);
+        if (g == 0) red[w * W + 16 * cb + c] = sv;
+      }
+      __syncthreads();
+      if (tid < W) {
+      double t2 = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < I8_WAVES; ++ww) t2 += red[ww * W + tid];
+      nout[c0 + tid] = t2;
+    }
+    }
+  }
+}
+
+template <int RB, int CB>
+hipError_t run_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f, int nb,
+                  int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
+                  double* sn, hipStream_t st) {
+  constexpr int W = 16 * CB;
+  const int Npk = (Np + 63) / 64 * 64;
+  const int count = nb * kc * (Np / W);
+  const size_t lds = (size_t)(2 * Np + I8_WAVES * W) * sizeof(double) + (size_t)NSL * W * (Npk + 16);
+  hipLaunchKernelGGL((seg_chain_i8<RB, CB>), dim3(xcd_grid(count)), dim3(64 * I8_WAVES), lds, st, Eq, Esc,
+                     E64, f, nb, N, Np, Npk, Ltau, n_s, m, k0, kc, ldl, S, sn);
+  return hipGetLastError();
+}
+
+template <int RB>
+hipError_t pick_i8(int CB, const int8_t* Eq, const double* Esc, const double* E64, FieldRef f,
+                   int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl,
+                   double* S, double* sn, hipStream_t st) {
+  if (CB == 2) return run_i8<RB, 2>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+  return run_i8<RB, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+}
+
+}  // namespace
+
+hipError_t launch_seg_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f,
+                         int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc,
+                         double ldl, double* S, double* snorm, hipStream_t st) {
+  const int NRB = Np / 16;
+  const int RB = (NRB + I8_WAVES - 1) / I8_WAVES;
+  // 32-column panels while the accumulators stay small (RB <= 2), 16 beyond
+  const int CB = (Np % 32 == 0 && RB <= 2) ? 2 : 1;
+  switch (RB) {
+    case 1: return pick_i8<1>(CB, Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 2: return pick_i8<2>(CB, Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 3: return run_i8<3, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 4: return run_i8<4, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace slmc

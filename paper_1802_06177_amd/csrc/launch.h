@@ -21,10 +21,12 @@ struct FieldRef {
 // k0 .. k0+kc-1 are computed (m stays the segment count of the S and snorm layout).
 // prec: 0 FP64; 1 FP32 with the bf16 correction of E's FP32 rounding; 4 FP32 without it;
 // (acc_chunk = k-steps of 4 per FP64 promotion of the FP32 sums, 0 = none); 2 bf16x3;
-// 3 bf16x6.  E64/E32/Elo/Ebf point at the padded exponential in each format
-// (Elo: bf16 of E64 - E32; Ebf: [pieces][Np][Np] bf16 bit patterns).
+// 3 bf16x6; 5 int8 slices (5 per operand, 15 products, exact int32 sums).
+// E64/E32/Elo/Ebf/Eq point at the padded exponential in each format (Elo: bf16 of
+// E64 - E32; Ebf: [pieces][Np][Np] bf16 bit patterns; Eq/Esc: int8 slices and row scales).
 hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const float* E32,
-                            const uint16_t* Elo, const uint16_t* Ebf, FieldRef f, int nb, int N, int Np, int Ltau,
+                            const uint16_t* Elo, const uint16_t* Ebf, const int8_t* Eq,
+                            const double* Esc, FieldRef f, int nb, int N, int Np, int Ltau,
                             int n_s, int m, int k0, int kc, double ldl, double* S, double* snorm,
                             hipStream_t st);
 

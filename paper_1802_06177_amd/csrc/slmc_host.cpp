@@ -113,7 +113,7 @@ int check_model(const slmc_model* m) {
 
 int check_opt(const slmc_options* o) {
   if (!o) return fail(SLMC_E_ARG, "options is NULL");
-  if (o->precision < 0 || o->precision > 4) return fail(SLMC_E_ARG, "unknown precision %d", o->precision);
+  if (o->precision < 0 || o->precision > 5) return fail(SLMC_E_ARG, "unknown precision %d", o->precision);
   if (o->residual_steps < 0 || o->residual_steps > 1) return fail(SLMC_E_ARG, "residual_steps must be 0 or 1");
   if (!(o->acc_chunk == 0 || o->acc_chunk == 1 || o->acc_chunk == 2 || o->acc_chunk == 4))
     return fail(SLMC_E_ARG, "acc_chunk must be one of 0, 1, 2, 4");
@@ -166,7 +166,35 @@ struct ModelConsts {
   uint16_t* Ebf2 = nullptr;   // [2][Np][Np]
   uint16_t* Ebf3 = nullptr;   // [3][Np][Np]
   uint16_t* Elo = nullptr;    // [Np][Np] bf16 of E64 - fp32(E64)
+  int8_t* Eq = nullptr;       // [Np][Npk/64][5][64] int8 slices of the row-scaled E
+  double* Esc = nullptr;      // [Np] row scales 2^{ea_i}
 };
+
+// E = diag(Esc) sum_p A_p 2^{-7(p+1)}: per row a power of two above twice the row maximum,
+// then 5 round-to-nearest 7-bit slices (|A_p| <= 64), zero for k >= Np, laid out
+// [row][k block of 64][slice][64 bytes] (the layout the int8 segment kernel reads).
+void split_e_int8(const std::vector<double>& Ep, int Np, std::vector<int8_t>& q,
+                  std::vector<double>& sc) {
+  const int Npk = (Np + 63) / 64 * 64, nkb = Npk / 64;
+  q.assign((size_t)Np * Npk * 5, 0);
+  sc.assign(Np, 1.0);
+  for (int i = 0; i < Np; ++i) {
+    double mx = 0.0;
+    for (int k = 0; k < Np; ++k) mx = std::max(mx, std::fabs(Ep[(size_t)i * Np + k]));
+    int e = 0;
+    if (mx > 0.0) (void)std::frexp(mx, &e);
+    const double s = mx > 0.0 ? std::ldexp(1.0, e + 1) : 1.0;
+    sc[i] = s;
+    for (int k = 0; k < Np; ++k) {
+      double y = Ep[(size_t)i * Np + k] / s * 128.0;
+      for (int p = 0; p < 5; ++p) {
+        const double a = std::nearbyint(y);
+        y = (y - a) * 128.0;
+        q[(((size_t)i * nkb + k / 64) * 5 + p) * 64 + (k % 64)] = (int8_t)a;
+      }
+    }
+  }
+}
 
 std::mutex g_cache_mu;
 std::map<std::tuple<int, int, int, double, double, double>, ModelConsts> g_cache;
@@ -210,6 +238,13 @@ int get_consts(const slmc_model* m, ModelConsts** out) {
   HIPCHK(hipMemcpy(mc.E32, E32.data(), E32.size() * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(mc.Ebf2, b2.data(), b2.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(mc.Ebf3, b3.data(), b3.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  std::vector<int8_t> eq;
+  std::vector<double> esc;
+  split_e_int8(Ep, Np, eq, esc);
+  HIPCHK(hipMalloc(&mc.Eq, eq.size()));
+  HIPCHK(hipMalloc(&mc.Esc, esc.size() * sizeof(double)));
+  HIPCHK(hipMemcpy(mc.Eq, eq.data(), eq.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(mc.Esc, esc.data(), esc.size() * sizeof(double), hipMemcpyHostToDevice));
   auto res = g_cache.emplace(key, mc);
   *out = &res.first->second;
   return SLMC_OK;
@@ -359,13 +394,13 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     HIPCHK(hipStreamWaitEvent(ss->s2, ss->ev[mseg], 0));
     for (int k = 0; k < mseg; ++k) {
       ProfScope ps(0, ss->s);
-      HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, f, nb, N,
+      HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb, N,
                               Np, m->Ltau, m->n_s, mseg, k, 1, ldl, w.S, w.snorm, ss->s));
       HIPCHK(hipEventRecord(ss->ev[k], ss->s));
     }
   } else {
     ProfScope ps(0, st);
-    HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, f, nb, N,
+    HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb, N,
                             Np, m->Ltau, m->n_s, mseg, 0, mseg, ldl, w.S, w.snorm, st));
   }
   // a3: stabilized accumulation
@@ -701,6 +736,8 @@ void slmc_cache_clear(void) {
     (void)hipFree(kv.second.Ebf2);
     (void)hipFree(kv.second.Ebf3);
     (void)hipFree(kv.second.Elo);
+    (void)hipFree(kv.second.Eq);
+    (void)hipFree(kv.second.Esc);
     (void)hipSetDevice(cur);
   }
   g_cache.clear();

@@ -226,7 +226,8 @@ def test_logdet_only_equals_green_logdet():
 
 @pytest.mark.parametrize("prec,chunk,rel_bar,g_bar", [
     ("fp32", 1, 1.5e-7, 1e-6), ("fp32", 4, 2e-7, 1e-6), ("fp32", 0, 8e-7, 3e-6),
-    ("fp32plain", 1, 3e-7, 1e-6), ("bf16x6", 0, 1.5e-6, 3e-6), ("bf16x3", 0, 1e-4, 2e-4)])
+    ("fp32plain", 1, 3e-7, 1e-6), ("bf16x6", 0, 1.5e-6, 3e-6), ("bf16x3", 0, 1e-4, 2e-4),
+    ("int8x5", 0, 1e-9, 1e-8)])
 def test_mixed_variants_error_bars_8x8(prec, chunk, rel_bar, g_bar):
     md = workload_models("W2")[0]
     xs = [workload_item("W2", b)[1] for b in range(0, 256, 64)]
@@ -249,3 +250,41 @@ def test_fp32_full_size_16x16():
     md = workload_models("W4", 1)[0]
     xs = [workload_item("W4", b, 1)[1] for b in (3,)]
     _check(md, xs, _run(md, xs, prec="fp32", chunk=1, resid=1), 2e-7, 1e-6)
+
+
+# ------------------------------------------------------------------------- int8 slices
+# The int8 split accumulates exactly; its error comes only from cutting E and the panels
+# into 5 slices of 7 bits (about 2^-36 relative per product), so it must meet the 1e-8
+# relative log-det target at the full 16x16 size and on padded / ragged shapes.
+
+def test_int8x5_full_size_16x16_meets_1e8():
+    md = workload_models("W4", 1)[0]
+    xs = [workload_item("W4", b, 1)[1] for b in (0, 77)]
+    _check(md, xs, _run(md, xs, prec="int8x5", resid=1), 1e-8, 1e-7)
+
+
+@pytest.mark.parametrize("lam_idx", [0, 2])
+def test_int8x5_16x16_other_couplings(lam_idx):
+    md = workload_models("W4", lam_idx)[0]
+    xs = [workload_item("W4", b, lam_idx)[1] for b in (3,)]
+    _check(md, xs, _run(md, xs, prec="int8x5", resid=1), 1e-8, 1e-7)
+
+
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s", [(2, 3, 10, 3), (6, 6, 30, 7), (10, 10, 40, 8),
+                                             (12, 12, 36, 10), (20, 20, 16, 8), (4, 4, 20, 1)])
+def test_int8x5_ragged_and_padded_shapes(Lx, Ly, Ltau, n_s):
+    md = _md(Lx, Ltau, n_s, 1.5, Ly=Ly, mu=0.1)
+    g = gen(94, Lx * 1000 + Ly * 100 + Ltau)
+    xs = [g.normal(0.0, 1.5, size=(Ltau, Lx * Ly)) for _ in range(3)]
+    _check(md, xs, _run(md, xs, prec="int8x5"), 1e-9, 1e-8)
+
+
+def test_int8x5_staggered_closed_form_16x16():
+    import pins
+    md = workload_models("W4", 2)[0]
+    xs = [workload_item("W4", b, 2)[1] for b in (128, 129)]
+    ld, sg, _, st = _run(md, xs, prec="int8x5", want_g=False)
+    for k, x in enumerate(xs):
+        ref = pins.staggered_logdet(16, 16, 1.0, 0.0, 0.1, md["lam"], x[0, 0], md["Ltau"])
+        assert st[k] == 0 and sg[k] == 1
+        assert abs(ld[k] - ref) <= 1e-8 * abs(ref), (ld[k], ref)
