@@ -12,8 +12,11 @@ One step = one SLMC cumulative update of every chain, i.e. every step of the hot
   FP64 residual step); bosonic action, effective energy and the accept/copy of Eq. 6.
 value = chains * steps / time  (fermion log-det + G evaluations per second).
 
-Also printed: a roofline line for the dominant kernel (HIP events around its launches on
-its stream), and the FP64 CPU oracle timed on a bounded sample of the same fields.
+The headline run uses the mixed path that meets the 1e-8 relative log-det target (segment
+products on the int8 matrix cores with 5-slice splits, everything else FP64); the FP64
+path is timed the same way beside it ("mixed vs FP64").  Also printed: the roofline of
+the dominant kernel (HIP events around its launches on its own stream), and the FP64 CPU
+oracle timed on a bounded sample of the same fields.
 """
 
 import argparse
@@ -25,46 +28,22 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "i8": 5000.0}   # dense matrix-core T(FL)OP/s, MI355X
+# dense matrix-core peaks of the MI355X, T(FL)OP/s
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "i8": 5000.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "int8x5": "i8"}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "int8x5": 15}   # per slice product
+# HBM bytes per launch of a kernel class at the 16x16 / 128-chain workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain 1 GiB copy
+# (factors 2.0 and 1.0); valid only for the kernel versions they were taken on.
+TRAFFIC = {("seg_chain", "int8x5"): 76.64e6}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6", "int8x5"])
-    ap.add_argument("--acc-chunk", type=int, default=0)
-    ap.add_argument("--residual", type=int, default=1)
-    ap.add_argument("--chains", type=int, default=128)
-    ap.add_argument("--lam", type=float, default=1.5)
-    ap.add_argument("--serial", action="store_true",
-                    help="keep the segment products on the caller's stream (no overlap)")
-    ap.add_argument("--cpu-sample", type=int, default=6, help="oracle items for cpu_baseline (0: skip)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-              "(chains shard across GPUs with no exchange; no multi-GPU run is part of it).",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_1802_06177_amd as slmc
-    from synth import workload_item, workload_models, eff_coefficients
-
+def run(slmc, torch, md, eff, xs, B, prec, args):
+    """Warm-up + timed steps of one precision; returns the measurements."""
     dev = torch.device("cuda:0")
-    lam_idx = {1.0: 0, 1.5: 1, 2.0: 2}.get(args.lam, 1)
-    md = dict(workload_models("W4", lam_idx)[0])
-    md["lam"] = args.lam
-    N, Lt, n_s, B = md["Lx"] * md["Ly"], md["Ltau"], md["n_s"], args.chains
+    N = md["Lx"] * md["Ly"]
     m = slmc.model_from_dict(md)
-    ec = eff_coefficients(4, 0, args.lam, delta=0.6)
-    eff = slmc.eff_model(**ec)
-    opt = slmc.options(args.precision, args.residual, args.acc_chunk, serial=args.serial)
-
-    xs = np.stack([workload_item("W4", b % 128, lam_idx)[1] for b in range(B)])
+    opt = slmc.options(prec, args.residual, args.acc_chunk, serial=args.serial)
     x_cur = torch.tensor(xs, dtype=torch.float64, device=dev)
     x_prop = torch.empty_like(x_cur)
     G = torch.empty((B, N, N), dtype=torch.float64, device=dev)
@@ -86,7 +65,6 @@ def main():
     torch.cuda.synchronize()
     ev0.record()
     t0 = time.perf_counter()
-    acc_total = 0
     accs = []
     for k in range(args.warmup, args.warmup + args.steps):
         a, _ = step(k)
@@ -98,33 +76,104 @@ def main():
     ms = ev0.elapsed_time(ev1)
     prof = slmc.profile_read()
     acc_total = int(sum(int(a.sum().item()) for a in accs))
-    ms_per_step = ms / args.steps
-    value = B * args.steps / (ms / 1e3)
+    return dict(ms=ms, wall=wall, prof=prof, accept=acc_total / (B * args.steps), opt=opt, m=m)
 
-    # dominant kernel and its roofline (algorithmic flops per launch / event-timed duration)
+
+def roofline(prof, prec, md, B, steps, counters_apply):
+    """Dominant kernel class (largest event time in the timed region) against its peak:
+    achieved = algorithmic work per launch / average launch time."""
+    N, Lt, n_s = md["Lx"] * md["Ly"], md["Ltau"], md["n_s"]
+    nseg = (Lt + n_s - 1) // n_s
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
-    nseg = (Lt + n_s - 1) // n_s
-    flops = {
-        "seg_chain": 2.0 * N ** 3 * (Lt - nseg) * B,        # (n_s - 1) products per segment
-        "qr": (4.0 / 3.0) * N ** 3 * B,                      # Householder QR of N x N
-        "wy_apply": 2.0 * N ** 3 * B,                        # S_k Q_{k-1}
-        "vupd": 1.0 * N ** 3 * B,                            # triangular times dense
-        "lu": (2.0 / 3.0) * N ** 3 * B,
-        "lu_solve": 2.0 * N ** 3 * B,
-        "residual": 2.0 * N ** 3 * B,
+    # per-evaluation algorithmic flops of each class (FP64-equivalent)
+    per_eval = {
+        "seg_chain": 2.0 * N ** 3 * (Lt - nseg),   # n_s - 1 products per segment
+        "qr": (4.0 / 3.0) * N ** 3 * nseg,         # Householder QR of N x N per block
+        "wy_apply": 2.0 * N ** 3 * nseg,           # S_k Q_{k-1}
+        "vupd": 1.0 * N ** 3 * nseg,               # triangular times dense
+        "lu": (2.0 / 3.0) * N ** 3,
+        "lu_solve": 4.0 * N ** 3,                  # solve + refinement solve
+        "residual": 2.0 * N ** 3,
+        "eff_sweep": 0.0,
     }
-    prec_dtype = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "int8x5": "i8"}[args.precision]
-    kern_dtype = prec_dtype if dom == "seg_chain" else "f64"
-    achieved = flops.get(dom, 0.0) / (dom_ms / dom_n / 1e3) / 1e12 if dom_n else 0.0
-    roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
-            "peak": PEAK[kern_dtype], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[kern_dtype], 4), "traffic": None,
-            "avg_launch_ms": round(dom_ms / dom_n, 4) if dom_n else None,
-            "per_class_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]}}
+    launches_per_step = dom_n / steps if dom_n else 1.0
+    work_per_launch = per_eval.get(dom, 0.0) * B / launches_per_step
+    t_launch = dom_ms / dom_n / 1e3 if dom_n else float("nan")
+    dtype = DTYPE[prec] if dom == "seg_chain" else "f64"
+    ops = work_per_launch * (PRODUCTS[prec] if dom == "seg_chain" else 1)
+    achieved = ops / t_launch / 1e12 if dom_n else 0.0
+    return {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[dtype],
+            "unit": "TOP/s" if dtype == "i8" else "TFLOP/s", "frac": round(achieved / PEAK[dtype], 4),
+            "traffic": TRAFFIC.get((dom, prec)) if counters_apply else None,
+            "avg_launch_ms": round(t_launch * 1e3, 4),
+            "work_per_launch": ops,
+            "fp64_equiv_tflops": round(work_per_launch / t_launch / 1e12, 3) if dom_n else None,
+            "per_class_ms_per_step": {k: round(v[0] / steps, 3) for k, v in prof.items() if v[1]}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="int8x5", choices=sorted(DTYPE))
+    ap.add_argument("--acc-chunk", type=int, default=0)
+    ap.add_argument("--residual", type=int, default=1)
+    ap.add_argument("--chains", type=int, default=128)
+    ap.add_argument("--lam", type=float, default=1.5)
+    ap.add_argument("--serial", action="store_true",
+                    help="keep the segment products on the caller's stream (no overlap)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--cpu-sample", type=int, default=6, help="oracle items for cpu_baseline (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB mebibytes (reference "
+                         "for the HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(chains shard across GPUs with no exchange; no multi-GPU run is part of it).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 8 * n, "copy_calibration_bytes_written": 8 * n}))
+        return
+
+    import paper_1802_06177_amd as slmc
+    from synth import workload_item, workload_models, eff_coefficients
+
+    lam_idx = {1.0: 0, 1.5: 1, 2.0: 2}.get(args.lam, 1)
+    md = dict(workload_models("W4", lam_idx)[0])
+    md["lam"] = args.lam
+    B = args.chains
+    eff = slmc.eff_model(**eff_coefficients(4, 0, args.lam, delta=0.6))
+    xs = np.stack([workload_item("W4", b % 128, lam_idx)[1] for b in range(B)])
+
+    main_run = run(slmc, torch, md, eff, xs, B, args.precision, args)
+    ms_per_step = main_run["ms"] / args.steps
+    value = B * args.steps / (main_run["ms"] / 1e3)
+    roof = roofline(main_run["prof"], args.precision, md, B, args.steps,
+                    counters_apply=(B == 128 and args.lam == 1.5))
+
+    fp64 = None
+    if args.precision != "fp64" and not args.no_fp64:
+        r64 = run(slmc, torch, md, eff, xs, B, "fp64", args)
+        fp64 = {"value": round(B * args.steps / (r64["ms"] / 1e3), 3),
+                "ms_per_step": round(r64["ms"] / args.steps, 4),
+                "mixed_over_fp64": round(r64["ms"] / main_run["ms"], 4)}
 
     # CPU oracle on a bounded sample of the same fields (log-det + G), and the error of the
-    # GPU path on those items
+    # GPU path (headline precision) on those items
     cpu = None
     err = None
     if args.cpu_sample > 0:
@@ -137,31 +186,31 @@ def main():
         E = oracle.expk(oracle.hopping_matrix(md["Lx"], md["Ly"], md["t"], md["mu"]), md["dtau"])
         ns = min(args.cpu_sample, B)
         xsamp = xs[:ns]
-        ld_g, _, G_g, _ = slmc.green(m, torch.tensor(xsamp, device=dev), opt)
+        ld_g, _, G_g, _ = slmc.green(main_run["m"], torch.tensor(xsamp, device="cuda:0"), main_run["opt"])
         torch.cuda.synchronize()
         ld_g, G_g = ld_g.cpu().numpy(), G_g.cpu().numpy()
         t1 = time.perf_counter()
-        refs = [oracle.logdet_green(E, xsamp[k], md["dtau"], md["lam"], n_s) for k in range(ns)]
+        refs = [oracle.logdet_green(E, xsamp[k], md["dtau"], md["lam"], md["n_s"]) for k in range(ns)]
         tc = time.perf_counter() - t1
         cpu = {"value": round(ns / tc, 4), "unit": "evals/s", "cores": int(cores), "kind": "oracle",
                "sample": "%d of the %d fields (16x16, Ltau=160, n_s=8, lam=%.1f), log-det + G, "
                          "numpy/scipy FP64 (LAPACK QRP + LU)" % (ns, B, md["lam"])}
         err = {"max_rel_logdet": float(max(abs(ld_g[k] - refs[k][0]) / abs(refs[k][0]) for k in range(ns))),
                "max_abs_G": float(max(np.max(np.abs(G_g[k] - refs[k][2])) for k in range(ns))),
-               "items": ns}
+               "items": ns, "precision": args.precision}
 
     out = {
         "metric": "fermion logdet+G evals/s at N=256,Ltau=160: mixed vs FP64, <=1e-8 rel err",
         "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": prec_dtype, "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": "16x16 (N=256), beta=16 (Ltau=160), n_s=8, lam=%.1f, omega0=1, "
-                              "%d chains; step = sweep + logdet+G of proposals + accept" % (md["lam"], B),
+                               "%d chains; step = sweep + logdet+G of proposals + accept" % (md["lam"], B),
                    "precision": args.precision, "acc_chunk": args.acc_chunk,
                    "residual_steps": args.residual, "global_batch": B, "parallelism": "none",
                    "schedule": "serial" if args.serial else "overlapped"},
-        "roofline": roof, "cpu_baseline": cpu, "error_vs_oracle": err,
-        "accept_rate": round(acc_total / (B * args.steps), 4), "wall_s": round(wall, 3),
+        "roofline": roof, "cpu_baseline": cpu, "error_vs_oracle": err, "fp64_path": fp64,
+        "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
     }
     print(json.dumps(out), flush=True)
 
