@@ -79,6 +79,31 @@ def run(slmc, torch, md, eff, xs, B, prec, args):
     return dict(ms=ms, wall=wall, prof=prof, accept=acc_total / (B * args.steps), opt=opt, m=m)
 
 
+def sweep_rates(slmc, torch, np, chains, n_sweeps=4, reps=5):
+    """Checkerboard sweeps of the effective model alone on the 12x12, Ltau = 120 shape
+    (seeded coefficients): site updates per second and algorithmic bytes per second (one
+    read and one write of the FP64 field per sweep)."""
+    from synth import gen, eff_coefficients
+    Lx = Ly = 12
+    Lt = 120
+    m = slmc.model(Lx, Ly, Lt, 10)
+    eff = slmc.eff_model(**eff_coefficients(3, 0, 1.5, delta=0.5))
+    x = torch.tensor(gen(3, 999).normal(size=(chains, Lt, Lx * Ly)), dtype=torch.float64, device="cuda:0")
+    slmc.eff_sweep(m, eff, x, n_sweeps, 7, 0)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for r in range(reps):
+        slmc.eff_sweep(m, eff, x, n_sweeps, 7, r + 1)
+    ev1.record()
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) / 1e3
+    sites = chains * Lx * Ly * Lt * n_sweeps * reps
+    return {"chains": chains, "sweeps_per_launch": n_sweeps, "updates_per_s": round(sites / t, 1),
+            "algorithmic_GB_per_s": round(16.0 * sites / t / 1e9, 2),
+            "working_set_MB": round(8.0 * chains * Lx * Ly * Lt / 1e6, 1)}
+
+
 def roofline(prof, prec, md, B, steps, counters_apply):
     """Dominant kernel class (largest event time in the timed region) against its peak:
     achieved = algorithmic work per launch / average launch time."""
@@ -172,6 +197,11 @@ def main():
                 "ms_per_step": round(r64["ms"] / args.steps, 4),
                 "mixed_over_fp64": round(r64["ms"] / main_run["ms"], 4)}
 
+    # the effective-model sweep alone on the 12x12 shape: 64 chains (L2-resident) and 2048
+    # chains (a working set above the 256 MB last-level cache)
+    sweep = {"12x12x120_64": sweep_rates(slmc, torch, np, 64),
+             "12x12x120_2048": sweep_rates(slmc, torch, np, 2048, n_sweeps=1, reps=3)}
+
     # CPU oracle on a bounded sample of the same fields (log-det + G), and the error of the
     # GPU path (headline precision) on those items
     cpu = None
@@ -210,6 +240,7 @@ def main():
                    "residual_steps": args.residual, "global_batch": B, "parallelism": "none",
                    "schedule": "serial" if args.serial else "overlapped"},
         "roofline": roof, "cpu_baseline": cpu, "error_vs_oracle": err, "fp64_path": fp64,
+        "sweep_only": sweep,
         "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
     }
     print(json.dumps(out), flush=True)

@@ -421,6 +421,75 @@ __device__ __forceinline__ void update_block(int nrbK, int j0, int cb, bool from
   }
 }
 
+// The column block of the next panel, updated with the current panel by the 4 panel waves
+// together: wave w takes the row blocks w, w+4, ..; the partial products Y^T blk meet in
+// LDS (wpart, [4][64 lanes][4]) behind one panel sync, then every wave finishes its rows.
+// Rows j0 .. j0+15 go to Q, the rows below to the next panel buffer Px.
+template <int RBQ>
+__device__ __forceinline__ void update_block_split(int nrbK, int j0, int cb, bool from_a,
+                                                   const double* __restrict__ Ab,
+                                                   const int* __restrict__ iperm,
+                                                   double* __restrict__ Q, int Np, const double* Pc,
+                                                   const double* Tc, double* Px, double* wpart,
+                                                   int w, int lane, int* cnt, int& epoch,
+                                                   int* timeout) {
+  int c = lane & 15, g = lane >> 4;
+  __asm__ volatile("" : "+v"(c), "+v"(g));
+  const int col = 16 * cb + c;
+  const double* src = from_a ? Ab + iperm[col] : Q + (size_t)j0 * Np + col;
+  double* dst = Q + (size_t)j0 * Np + col;
+  dx4 blk[RBQ];
+#pragma unroll
+  for (int r = 0; r < RBQ; ++r) {
+    const int rb = w + QR_PANEL_WAVES * r;
+    if (rb < nrbK) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) blk[r][v] = src[(16 * rb + drow64(g, v)) * Np];
+    }
+  }
+  dx4 aw[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
+#pragma unroll
+  for (int r = 0; r < RBQ; ++r) {
+    const int rb = w + QR_PANEL_WAVES * r;
+    if (rb < nrbK) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        aw[s] = mfma64(yval(Pc, 16 * rb + drow64(g, s), c), blk[r][s], aw[s]);
+    }
+  }
+  const dx4 Wp = aw[0] + aw[1] + aw[2] + aw[3];
+  *(dx4*)(wpart + (w * 64 + lane) * 4) = Wp;
+  panel_sync(cnt, epoch, lane, timeout);
+  dx4 W = zero4d();
+#pragma unroll
+  for (int ww = 0; ww < QR_PANEL_WAVES; ++ww) W += *(const dx4*)(wpart + (ww * 64 + lane) * 4);
+  double tv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) tv[s] = Tc[drow64(g, s) * LDY + c];
+  dx4 Wt = zero4d();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) Wt = mfma64(tv[s], W[s], Wt);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+#pragma unroll
+    for (int r = 0; r < RBQ; ++r) {
+      const int rb = w + QR_PANEL_WAVES * r;
+      if (rb < nrbK) blk[r] = mfma64(-yval(Pc, 16 * rb + c, drow64(g, s)), Wt[s], blk[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RBQ; ++r) {
+    const int rb = w + QR_PANEL_WAVES * r;
+    if (rb < nrbK) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (rb == 0) dst[drow64(g, v) * Np] = blk[r][v];
+        else Px[(16 * (rb - 1) + drow64(g, v)) * LDY + c] = blk[r][v];
+      }
+    }
+  }
+}
+
 template <int NRBMAX>
 __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A, int64_t astride,
                                                    const double* __restrict__ norm2,
@@ -441,7 +510,8 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   double* red = Tl0 + 2 * 16 * LDY;         // [2][4][16]
   double* prow = red + 2 * QR_PANEL_WAVES * 16;   // [2][16]
   double* wsum = prow + 32;                 // [4][16]
-  double* key = wsum + QR_PANEL_WAVES * 16; // [Np]
+  double* wpart = wsum + QR_PANEL_WAVES * 16;     // [4][64][4] partial Y^T blk
+  double* key = wpart + QR_PANEL_WAVES * 256;     // [Np]
   double* beta = key + Np;                  // [Np]
   double* tauA = beta + Np;                 // [Np]
   double* nt = tauA + Np;                   // [8]
@@ -478,8 +548,8 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   for (int j = tid; j < Np; j += QR_THREADS) key[j] = logDp ? logDp[(size_t)b * Np + iperm[j]] : 0.0;
 
   // Panel waves (0-3) factor panel 0, then for every step p update column block p+1 with
-  // panel p and factor it as panel p+1; waves 4-7 meanwhile apply panel p to the column
-  // blocks p+2 ..  One workgroup barrier per step publishes panel p+1.
+  // panel p (split by row blocks) and factor it as panel p+1; waves 4-7 meanwhile apply
+  // panel p to the column blocks p+2 ..  One workgroup barrier per step publishes panel p+1.
   constexpr bool TWO = NRBMAX > 16;
   const bool panel_wave = w < QR_PANEL_WAVES;
   int epoch = 0;
@@ -500,9 +570,9 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
       if (p >= 0) {
         // column block q, updated with panel p, lands in Yq (rows below its R part)
         const int j0 = 16 * p;
-        if (w == 0)
-          update_block<NRBMAX>(NRB - p, j0, q, p == 0, Ab, iperm, Q, Np, Pn0 + (p & 1) * Np * LDY,
-                               Tl0 + (p & 1) * 16 * LDY, Yq, lane);
+        update_block_split<(NRBMAX + QR_PANEL_WAVES - 1) / QR_PANEL_WAVES>(
+            NRB - p, j0, q, p == 0, Ab, iperm, Q, Np, Pn0 + (p & 1) * Np * LDY,
+            Tl0 + (p & 1) * 16 * LDY, Yq, wpart, w, lane, cnt, epoch, flag + 1);
         panel_sync(cnt, epoch, lane, flag + 1);
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
@@ -650,7 +720,8 @@ template <int NRBMAX>
 hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride, int nparts,
                   const double* logDp, double* QRW, double* Tb, int* perm, double* logD,
                   int* qsign, int* status, int nb, int Np, hipStream_t st) {
-  const size_t lds = (size_t)(2 * Np * LDY + 2 * 16 * LDY + 3 * QR_PANEL_WAVES * 16 + 32 + 3 * Np + 8) *
+  const size_t lds = (size_t)(2 * Np * LDY + 2 * 16 * LDY + 3 * QR_PANEL_WAVES * 16 + 32 +
+                              QR_PANEL_WAVES * 256 + 3 * Np + 8) *
                          sizeof(double) + (size_t)(Np + 4) * sizeof(int);
   hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(QR_THREADS), lds, st, A, astride, norm2, nstride, nparts,
                      logDp, QRW, Tb, perm, logD, qsign, status, Np);

@@ -288,3 +288,44 @@ def test_int8x5_staggered_closed_form_16x16():
         ref = pins.staggered_logdet(16, 16, 1.0, 0.0, 0.1, md["lam"], x[0, 0], md["Ltau"])
         assert st[k] == 0 and sg[k] == 1
         assert abs(ld[k] - ref) <= 1e-8 * abs(ref), (ld[k], ref)
+
+
+# ------------------------------------------------------------------------- packed uneven batch
+# The uneven workload: 32 fields for each of L = 8, 12, 16, 20 (Ltau = 10 L, n_s = 10) in one
+# packed call, items interleaved across the four models; sampled items against the oracle.
+
+@pytest.mark.parametrize("prec,rel_bar,g_bar", [("fp64", 1e-11, 1e-9), ("int8x5", 1e-8, 1e-7)])
+def test_uneven_workload_packed_sampled(prec, rel_bar, g_bar):
+    mds = workload_models("W5")
+    models = [slmc.model_from_dict(d) for d in mds]
+    items = list(range(128))
+    order = [items[(7 * k) % 128] for k in range(128)]          # interleave the sizes
+    xs, midx = [], []
+    for b in order:
+        mi, x = workload_item("W5", b)
+        xs.append(x)
+        midx.append(mi)
+    x_off = np.cumsum([0] + [x.size for x in xs[:-1]])
+    g_sizes = [(mds[k]["Lx"] * mds[k]["Ly"]) ** 2 for k in midx]
+    g_off = np.cumsum([0] + g_sizes[:-1])
+    x = torch.tensor(np.concatenate([a.ravel() for a in xs]), dtype=torch.float64, device=DEV)
+    G = torch.zeros(int(sum(g_sizes)), dtype=torch.float64, device=DEV)
+    print("case: uneven W5 packed, 128 items, prec=%s" % prec, flush=True)
+    ld, sg, G, st = slmc.green(models, x, slmc.options(prec, 1), model_idx=midx, x_off=x_off,
+                               g_off=g_off, n_items=len(order), G=G)
+    torch.cuda.synchronize()
+    ld, sg, Gh, st = ld.cpu().numpy(), sg.cpu().numpy(), G.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    # one sampled item per size class (the oracle at L = 20 takes a few seconds)
+    seen = set()
+    for j, mi in enumerate(midx):
+        if mi in seen:
+            continue
+        seen.add(mi)
+        ref, rs, rG = _ref(mds[mi], xs[j])
+        N = mds[mi]["Lx"] * mds[mi]["Ly"]
+        Gj = Gh[g_off[j]:g_off[j] + N * N].reshape(N, N)
+        assert sg[j] == rs
+        assert abs(ld[j] - ref) <= rel_bar * abs(ref), (mi, ld[j], ref)
+        assert np.max(np.abs(Gj - rG)) <= g_bar
+    assert seen == {0, 1, 2, 3}
