@@ -8,7 +8,7 @@
 // X is factored by a blocked LU with partial pivoting (one workgroup per item, the pivot
 // order kept as a row map so no row is moved in memory); the solve for G gives each wave
 // one 16-column block of the right-hand side held in registers.  The FP64 residual step
-// refines that solve: R = Db^{-1} U^T - X G, G += X^{-1} R.
+// refines that solve: R = Db^{-1} U^T - X G (a tiled batched GEMM), G += X^{-1} R.
 #include "common.h"
 #include "launch.h"
 
@@ -244,6 +244,10 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
   }
 }
 
+// X^{-1} applied to a right-hand side (mode 0: Db^{-1} U^T; mode 1: R): forward
+// substitution with the unit lower factor, then backward with the upper one, using the
+// 16x16 inverses of the diagonal blocks from the LU; one wave per (item, 16 columns), the
+// right-hand-side strip in registers.
 template <int NRBMAX>
 __global__ __launch_bounds__(256) void lu_solve_k(int mode, const double* __restrict__ QT,
                                                   const double* __restrict__ logD,
@@ -333,58 +337,78 @@ __global__ __launch_bounds__(256) void lu_solve_k(int mode, const double* __rest
   }
 }
 
-template <int NRBMAX>
+// R = Db^{-1} U^T - X G for every item, X = Db^{-1} U^T + Ds V formed while the tiles are
+// staged: a batched GEMM with 64 x 64 output tiles per workgroup (4 waves of 32 x 32) and
+// k steps of 16 through LDS.
+constexpr int RT = 64, RKS = 16;
 __global__ __launch_bounds__(256) void residual_k(const double* __restrict__ QT,
                                                   const double* __restrict__ V,
                                                   const double* __restrict__ logD,
                                                   const double* __restrict__ Gint,
                                                   double* __restrict__ R, int nb, int Np) {
-  const int NRB = Np >> 4;
-  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wid >= nb * NRB) return;
-  const int cb = wid % NRB, b = wid / NRB;
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  __shared__ double As[RT][RKS + 2];
+  __shared__ double Bs[RKS][RT + 2];
+  __shared__ double dbs[RT], dss[RT];
+  const int nt = (Np + RT - 1) / RT;
+  const int id = xcd_remap(blockIdx.x, nb * nt * nt);
+  if (id < 0) return;
+  const int tj = id % nt, ti = (id / nt) % nt, b = id / (nt * nt);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+  const int i0 = RT * ti, j0 = RT * tj, ro = 32 * (w >> 1), co = 32 * (w & 1);
   const size_t off = (size_t)b * Np * Np;
-  const double* ld = logD + (size_t)b * Np;
-  const int col = 16 * cb + c;
-  dx4 acc[NRBMAX];
-  double dbr[NRBMAX], dsr[NRBMAX];
+  if (tid < RT) {
+    const int row = i0 + tid;
+    const double l = row < Np ? logD[(size_t)b * Np + row] : 0.0;
+    dbs[tid] = exp(-fmax(l, 0.0));
+    dss[tid] = exp(fmin(l, 0.0));
+  }
+  __syncthreads();
+  dx4 acc[2][2] = {{zero4d(), zero4d()}, {zero4d(), zero4d()}};
+  const int ar = tid >> 2, ak = 4 * (tid & 3);      // A tile element group
+  const int bk = tid >> 4, bj = 4 * (tid & 15);     // B tile element group
+  for (int k0 = 0; k0 < Np; k0 += RKS) {
+    {
+      const int row = i0 + ar;
 #pragma unroll
-  for (int rb = 0; rb < NRBMAX; ++rb) {
-    if (rb < NRB) {
+      for (int e = 0; e < 4; ++e) {
+        const int k = k0 + ak + e;
+        As[ar][ak + e] = row < Np ? dbs[ar] * QT[off + (size_t)row * Np + k] +
+                                        dss[ar] * V[off + (size_t)row * Np + k]
+                                  : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = j0 + bj + e;
+        Bs[bk][bj + e] = j < Np ? Gint[off + (size_t)(k0 + bk) * Np + j] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      double a[2], bv[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        a[h] = As[ro + 16 * h + c][4 * kk + g];
+        bv[h] = Bs[4 * kk + g][co + 16 * h + c];
+      }
+#pragma unroll
+      for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+        for (int hj = 0; hj < 2; ++hj) acc[hi][hj] = mfma64(a[hi], bv[hj], acc[hi][hj]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+    for (int hj = 0; hj < 2; ++hj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * rb + drow64(g, v);
-        acc[rb][v] = exp(-fmax(ld[row], 0.0)) * QT[off + (size_t)row * Np + col];
+        const int rl = ro + 16 * hi + drow64(g, v);
+        const int row = i0 + rl, col = j0 + co + 16 * hj + c;
+        if (row < Np && col < Np)
+          R[off + (size_t)row * Np + col] = dbs[rl] * QT[off + (size_t)row * Np + col] - acc[hi][hj][v];
       }
-      const double l = ld[16 * rb + c];
-      dbr[rb] = exp(-fmax(l, 0.0));
-      dsr[rb] = exp(fmin(l, 0.0));
-    }
-  }
-  for (int kb = 0; kb < NRB; ++kb) {
-    const int q = 16 * kb + 4 * g;
-    double gv[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) gv[s] = Gint[off + (size_t)(q + s) * Np + col];
-#pragma unroll
-    for (int rb = 0; rb < NRBMAX; ++rb) {
-      if (rb < NRB) {
-        const double* qt = QT + off + (size_t)(16 * rb + c) * Np + q;
-        const double* vv = V + off + (size_t)(16 * rb + c) * Np + q;
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-          acc[rb] = mfma64(-(dbr[rb] * qt[s] + dsr[rb] * vv[s]), gv[s], acc[rb]);
-      }
-    }
-  }
-#pragma unroll
-  for (int rb = 0; rb < NRBMAX; ++rb) {
-    if (rb < NRB) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) R[off + (size_t)(16 * rb + drow64(g, v)) * Np + col] = acc[rb][v];
-    }
-  }
 }
 
 template <int NRBMAX>
@@ -405,15 +429,6 @@ hipError_t run_solve(int mode, const double* QT, const double* logD, const doubl
   const int waves = nb * (Np / 16);
   hipLaunchKernelGGL(lu_solve_k<NRBMAX>, dim3((waves + 3) / 4), dim3(256), 0, st, mode, QT, logD,
                      R, LU, prow, DI, Gint, acc, Gout, goff, nb, N, Np);
-  return hipGetLastError();
-}
-
-template <int NRBMAX>
-hipError_t run_resid(const double* QT, const double* V, const double* logD, const double* Gint,
-                     double* R, int nb, int Np, hipStream_t st) {
-  const int waves = nb * (Np / 16);
-  hipLaunchKernelGGL(residual_k<NRBMAX>, dim3((waves + 3) / 4), dim3(256), 0, st, QT, V, logD,
-                     Gint, R, nb, Np);
   return hipGetLastError();
 }
 
@@ -448,7 +463,10 @@ hipError_t launch_lu_solve(int mode, const double* QT, const double* logD, const
 
 hipError_t launch_residual(const double* QT, const double* V, const double* logD,
                            const double* Gint, double* R, int nb, int Np, hipStream_t st) {
-  SLMC_NRB_DISPATCH(run_resid, QT, V, logD, Gint, R, nb, Np, st);
+  const int nt = (Np + RT - 1) / RT;
+  hipLaunchKernelGGL(residual_k, dim3(xcd_grid(nb * nt * nt)), dim3(256), 0, st, QT, V, logD, Gint,
+                     R, nb, Np);
+  return hipGetLastError();
 }
 
 }  // namespace slmc

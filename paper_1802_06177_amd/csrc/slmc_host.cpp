@@ -470,15 +470,20 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
                    st_out, nb, N, Np, st));
   }
   if (G) {
-    ProfScope ps(5, st);
     const bool resid = o->residual_steps > 0;
-    HIPCHK(launch_lu_solve(0, QT, logDf, nullptr, LU, w.prow, w.DI, Gint, 0, resid ? nullptr : g_out,
-                           goff, nb, N, Np, st));
+    {
+      ProfScope ps(5, st);
+      HIPCHK(launch_lu_solve(0, QT, logDf, nullptr, LU, w.prow, w.DI, Gint, 0,
+                             resid ? nullptr : g_out, goff, nb, N, Np, st));
+    }
     if (resid) {
       // a5: R = Db^-1 U^T - X G, G += X^-1 R
       double* R = w.QRW[mseg & 1];   // the other QR buffer is free now
-      ProfScope pr(6, st);
-      HIPCHK(launch_residual(QT, Vf, logDf, Gint, R, nb, Np, st));
+      {
+        ProfScope pr(6, st);
+        HIPCHK(launch_residual(QT, Vf, logDf, Gint, R, nb, Np, st));
+      }
+      ProfScope ps(5, st);
       HIPCHK(launch_lu_solve(1, QT, logDf, R, LU, w.prow, w.DI, Gint, 1, g_out, goff, nb, N, Np, st));
     }
   }
