@@ -284,11 +284,11 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
       }
       __syncthreads();
       if (tid < W) {
-      double t2 = 0.0;
+        double t2 = 0.0;
 #pragma unroll
-      for (int ww = 0; ww < I8_WAVES; ++ww) t2 += red[ww * W + tid];
-      nout[c0 + tid] = t2;
-    }
+        for (int ww = 0; ww < I8_WAVES; ++ww) t2 += red[ww * W + tid];
+        nout[c0 + tid] = t2;
+      }
     }
   }
 }

@@ -421,24 +421,17 @@ __device__ __forceinline__ void update_block(int nrbK, int j0, int cb, bool from
   }
 }
 
-// The column block of the next panel, updated with the current panel by the 4 panel waves
-// together: wave w takes the row blocks w, w+4, ..; the partial products Y^T blk meet in
-// LDS (wpart, [4][64 lanes][4]) behind one panel sync, then every wave finishes its rows.
-// Rows j0 .. j0+15 go to Q, the rows below to the next panel buffer Px.
+// Rows of a column block owned by panel wave w in the split update below (row blocks w,
+// w+4, .. of the rows j0 ..), loaded ahead of use: from A through the column order on the
+// first step (from_a), from Q after.
 template <int RBQ>
-__device__ __forceinline__ void update_block_split(int nrbK, int j0, int cb, bool from_a,
-                                                   const double* __restrict__ Ab,
-                                                   const int* __restrict__ iperm,
-                                                   double* __restrict__ Q, int Np, const double* Pc,
-                                                   const double* Tc, double* Px, double* wpart,
-                                                   int w, int lane, int* cnt, int& epoch,
-                                                   int* timeout) {
-  int c = lane & 15, g = lane >> 4;
-  __asm__ volatile("" : "+v"(c), "+v"(g));
-  const int col = 16 * cb + c;
+__device__ __forceinline__ void prefetch_block(dx4 (&blk)[RBQ], int nrbK, int j0, int cb,
+                                               bool from_a, const double* __restrict__ Ab,
+                                               const int* __restrict__ iperm,
+                                               const double* __restrict__ Q, int Np, int w,
+                                               int lane) {
+  const int c = lane & 15, g = lane >> 4, col = 16 * cb + c;
   const double* src = from_a ? Ab + iperm[col] : Q + (size_t)j0 * Np + col;
-  double* dst = Q + (size_t)j0 * Np + col;
-  dx4 blk[RBQ];
 #pragma unroll
   for (int r = 0; r < RBQ; ++r) {
     const int rb = w + QR_PANEL_WAVES * r;
@@ -447,6 +440,21 @@ __device__ __forceinline__ void update_block_split(int nrbK, int j0, int cb, boo
       for (int v = 0; v < 4; ++v) blk[r][v] = src[(16 * rb + drow64(g, v)) * Np];
     }
   }
+}
+
+// The column block of the next panel, updated with the current panel by the 4 panel waves
+// together: wave w holds the row blocks w, w+4, .. (prefetched); the partial products
+// Y^T blk meet in LDS (wpart, [4][64 lanes][4]) behind one panel sync, then every wave
+// finishes its rows.  Rows j0 .. j0+15 go to Q, the rows below to the next panel buffer Px.
+template <int RBQ>
+__device__ __forceinline__ void apply_block_split(dx4 (&blk)[RBQ], int nrbK, int j0, int cb,
+                                                  double* __restrict__ Q, int Np, const double* Pc,
+                                                  const double* Tc, double* Px, double* wpart,
+                                                  int w, int lane, int* cnt, int& epoch,
+                                                  int* timeout) {
+  int c = lane & 15, g = lane >> 4;
+  __asm__ volatile("" : "+v"(c), "+v"(g));
+  double* dst = Q + (size_t)j0 * Np + 16 * cb + c;
   dx4 aw[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
 #pragma unroll
   for (int r = 0; r < RBQ; ++r) {
@@ -518,11 +526,12 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   int* iperm = (int*)(nt + 8);              // [Np]
   int* flag = iperm + Np;                   // [2]: non-finite input, sync timeout
   int* cnt = flag + 2;                      // [1] panel-wave sync counter
+  int* blkrdy = cnt + 1;                    // [1] last step whose first trailing block is stored
 
   const double* Ab = A + (size_t)b * astride;
   double* Q = QRW + (size_t)b * Np * Np;
   double* Tg = Tb + (size_t)b * NRB * 256;
-  if (tid == 0) { flag[0] = 0; flag[1] = 0; cnt[0] = 0; }
+  if (tid == 0) { flag[0] = 0; flag[1] = 0; cnt[0] = 0; blkrdy[0] = -1; }
   __syncthreads();
 
   // ---- pre-pivoting: order columns by log ||A e_j|| + log D_prev[j], descending
@@ -551,9 +560,12 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   // panel p (split by row blocks) and factor it as panel p+1; waves 4-7 meanwhile apply
   // panel p to the column blocks p+2 ..  One workgroup barrier per step publishes panel p+1.
   constexpr bool TWO = NRBMAX > 16;
-  const bool panel_wave = w < QR_PANEL_WAVES;
+  constexpr int RBQ = (NRBMAX + QR_PANEL_WAVES - 1) / QR_PANEL_WAVES;
+  // wave-uniform role (readfirstlane makes the branch on it a scalar one)
+  const bool panel_wave = __builtin_amdgcn_readfirstlane(w) < QR_PANEL_WAVES;
   int epoch = 0;
   double row0[16], row1[16], trow[16];
+  dx4 nblk[RBQ];   // this panel wave's rows of the next column block (prefetched)
   if (panel_wave) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -561,18 +573,19 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
       row1[j] = (TWO && tid + 256 < Np) ? Ab[(size_t)(tid + 256) * Np + iperm[j]] : 0.0;
     }
   }
-  for (int p = -1; p < NRB - 1; ++p) {
-    // this step factors panel q = p + 1; panel p (if any) is published in buffer p & 1
-    const int q = p + 1, jq = 16 * q, Kq = Np - jq;
-    double* Yq = Pn0 + (q & 1) * Np * LDY;
-    double* Tq = Tl0 + (q & 1) * 16 * LDY;
-    if (panel_wave) {
+  // The two roles run separate loops (same number of workgroup barriers), so that the
+  // registers of one role's data do not constrain the other's.
+  if (panel_wave) {
+    for (int p = -1; p < NRB - 1; ++p) {
+      // this step factors panel q = p + 1; panel p (if any) is published in buffer p & 1
+      const int q = p + 1, jq = 16 * q, Kq = Np - jq;
+      double* Yq = Pn0 + (q & 1) * Np * LDY;
+      double* Tq = Tl0 + (q & 1) * 16 * LDY;
       if (p >= 0) {
-        // column block q, updated with panel p, lands in Yq (rows below its R part)
-        const int j0 = 16 * p;
-        update_block_split<(NRBMAX + QR_PANEL_WAVES - 1) / QR_PANEL_WAVES>(
-            NRB - p, j0, q, p == 0, Ab, iperm, Q, Np, Pn0 + (p & 1) * Np * LDY,
-            Tl0 + (p & 1) * 16 * LDY, Yq, wpart, w, lane, cnt, epoch, flag + 1);
+        // column block q (prefetched at the end of the previous step), updated with panel
+        // p, lands in Yq (rows below its R part)
+        apply_block_split<RBQ>(nblk, NRB - p, 16 * p, q, Q, Np, Pn0 + (p & 1) * Np * LDY,
+                               Tl0 + (p & 1) * 16 * LDY, Yq, wpart, w, lane, cnt, epoch, flag + 1);
         panel_sync(cnt, epoch, lane, flag + 1);
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
@@ -611,14 +624,39 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
 #pragma unroll
         for (int j = 0; j < 16; ++j) Tg[(size_t)q * 256 + tid * 16 + j] = trow[j];
       }
-    } else if (p >= 0) {
-      // trailing column blocks q+1 .. with panel p
-      for (int cb = q + 1 + (w - QR_PANEL_WAVES); cb < NRB; cb += QR_THREADS / 64 - QR_PANEL_WAVES)
-        update_block<NRBMAX>(NRB - p, 16 * p, cb, p == 0, Ab, iperm, Q, Np, Pn0 + (p & 1) * Np * LDY,
-                             Tl0 + (p & 1) * 16 * LDY, nullptr, lane);
+      // prefetch the rows of column block q+1 for the next step: from A on the first step,
+      // else from Q once wave 4 has stored it (its first block this step)
+      if (q + 1 < NRB) {
+        if (p >= 0) {
+          int spins = 0;
+          while (__hip_atomic_load(blkrdy, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < p) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > QR_SPIN_LIMIT) { flag[1] = 1; break; }
+          }
+        }
+        prefetch_block<RBQ>(nblk, NRB - q, jq, q + 1, p < 0, Ab, iperm, Q, Np, w, lane);
+      }
+      __threadfence_block();
+      __syncthreads();
     }
-    __threadfence_block();
-    __syncthreads();
+  } else {
+    for (int p = -1; p < NRB - 1; ++p) {
+      const int q = p + 1;
+      if (p >= 0) {
+        // trailing column blocks q+1 .. with panel p; the first (wave 4) is announced to the
+        // panel waves, which prefetch it for the next step
+        for (int cb = q + 1 + (w - QR_PANEL_WAVES); cb < NRB; cb += QR_THREADS / 64 - QR_PANEL_WAVES) {
+          update_block<NRBMAX>(NRB - p, 16 * p, cb, p == 0, Ab, iperm, Q, Np,
+                               Pn0 + (p & 1) * Np * LDY, Tl0 + (p & 1) * 16 * LDY, nullptr, lane);
+          if (cb == q + 1) {
+            __threadfence_block();
+            if (lane == 0) __hip_atomic_store(blkrdy, p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
   }
 
   // ---- outputs: log D, det Q, perm, and the V-update factor in the upper triangle
@@ -722,7 +760,7 @@ hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t
                   int* qsign, int* status, int nb, int Np, hipStream_t st) {
   const size_t lds = (size_t)(2 * Np * LDY + 2 * 16 * LDY + 3 * QR_PANEL_WAVES * 16 + 32 +
                               QR_PANEL_WAVES * 256 + 3 * Np + 8) *
-                         sizeof(double) + (size_t)(Np + 4) * sizeof(int);
+                         sizeof(double) + (size_t)(Np + 6) * sizeof(int);
   hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(QR_THREADS), lds, st, A, astride, norm2, nstride, nparts,
                      logDp, QRW, Tb, perm, logD, qsign, status, Np);
   return hipGetLastError();
