@@ -101,7 +101,11 @@ typedef struct {
  * overlaps the remaining segment products and the V updates.  Results are identical either way; calls from several
  * host threads on one device serialize while they enqueue. */
 enum slmc_flags {
-  SLMC_FLAG_SERIAL = 1  /* run every kernel on the caller's stream, in order            */
+  SLMC_FLAG_SERIAL = 1,  /* run every kernel on the caller's stream, in order           */
+  SLMC_FLAG_STREAM_E = 2 /* SLMC_INT8X5: read every E slice from device memory in each
+                            product, even where E's translation symmetry lets the kernel
+                            keep a few base rows in LDS instead (bitwise the same result;
+                            for checking and measurement)                              */
 };
 
 /* A batch of items, possibly of different models (uneven sizes in one call).

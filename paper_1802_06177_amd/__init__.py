@@ -41,11 +41,14 @@ def model_from_dict(d):
                  d.get("dtau", 0.1), d.get("lam", 1.5), d.get("omega0", 1.0), d.get("c_kin", 0.5))
 
 
-def options(precision="fp64", residual_steps=0, acc_chunk=0, serial=False):
+def options(precision="fp64", residual_steps=0, acc_chunk=0, serial=False, stream_e=False):
     """slmc_options; serial=True keeps every kernel on the caller's stream (no overlap of
-    the segment products with the stabilization chain)."""
+    the segment products with the stabilization chain); stream_e=True makes the int8 path
+    read all of E in every product instead of an LDS copy of its translation-invariant
+    base rows (same result)."""
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    return Options(p, int(residual_steps), int(acc_chunk), _abi.SLMC_FLAG_SERIAL if serial else 0)
+    flags = (_abi.SLMC_FLAG_SERIAL if serial else 0) | (_abi.SLMC_FLAG_STREAM_E if stream_e else 0)
+    return Options(p, int(residual_steps), int(acc_chunk), flags)
 
 
 def eff_model(Jk=0.0, J2=0.0, Jp=0.0, Jp6=0.0, a=0.0, Js=(0.0, 0.0, 0.0), Jt=0.0, delta=0.5):

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libslmc.so")
 SLMC_OK, SLMC_E_ARG, SLMC_E_SHAPE, SLMC_E_WORKSPACE, SLMC_E_DEVICE, SLMC_E_NONFINITE, \
     SLMC_E_UNSUPPORTED = range(7)
 SLMC_FLAG_SERIAL = 1
+SLMC_FLAG_STREAM_E = 2
 SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLAIN, SLMC_INT8X5 = range(6)
 
 EXPORTS = ("slmc_version", "slmc_last_error", "slmc_expk", "slmc_workspace_bytes", "slmc_logdet",

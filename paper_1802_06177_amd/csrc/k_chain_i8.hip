@@ -12,8 +12,18 @@
 // biased (round-to-nearest slices).
 //
 // Workgroup (8 waves) = one (item, segment, 32- or 16-column panel), as in the FP64 kernel: the
-// panel's int8 slices live in LDS, the E slices stream from L2 as the A operand, and the
-// phonon factors of the next slice are applied when the FP64 result is recombined.  The
+// panel's int8 slices live in LDS, the E slices are the A operand, and the phonon factors
+// of the next slice are applied when the FP64 result is recombined.
+//
+// E commutes with the lattice translations (nearest-neighbour hopping on a periodic
+// lattice, SM Eq. S1), and the site order i = x + Lx y makes a translation by one lattice
+// row an index shift by Lx: E[i + s][j + s] = E[i][j] (indices mod N) for every multiple
+// s of Lx.  With N a multiple of 16 and trow = lcm(16, Lx), row block rb (16 rows) of E is
+// base row block rb mod (trow/16), its columns rotated by 16 (rb - rb mod (trow/16)): the
+// kernel keeps the slices of the first trow rows in LDS and reads every A operand there
+// (tab mode), instead of streaming all of E from L2 once per slice product.  The host
+// builds E from the displacement table, so the rotated rows are the same bytes and the
+// result is bitwise that of the streaming mode.  The
 // values are never stored in FP64 between slices: the new column scales come from a
 // column-maximum pass over the accumulators, then the slices are cut from the same
 // accumulators.
@@ -65,20 +75,22 @@ __device__ __forceinline__ void slice5(double y, int shift, uint32_t (&out)[NSL]
 
 constexpr int I8_WAVES = 8;   // two waves per SIMD: one computes while the other waits
 
-template <int RB, int CB>
+template <int RB, int CB, bool TAB>
 __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __restrict__ Eq,
                                                     const double* __restrict__ Esc,
                                                     const double* __restrict__ E64, FieldRef f,
                                                     int nb, int N, int Np, int Npk, int Ltau,
                                                     int n_s, int m, int k0, int kc, double ldl,
                                                     double* __restrict__ S,
-                                                    double* __restrict__ snorm) {
+                                                    double* __restrict__ snorm, int trow,
+                                                    int LDE) {
   constexpr int W = 16 * CB;
   extern __shared__ double lds[];
-  const int LDK = Npk + 16;                     // bytes per slice column (bank spread)
+  constexpr int KBB = NSL * W * 64;             // bytes of one 64-row k block of slices
   double* vbuf = lds;                           // [2][Np]
   double* red = vbuf + 2 * Np;                  // [I8_WAVES][W]
-  int8_t* Bsl = (int8_t*)(red + I8_WAVES * W);  // [NSL][W][LDK]
+  int8_t* Bsl = (int8_t*)(red + I8_WAVES * W);  // [Npk/64][NSL][W][64]
+  int8_t* E0 = Bsl + (Npk >> 6) * KBB;          // tab mode: [NSL][trow][LDE]
   const int npan = Np / W;
   const int id = xcd_remap(blockIdx.x, nb * kc * npan);
   if (id < 0) return;
@@ -95,7 +107,17 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
   // zero the k padding of the slices once (rows Np .. Npk-1 are never written later)
   for (int idx = tid; idx < NSL * W * (Npk - Np); idx += 64 * I8_WAVES) {
     const int pc = idx / (Npk - Np), r = Np + idx - pc * (Npk - Np);
-    Bsl[pc * LDK + r] = 0;
+    Bsl[(r >> 6) * KBB + pc * 64 + (r & 63)] = 0;
+  }
+  if (TAB && len > 1) {
+    // the slices of E's first trow rows, 16-byte chunks from the [row][k block][slice][64]
+    // layout into [slice][row][LDE]
+    const int nkb = Npk >> 6, nch = trow * nkb * NSL * 4;
+    for (int idx = tid; idx < nch; idx += 64 * I8_WAVES) {
+      const int q4 = idx & 3, t = idx >> 2, p = t % NSL, kb = (t / NSL) % nkb, row = t / (NSL * nkb);
+      *(ix4*)(E0 + (p * trow + row) * LDE + 64 * kb + 16 * q4) =
+          *(const ix4*)(Eq + (((size_t)row * nkb + kb) * NSL + p) * 64 + 16 * q4);
+    }
   }
   __syncthreads();
 
@@ -183,7 +205,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
           for (int i = 0; i < 4; ++i) slice5(vals[r][cb][i] * inv[cb], 8 * i, packed);
 #pragma unroll
           for (int p = 0; p < NSL; ++p)
-            *(uint32_t*)(Bsl + (p * W + 16 * cb + c) * LDK + 16 * rb + 4 * g) = packed[p];
+            *(uint32_t*)(Bsl + (rb >> 2) * KBB + (p * W + 16 * cb + c) * 64 + 16 * (rb & 3) + 4 * g) = packed[p];
         }
       }
     }
@@ -213,29 +235,65 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
       for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int d = 0; d < NDIAG; ++d) acc[r][cb][d] = ix4{0, 0, 0, 0};
-    for (int kb = 0; kb < nkb; ++kb) {
+    if constexpr (TAB) {
+      // A operands from the LDS copy of the base rows; the panel's slices stay in registers
+      // across the row blocks
+      const int Nc = Np >> 4, nbase = trow >> 4;
+      for (int kb = 0; kb < nkb; ++kb) {
+        const int8_t* bk = Bsl + kb * KBB + 64 * c + 16 * g;
+        ix4 bq[CB][NSL];
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int rb = w + I8_WAVES * r;
-        if (rb < NRB) {
-          // E slices laid out [row][k block][slice][64 bytes]: one address per row block
-          const int8_t* ep = Eq + ((size_t)(16 * rb + c) * nkb + kb) * (NSL * 64) + 16 * g;
-          ix4 ap[NSL];
+        for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-          for (int p = 0; p < NSL; ++p) ap[p] = *(const ix4*)(ep + 64 * p);
+          for (int q = 0; q < NSL; ++q) bq[cb][q] = *(const ix4*)(bk + (q * W + 16 * cb) * 64);
+        // this lane's 16-column chunk of k; chunks past N meet zero panel rows, any
+        // in-range chunk serves them
+        const int kap = min(4 * kb + g, Nc - 1);
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            // the panel's slices are re-read from LDS per row block (registers are the
-            // scarcer resource)
-            ix4 bq[NSL];
+        for (int r = 0; r < RB; ++r) {
+          const int rb = w + I8_WAVES * r;
+          if (rb < NRB) {
+            const int rb0 = rb % nbase, d = rb - rb0;
+            const int src = kap - d < 0 ? kap - d + Nc : kap - d;
+            const int8_t* ep = E0 + (16 * rb0 + c) * LDE + 16 * src;
+            ix4 ap[NSL];
 #pragma unroll
-            for (int q = 0; q < NSL; ++q)
-              bq[q] = *(const ix4*)(Bsl + (q * W + 16 * cb + c) * LDK + 64 * kb + 16 * g);
+            for (int p = 0; p < NSL; ++p) ap[p] = *(const ix4*)(ep + p * trow * LDE);
 #pragma unroll
-            for (int p = 0; p < NSL; ++p)
+            for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-              for (int q = 0; q + p < NSL; ++q)
-                acc[r][cb][p + q] = mfma_i8(ap[p], bq[q], acc[r][cb][p + q]);
+              for (int p = 0; p < NSL; ++p)
+#pragma unroll
+                for (int q = 0; q + p < NSL; ++q)
+                  acc[r][cb][p + q] = mfma_i8(ap[p], bq[cb][q], acc[r][cb][p + q]);
+          }
+        }
+      }
+    } else {
+      for (int kb = 0; kb < nkb; ++kb) {
+        const int8_t* bk = Bsl + kb * KBB + 64 * c + 16 * g;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int rb = w + I8_WAVES * r;
+          if (rb < NRB) {
+            // E slices laid out [row][k block][slice][64 bytes]: one address per row block
+            const int8_t* ep = Eq + ((size_t)(16 * rb + c) * nkb + kb) * (NSL * 64) + 16 * g;
+            ix4 ap[NSL];
+#pragma unroll
+            for (int p = 0; p < NSL; ++p) ap[p] = *(const ix4*)(ep + 64 * p);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+              // the panel's slices are re-read from LDS per row block (registers are the
+              // scarcer resource)
+              ix4 bq[NSL];
+#pragma unroll
+              for (int q = 0; q < NSL; ++q) bq[q] = *(const ix4*)(bk + (q * W + 16 * cb) * 64);
+#pragma unroll
+              for (int p = 0; p < NSL; ++p)
+#pragma unroll
+                for (int q = 0; q + p < NSL; ++q)
+                  acc[r][cb][p + q] = mfma_i8(ap[p], bq[q], acc[r][cb][p + q]);
+            }
           }
         }
       }
@@ -293,41 +351,56 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
   }
 }
 
-template <int RB, int CB>
+template <int RB, int CB, bool TAB>
 hipError_t run_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f, int nb,
                   int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
-                  double* sn, hipStream_t st) {
+                  double* sn, int trow, int LDE, hipStream_t st) {
   constexpr int W = 16 * CB;
   const int Npk = (Np + 63) / 64 * 64;
   const int count = nb * kc * (Np / W);
-  const size_t lds = (size_t)(2 * Np + I8_WAVES * W) * sizeof(double) + (size_t)NSL * W * (Npk + 16);
-  hipLaunchKernelGGL((seg_chain_i8<RB, CB>), dim3(xcd_grid(count)), dim3(64 * I8_WAVES), lds, st, Eq, Esc,
-                     E64, f, nb, N, Np, Npk, Ltau, n_s, m, k0, kc, ldl, S, sn);
+  const size_t lds = (size_t)(2 * Np + I8_WAVES * W) * sizeof(double) + (size_t)NSL * W * Npk +
+                     (TAB ? (size_t)NSL * trow * LDE : 0);
+  hipLaunchKernelGGL((seg_chain_i8<RB, CB, TAB>), dim3(xcd_grid(count)), dim3(64 * I8_WAVES), lds, st, Eq,
+                     Esc, E64, f, nb, N, Np, Npk, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE);
   return hipGetLastError();
+}
+
+template <int RB, int CB>
+hipError_t pick_tab(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f, int nb,
+                    int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
+                    double* sn, int trow, int LDE, hipStream_t st) {
+  if (trow > 0)
+    return run_i8<RB, CB, true>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
+  return run_i8<RB, CB, false>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, 0, 0, st);
 }
 
 template <int RB>
 hipError_t pick_i8(int CB, const int8_t* Eq, const double* Esc, const double* E64, FieldRef f,
                    int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl,
-                   double* S, double* sn, hipStream_t st) {
-  if (CB == 2) return run_i8<RB, 2>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
-  return run_i8<RB, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
+                   double* S, double* sn, int trow, int LDE, hipStream_t st) {
+  if (CB == 2) return pick_tab<RB, 2>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
+  return pick_tab<RB, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
 }
 
 }  // namespace
 
 hipError_t launch_seg_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f,
                          int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc,
-                         double ldl, double* S, double* snorm, hipStream_t st) {
+                         double ldl, double* S, double* snorm, int trow, hipStream_t st) {
   const int NRB = Np / 16;
   const int RB = (NRB + I8_WAVES - 1) / I8_WAVES;
   // 32-column panels while the accumulators stay small (RB <= 2), 16 beyond
   const int CB = (Np % 32 == 0 && RB <= 2) ? 2 : 1;
+  // tab mode when E repeats every trow rows (a multiple of 16, N unpadded) and the base
+  // rows' slices fit in 64 KB of LDS; LDE = 16 mod 256 keeps the 16-row reads conflict free
+  const int LDE = (N + 255) / 256 * 256 + 16;
+  if (!(trow > 0 && trow % 16 == 0 && trow <= N && N == Np && (size_t)NSL * trow * LDE <= 65536))
+    trow = 0;
   switch (RB) {
-    case 1: return pick_i8<1>(CB, Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
-    case 2: return pick_i8<2>(CB, Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
-    case 3: return run_i8<3, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
-    case 4: return run_i8<4, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
+    case 1: return pick_i8<1>(CB, Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st);
+    case 2: return pick_i8<2>(CB, Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st);
+    case 3: return pick_tab<3, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st);
+    case 4: return pick_tab<4, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -24,11 +24,14 @@ struct FieldRef {
 // 3 bf16x6; 5 int8 slices (5 per operand, 15 products, exact int32 sums).
 // E64/E32/Elo/Ebf/Eq point at the padded exponential in each format (Elo: bf16 of
 // E64 - E32; Ebf: [pieces][Np][Np] bf16 bit patterns; Eq/Esc: int8 slices and row scales).
+// trow > 0: E[i + trow][j + trow] = E[i][j] (indices mod N), trow a multiple of 16; the
+// int8 kernel then reads E's slices from an LDS copy of the first trow rows.  0: no such
+// structure is used.
 hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const float* E32,
                             const uint16_t* Elo, const uint16_t* Ebf, const int8_t* Eq,
                             const double* Esc, FieldRef f, int nb, int N, int Np, int Ltau,
                             int n_s, int m, int k0, int kc, double ldl, double* S, double* snorm,
-                            hipStream_t st);
+                            int trow, hipStream_t st);
 
 // A[b] = Bsrc[b] Q[b] (Q = H_0 ... H_{Np-1} in compact-WY blocks: Householder vectors
 // in the strict lower triangle of QRW[b], T blocks in Tb[b][Np/16][16][16]).

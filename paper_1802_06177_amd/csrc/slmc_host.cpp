@@ -117,7 +117,7 @@ int check_opt(const slmc_options* o) {
   if (o->residual_steps < 0 || o->residual_steps > 1) return fail(SLMC_E_ARG, "residual_steps must be 0 or 1");
   if (!(o->acc_chunk == 0 || o->acc_chunk == 1 || o->acc_chunk == 2 || o->acc_chunk == 4))
     return fail(SLMC_E_ARG, "acc_chunk must be one of 0, 1, 2, 4");
-  if (o->flags & ~SLMC_FLAG_SERIAL) return fail(SLMC_E_ARG, "unknown flags 0x%x", o->flags);
+  if (o->flags & ~(SLMC_FLAG_SERIAL | SLMC_FLAG_STREAM_E)) return fail(SLMC_E_ARG, "unknown flags 0x%x", o->flags);
   return SLMC_OK;
 }
 
@@ -382,6 +382,15 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   // chain below waits only for block k: the chain (one workgroup per item, latency-bound)
   // then runs while the later segment products fill the compute units it leaves idle.
   const uint16_t* Ebf = o->precision == 2 ? mc->Ebf2 : mc->Ebf3;
+  // E is built from the displacement table (site i = x + Lx y), so a shift by any
+  // multiple of Lx rows and columns maps it onto itself: with N a multiple of 16 the row
+  // blocks repeat every lcm(16, Lx) rows
+  int trow = 0;
+  if (N % 16 == 0 && !(o->flags & SLMC_FLAG_STREAM_E)) {
+    int a = 16, b = m->Lx;
+    while (b) { const int t = a % b; a = b; b = t; }
+    if (16 / a * m->Lx <= N) trow = 16 / a * m->Lx;
+  }
   const bool overlap = !(o->flags & SLMC_FLAG_SERIAL) && mseg > 1;
   std::unique_lock<std::mutex> side_lock(g_side_mu, std::defer_lock);
   SideStream* ss = nullptr;
@@ -395,13 +404,13 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     for (int k = 0; k < mseg; ++k) {
       ProfScope ps(0, ss->s);
       HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb, N,
-                              Np, m->Ltau, m->n_s, mseg, k, 1, ldl, w.S, w.snorm, ss->s));
+                              Np, m->Ltau, m->n_s, mseg, k, 1, ldl, w.S, w.snorm, trow, ss->s));
       HIPCHK(hipEventRecord(ss->ev[k], ss->s));
     }
   } else {
     ProfScope ps(0, st);
     HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb, N,
-                            Np, m->Ltau, m->n_s, mseg, 0, mseg, ldl, w.S, w.snorm, st));
+                            Np, m->Ltau, m->n_s, mseg, 0, mseg, ldl, w.S, w.snorm, trow, st));
   }
   // a3: stabilized accumulation
   double* logD[2] = {w.logD0, w.logD1};

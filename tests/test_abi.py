@@ -65,7 +65,7 @@ def test_validation_errors_are_synchronous_codes():
     assert _call_logdet([slmc.model(4, 4, 40, 10, lam=float("nan"))], 2) == _abi.SLMC_E_ARG
     assert _call_logdet([good], 2, opt=slmc.options(precision=7)) == _abi.SLMC_E_ARG
     assert _call_logdet([good], 2, opt=slmc.options(acc_chunk=3)) == _abi.SLMC_E_ARG
-    assert _call_logdet([good], 2, opt=slmc.Options(0, 0, 0, 2)) == _abi.SLMC_E_ARG
+    assert _call_logdet([good], 2, opt=slmc.Options(0, 0, 0, 4)) == _abi.SLMC_E_ARG      # unknown flag
     assert _call_logdet([good], 2, opt=slmc.options(residual_steps=2)) == _abi.SLMC_E_ARG
     assert _call_logdet([good], 2, ws_bytes=0) == _abi.SLMC_E_WORKSPACE
     need = slmc.workspace_bytes(good, 2)

@@ -279,6 +279,29 @@ def test_int8x5_ragged_and_padded_shapes(Lx, Ly, Ltau, n_s):
     _check(md, xs, _run(md, xs, prec="int8x5"), 1e-9, 1e-8)
 
 
+# E is a function of the displacement only, so its row blocks repeat (columns rotated) every
+# lcm(16, Lx) rows when N is a multiple of 16; the int8 kernel then keeps the base rows'
+# slices in LDS.  Integer sums are exact, so the result must equal the streaming mode's
+# bit for bit, and both must meet the oracle bar.
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s", [(16, 16, 40, 8), (12, 12, 36, 10), (8, 6, 24, 6),
+                                             (4, 4, 20, 5), (16, 28, 16, 8), (8, 10, 20, 7)])
+def test_int8x5_lds_base_rows_equal_streamed_bitwise(Lx, Ly, Ltau, n_s):
+    md = _md(Lx, Ltau, n_s, 1.5, Ly=Ly, mu=0.1)
+    g = gen(95, Lx * 1000 + Ly * 100 + Ltau)
+    xs = [g.normal(0.0, 1.5, size=(Ltau, Lx * Ly)) for _ in range(3)]
+    print("case: %dx%d Ltau=%d n_s=%d int8x5 LDS base rows vs streamed E" % (Lx, Ly, Ltau, n_s), flush=True)
+    m = slmc.model_from_dict(md)
+    x = torch.tensor(np.stack(xs), dtype=torch.float64, device=DEV)
+    outs = []
+    for stream_e in (False, True):
+        r = slmc.green(m, x, slmc.options("int8x5", 1, 0, stream_e=stream_e))
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy() for t in r])
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    _check(md, xs[:1], [o[:1] for o in outs[0]], 1e-9, 1e-8)
+
+
 def test_int8x5_staggered_closed_form_16x16():
     import pins
     md = workload_models("W4", 2)[0]
