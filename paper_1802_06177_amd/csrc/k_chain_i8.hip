@@ -4,14 +4,15 @@
 // Every product E P is split into integer pieces: E is scaled per row by a power of two
 // 2^{ea_i} (|E_ik 2^{-ea_i}| < 1/2) and cut into 5 slices of 7 bits each, rounded to
 // nearest (|slice| <= 64), so E = 2^{ea} sum_p A_p 2^{-7p} up to 2^{-36} of the row
-// maximum; the panel P is cut the same way per column.  The products A_p B_q with
+// maximum; the panel P is scaled per column by a power of two and rounded to nearest at
+// 2^{-36} of that scale, then written as 5 signed 7-bit digits.  The products A_p B_q with
 // p + q <= 6 (15 of the 25) are accumulated in int32 on v_mfma_i32_16x16x64_i8, exactly
 // (|entries| <= 64 and K <= 448 keep every sum below 2^31), one accumulator per p + q,
 // and recombined in FP64.  Relative to the row/column maxima the result carries an error
 // of about 2^-36 per product, well below the FP32 matrix cores' rounding, and it is not
 // biased (round-to-nearest slices).
 //
-// Workgroup (8 waves) = one (item, segment, 32- or 16-column panel), as in the FP64 kernel: the
+// Workgroup (4 or 8 waves) = one (item, segment, 32- or 16-column panel), as in the FP64 kernel: the
 // panel's int8 slices live in LDS, the E slices are the A operand, and the phonon factors
 // of the next slice are applied when the FP64 result is recombined.
 //
@@ -45,13 +46,11 @@ __device__ __forceinline__ ix4 mfma_i8(ix4 a, ix4 b, ix4 c) {
 }
 
 // FP64 value of one output element from its 5 diagonal sums (2^-14 .. 2^-42 weights).
+// Each sum is below 2^24 in magnitude (K <= 448 terms of |a b| <= 2^12, at most 5 products
+// per diagonal), so d0 128 + d1 and d2 128 + d3 are exact in int32.
 __device__ __forceinline__ double recombine5(int d0, int d1, int d2, int d3, int d4) {
-  double s = (double)d4 * 0x1p-42;
-  s += (double)d3 * 0x1p-35;
-  s += (double)d2 * 0x1p-28;
-  s += (double)d1 * 0x1p-21;
-  s += (double)d0 * 0x1p-14;
-  return s;
+  const int hi = d0 * 128 + d1, mid = d2 * 128 + d3;
+  return fma((double)hi, 0x1p-21, fma((double)mid, 0x1p-35, (double)d4 * 0x1p-42));
 }
 
 // 2^{e+1} with |m| < 2^e (frexp convention), so |value / scale| < 1/2; 1 for zero.
@@ -62,21 +61,36 @@ __device__ __forceinline__ double pow2_above(double m) {
   return ldexp(1.0, e + 1);
 }
 
-// 5 round-to-nearest 7-bit slices of y (|y| < 64), one byte each, packed per slice into
-// the byte `shift` of out[p].
-__device__ __forceinline__ void slice5(double y, int shift, uint32_t (&out)[NSL]) {
+// The 5 signed 7-bit digits (most significant first) of Y = RNE(v sc), |v sc| < 2^34,
+// for 4 values: byte i of out[p] is digit p of value i, and Y = sum_p d_p 128^{4-p}.
+// Adding 1.5 2^52 leaves Y in the low mantissa bits; adding C = 64 sum_p 128^p turns the
+// signed digits into unsigned 7-bit fields of Y + C (0 <= Y + C < 2^36), which are cut by
+// shifts and masks.  The top field gets 8 bits (digit range [-64, 64]); the others lose
+// their offset byte-parallel: for u in [0, 127], u - 64 as a byte is w | (w & 0x40) << 1
+// with w = u ^ 0x40.
+__host__ __device__ __forceinline__ void slice4x5(const double (&v)[4], double sc,
+                                                  uint32_t (&out)[NSL]) {
+  uint32_t u[NSL] = {0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-  for (int p = 0; p < NSL; ++p) {
-    const double a = rint(y);
-    y = (y - a) * 128.0;
-    out[p] |= ((uint32_t)((int)a) & 0xFFu) << shift;
+  for (int i = 0; i < 4; ++i) {
+    const double t = fma(v[i], sc, 0x1.8p52);
+    const uint64_t z = __builtin_bit_cast(uint64_t, t) + 0x408102040ull;
+    u[0] |= (((uint32_t)(z >> 28) + 192u) & 255u) << (8 * i);
+#pragma unroll
+    for (int p = 1; p < NSL; ++p) u[p] |= ((uint32_t)(z >> (28 - 7 * p)) & 127u) << (8 * i);
+  }
+  out[0] = u[0];
+#pragma unroll
+  for (int p = 1; p < NSL; ++p) {
+    const uint32_t w = u[p] ^ 0x40404040u;
+    out[p] = w | ((w & 0x40404040u) << 1);
   }
 }
 
-constexpr int I8_WAVES = 8;   // two waves per SIMD: one computes while the other waits
-
-template <int RB, int CB, bool TAB>
-__global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __restrict__ Eq,
+// NW waves per workgroup, two waves per SIMD: 8 (one workgroup per CU) or 4 (two
+// workgroups per CU, so that one slices its panel while the other is on the matrix cores)
+template <int NW, int RB, int CB, bool TAB>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __restrict__ Eq,
                                                     const double* __restrict__ Esc,
                                                     const double* __restrict__ E64, FieldRef f,
                                                     int nb, int N, int Np, int Npk, int Ltau,
@@ -88,8 +102,8 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
   extern __shared__ double lds[];
   constexpr int KBB = NSL * W * 64;             // bytes of one 64-row k block of slices
   double* vbuf = lds;                           // [2][Np]
-  double* red = vbuf + 2 * Np;                  // [I8_WAVES][W]
-  int8_t* Bsl = (int8_t*)(red + I8_WAVES * W);  // [Npk/64][NSL][W][64]
+  double* red = vbuf + 2 * Np;                  // [NW][W]
+  int8_t* Bsl = (int8_t*)(red + NW * W);  // [Npk/64][NSL][W][64]
   int8_t* E0 = Bsl + (Npk >> 6) * KBB;          // tab mode: [NSL][trow][LDE]
   const int npan = Np / W;
   const int id = xcd_remap(blockIdx.x, nb * kc * npan);
@@ -105,7 +119,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
   fill_v(vbuf, xb, l0, N, Np, ldl);
   if (len > 1) fill_v(vbuf + Np, xb, l0 + 1, N, Np, ldl);
   // zero the k padding of the slices once (rows Np .. Npk-1 are never written later)
-  for (int idx = tid; idx < NSL * W * (Npk - Np); idx += 64 * I8_WAVES) {
+  for (int idx = tid; idx < NSL * W * (Npk - Np); idx += 64 * NW) {
     const int pc = idx / (Npk - Np), r = Np + idx - pc * (Npk - Np);
     Bsl[(r >> 6) * KBB + pc * 64 + (r & 63)] = 0;
   }
@@ -113,7 +127,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
     // the slices of E's first trow rows, 16-byte chunks from the [row][k block][slice][64]
     // layout into [slice][row][LDE]
     const int nkb = Npk >> 6, nch = trow * nkb * NSL * 4;
-    for (int idx = tid; idx < nch; idx += 64 * I8_WAVES) {
+    for (int idx = tid; idx < nch; idx += 64 * NW) {
       const int q4 = idx & 3, t = idx >> 2, p = t % NSL, kb = (t / NSL) % nkb, row = t / (NSL * nkb);
       *(ix4*)(E0 + (p * trow + row) * LDE + 64 * kb + 16 * q4) =
           *(const ix4*)(Eq + (((size_t)row * nkb + kb) * NSL + p) * 64 + 16 * q4);
@@ -128,7 +142,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
     for (int cb = 0; cb < CB; ++cb) s2[cb] = 0.0;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const int rb = w + I8_WAVES * r;
+      const int rb = w + NW * r;
       if (rb < NRB) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
@@ -152,7 +166,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
     if (tid < W) {
       double t2 = 0.0;
 #pragma unroll
-      for (int ww = 0; ww < I8_WAVES; ++ww) t2 += red[ww * W + tid];
+      for (int ww = 0; ww < NW; ++ww) t2 += red[ww * W + tid];
       nout[c0 + tid] = t2;
     }
     return;
@@ -170,7 +184,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
     for (int cb = 0; cb < CB; ++cb) mx[cb] = 0.0;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
-      if (w + I8_WAVES * r < NRB) {
+      if (w + NW * r < NRB) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
@@ -190,19 +204,18 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
       const int col = 16 * cb + c;
       double v = 0.0;
 #pragma unroll
-      for (int ww = 0; ww < I8_WAVES; ++ww) v = fmax(v, red[ww * W + col]);
+      for (int ww = 0; ww < NW; ++ww) v = fmax(v, red[ww * W + col]);
       fcur[cb] = pow2_above(v);
-      inv[cb] = 128.0 / fcur[cb];
+      inv[cb] = 0x1p35 / fcur[cb];
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const int rb = w + I8_WAVES * r;
+      const int rb = w + NW * r;
       if (rb < NRB) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-          uint32_t packed[NSL] = {0u, 0u, 0u, 0u, 0u};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) slice5(vals[r][cb][i] * inv[cb], 8 * i, packed);
+          uint32_t packed[NSL];
+          slice4x5(vals[r][cb], inv[cb], packed);
 #pragma unroll
           for (int p = 0; p < NSL; ++p)
             *(uint32_t*)(Bsl + (rb >> 2) * KBB + (p * W + 16 * cb + c) * 64 + 16 * (rb & 3) + 4 * g) = packed[p];
@@ -219,8 +232,8 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = 16 * (w + I8_WAVES * r) + drow32(g, i), col = c0 + 16 * cb + c;
-        vals[r][cb][i] = (w + I8_WAVES * r < NRB) ? vbuf[Np + row] * E64[(size_t)row * Np + col] * vbuf[col] : 0.0;
+        const int row = 16 * (w + NW * r) + drow32(g, i), col = c0 + 16 * cb + c;
+        vals[r][cb][i] = (w + NW * r < NRB) ? vbuf[Np + row] * E64[(size_t)row * Np + col] * vbuf[col] : 0.0;
       }
   make_slices();
 
@@ -251,7 +264,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
         const int kap = min(4 * kb + g, Nc - 1);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const int rb = w + I8_WAVES * r;
+          const int rb = w + NW * r;
           if (rb < NRB) {
             const int rb0 = rb % nbase, d = rb - rb0;
             const int src = kap - d < 0 ? kap - d + Nc : kap - d;
@@ -274,7 +287,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
         const int8_t* bk = Bsl + kb * KBB + 64 * c + 16 * g;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const int rb = w + I8_WAVES * r;
+          const int rb = w + NW * r;
           if (rb < NRB) {
             // E slices laid out [row][k block][slice][64 bytes]: one address per row block
             const int8_t* ep = Eq + ((size_t)(16 * rb + c) * nkb + kb) * (NSL * 64) + 16 * g;
@@ -306,10 +319,10 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
         for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int row = 16 * (w + I8_WAVES * r) + drow32(g, i);
+            const int row = 16 * (w + NW * r) + drow32(g, i);
             const double x = recombine5(acc[r][cb][0][i], acc[r][cb][1][i], acc[r][cb][2][i],
                                         acc[r][cb][3][i], acc[r][cb][4][i]);
-            vals[r][cb][i] = (w + I8_WAVES * r < NRB) ? vnext[row] * (Esc[row] * fcur[cb] * x) : 0.0;
+            vals[r][cb][i] = (w + NW * r < NRB) ? vnext[row] * (Esc[row] * fcur[cb] * x) : 0.0;
           }
       make_slices();
     } else {
@@ -318,7 +331,7 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
       for (int cb = 0; cb < CB; ++cb) s2[cb] = 0.0;
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const int rb = w + I8_WAVES * r;
+        const int rb = w + NW * r;
         if (rb < NRB) {
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb)
@@ -344,42 +357,34 @@ __global__ __launch_bounds__(64 * I8_WAVES) void seg_chain_i8(const int8_t* __re
       if (tid < W) {
         double t2 = 0.0;
 #pragma unroll
-        for (int ww = 0; ww < I8_WAVES; ++ww) t2 += red[ww * W + tid];
+        for (int ww = 0; ww < NW; ++ww) t2 += red[ww * W + tid];
         nout[c0 + tid] = t2;
       }
     }
   }
 }
 
-template <int RB, int CB, bool TAB>
+template <int NW, int RB, int CB, bool TAB>
 hipError_t run_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f, int nb,
                   int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
                   double* sn, int trow, int LDE, hipStream_t st) {
   constexpr int W = 16 * CB;
   const int Npk = (Np + 63) / 64 * 64;
   const int count = nb * kc * (Np / W);
-  const size_t lds = (size_t)(2 * Np + I8_WAVES * W) * sizeof(double) + (size_t)NSL * W * Npk +
+  const size_t lds = (size_t)(2 * Np + NW * W) * sizeof(double) + (size_t)NSL * W * Npk +
                      (TAB ? (size_t)NSL * trow * LDE : 0);
-  hipLaunchKernelGGL((seg_chain_i8<RB, CB, TAB>), dim3(xcd_grid(count)), dim3(64 * I8_WAVES), lds, st, Eq,
+  hipLaunchKernelGGL((seg_chain_i8<NW, RB, CB, TAB>), dim3(xcd_grid(count)), dim3(64 * NW), lds, st, Eq,
                      Esc, E64, f, nb, N, Np, Npk, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE);
   return hipGetLastError();
 }
 
-template <int RB, int CB>
+template <int NW, int RB, int CB>
 hipError_t pick_tab(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f, int nb,
                     int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
                     double* sn, int trow, int LDE, hipStream_t st) {
   if (trow > 0)
-    return run_i8<RB, CB, true>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
-  return run_i8<RB, CB, false>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, 0, 0, st);
-}
-
-template <int RB>
-hipError_t pick_i8(int CB, const int8_t* Eq, const double* Esc, const double* E64, FieldRef f,
-                   int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl,
-                   double* S, double* sn, int trow, int LDE, hipStream_t st) {
-  if (CB == 2) return pick_tab<RB, 2>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
-  return pick_tab<RB, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
+    return run_i8<NW, RB, CB, true>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
+  return run_i8<NW, RB, CB, false>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, 0, 0, st);
 }
 
 }  // namespace
@@ -388,21 +393,29 @@ hipError_t launch_seg_i8(const int8_t* Eq, const double* Esc, const double* E64,
                          int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc,
                          double ldl, double* S, double* snorm, int trow, hipStream_t st) {
   const int NRB = Np / 16;
-  const int RB = (NRB + I8_WAVES - 1) / I8_WAVES;
-  // 32-column panels while the accumulators stay small (RB <= 2), 16 beyond
-  const int CB = (Np % 32 == 0 && RB <= 2) ? 2 : 1;
   // tab mode when E repeats every trow rows (a multiple of 16, N unpadded) and the base
   // rows' slices fit in 64 KB of LDS; LDE = 16 mod 256 keeps the 16-row reads conflict free
   const int LDE = (N + 255) / 256 * 256 + 16;
   if (!(trow > 0 && trow % 16 == 0 && trow <= N && N == Np && (size_t)NSL * trow * LDE <= 65536))
     trow = 0;
-  switch (RB) {
-    case 1: return pick_i8<1>(CB, Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st);
-    case 2: return pick_i8<2>(CB, Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st);
-    case 3: return pick_tab<3, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st);
-    case 4: return pick_tab<4, 1>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st);
-    default: return hipErrorInvalidValue;
+#define SEG_I8_ARGS Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st
+  if (NRB <= 16) {
+    // 4 waves, up to 4 row blocks each; 32-column panels while RB <= 2
+    const int RB = (NRB + 3) / 4;
+    const bool cb2 = Np % 32 == 0 && RB <= 2;
+    switch (RB) {
+      case 1: return cb2 ? pick_tab<4, 1, 2>(SEG_I8_ARGS) : pick_tab<4, 1, 1>(SEG_I8_ARGS);
+      case 2: return cb2 ? pick_tab<4, 2, 2>(SEG_I8_ARGS) : pick_tab<4, 2, 1>(SEG_I8_ARGS);
+      case 3: return pick_tab<4, 3, 1>(SEG_I8_ARGS);
+      default: return pick_tab<4, 4, 1>(SEG_I8_ARGS);
+    }
   }
+  // 8 waves, 3 or 4 row blocks each (Np <= 448 gives NRB <= 28)
+  const int RB = (NRB + 7) / 8;
+  if (RB == 3) return pick_tab<8, 3, 1>(SEG_I8_ARGS);
+  if (RB == 4) return pick_tab<8, 4, 1>(SEG_I8_ARGS);
+#undef SEG_I8_ARGS
+  return hipErrorInvalidValue;
 }
 
 }  // namespace slmc

@@ -271,7 +271,8 @@ def test_int8x5_16x16_other_couplings(lam_idx):
 
 
 @pytest.mark.parametrize("Lx,Ly,Ltau,n_s", [(2, 3, 10, 3), (6, 6, 30, 7), (10, 10, 40, 8),
-                                             (12, 12, 36, 10), (20, 20, 16, 8), (4, 4, 20, 1)])
+                                             (12, 12, 36, 10), (18, 18, 16, 8), (20, 20, 16, 8),
+                                             (4, 4, 20, 1)])
 def test_int8x5_ragged_and_padded_shapes(Lx, Ly, Ltau, n_s):
     md = _md(Lx, Ltau, n_s, 1.5, Ly=Ly, mu=0.1)
     g = gen(94, Lx * 1000 + Ly * 100 + Ltau)
