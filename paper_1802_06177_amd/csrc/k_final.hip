@@ -19,6 +19,44 @@ namespace {
 constexpr int LDY = 17;
 constexpr double LN2 = 0.69314718055994530942;
 
+// Pivot search key: the bits of |a| (monotonic for non-negative doubles) with the low 9
+// mantissa bits replaced by 511 - slot, so the largest |a| wins and, among values equal to
+// within 2^-43, the lowest slot.  Never 0 for a live row (slot < 448); NaN sorts above every
+// number, so a NaN column becomes the pivot and is reported.
+__device__ __forceinline__ uint64_t pivot_key(double a, int slot) {
+  return ((uint64_t)__double_as_longlong(fabs(a)) & ~511ull) | (uint64_t)(511 - slot);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+// Maximum over the 64 lanes, returned to every lane: row rotations inside each 16-lane row
+// (DPP row_ror 8, 4, 2, 1), then the permlane16 and permlane32 swaps of two copies, which
+// leave lane l's partner (l ^ 16, then l ^ 32) in the second copy.
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  v = umax64(v, dpp_u64<0x128>(v));
+  v = umax64(v, dpp_u64<0x124>(v));
+  v = umax64(v, dpp_u64<0x122>(v));
+  v = umax64(v, dpp_u64<0x121>(v));
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)v, (uint32_t)v, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(v >> 32), (uint32_t)(v >> 32), false, false);
+    v = umax64(((uint64_t)hi[0] << 32) | lo[0], ((uint64_t)hi[1] << 32) | lo[1]);
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)v, (uint32_t)v, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(v >> 32), (uint32_t)(v >> 32), false, false);
+    v = umax64(((uint64_t)hi[0] << 32) | lo[0], ((uint64_t)hi[1] << 32) | lo[1]);
+  }
+  return v;
+}
+
 __device__ __forceinline__ double xval(const double* QT, const double* V, const double* dbi,
                                        const double* dsm, int Np, int r, int j) {
   return dbi[r] * QT[(size_t)r * Np + j] + dsm[r] * V[(size_t)r * Np + j];
@@ -47,9 +85,12 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
   double* Li = ud + Np;                    // [16][LDY]
   double* Ui = Li + 16 * LDY;              // [16][LDY]
   double* redv = Ui + 16 * LDY;            // [8]
-  int* prow = (int*)(redv + 8);            // [Np]
+  double* cand = redv + 8;                 // [2][4][17]: each wave's pivot candidate row + key
+  int* prow = (int*)(cand + 2 * 4 * 17);   // [Np]
   int* redi = prow + Np;                   // [8]
   int* cnt = redi + 8;                     // [2]: swaps, singular
+  int* phys = cnt + 2;                     // [Np] panel position -> slot
+  int* posof = phys + Np;                  // [Np] slot -> panel position
 
   const double* QTb = QT + (size_t)b * Np * Np;
   const double* Vb = V + (size_t)b * Np * Np;
@@ -73,61 +114,96 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
     const int j0 = 16 * p, K = Np - j0, nrbK = NRB - p;
     double* Pn = Pn0 + (p & 1) * Np * LDY;
     double* Pnx = Pn0 + ((p + 1) & 1) * Np * LDY;
+    // Panel (K rows x 16 columns): thread t keeps slots t and t + 256 in registers.  Rows
+    // never move: a row chosen as pivot leaves the search, and thread 0 keeps the
+    // position <-> slot maps of the equivalent row exchanges (and their count).  One
+    // barrier per column: every wave publishes its best candidate row, every thread then
+    // takes the winner from LDS.
+    const bool h0 = tid < K, h1 = tid + 256 < K;
+    double ra[16], rc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      ra[j] = h0 ? Pn[tid * LDY + j] : 0.0;
+      rc[j] = h1 ? Pn[(tid + 256) * LDY + j] : 0.0;
+    }
+    for (int i = tid; i < K; i += 256) { phys[i] = i; posof[i] = i; }
+    bool a0 = h0, a1 = h1;
+#pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
-      // pivot search over local rows >= cc (largest |a|, lowest row on ties)
-      double bv = -1.0;
-      int bi = 0x7fffffff;
-#pragma unroll 2
-      for (int r = cc + tid; r < K; r += 256) {
-        const double a = fabs(Pn[r * LDY + cc]);
-        if (a > bv) { bv = a; bi = r; }
+      const uint64_t k0 = a0 ? pivot_key(ra[cc], tid) : 0ull;
+      const uint64_t k1 = a1 ? pivot_key(rc[cc], tid + 256) : 0ull;
+      const uint64_t mine = umax64(k0, k1);
+      const uint64_t kw = wave_max_u64(mine);
+      double* cd = cand + (cc & 1) * 68 + w * 17;
+      if (kw != 0ull && mine == kw) {
+        const bool second = (k1 == kw);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) cd[j] = second ? rc[j] : ra[j];
+        cd[16] = __longlong_as_double((long long)kw);
       }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(bv, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
-      if (lane == 0) { redv[w] = bv; redi[w] = bi; }
+      if (kw == 0ull && lane == 0) cd[16] = 0.0;
       __syncthreads();
+      const double* c0 = cand + (cc & 1) * 68;
+      uint64_t best = 0ull;
+      int bw = 0;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        const uint64_t kk = (uint64_t)__double_as_longlong(c0[ww * 17 + 16]);
+        if (kk > best) { best = kk; bw = ww; }
+      }
+      const int sp = 511 - (int)(best & 511ull);
+      double pv[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) pv[j] = c0[bw * 17 + j];
+      const double u = pv[cc];
       if (tid == 0) {
-        double v = redv[0];
-        int pr = redi[0];
-        for (int k = 1; k < 4; ++k)
-          if (redv[k] > v || (redv[k] == v && redi[k] < pr)) { v = redv[k]; pr = redi[k]; }
-        if (pr != cc && pr < K) {
-          for (int j = 0; j < 16; ++j) {
-            const double t = Pn[cc * LDY + j];
-            Pn[cc * LDY + j] = Pn[pr * LDY + j];
-            Pn[pr * LDY + j] = t;
-          }
-          const int t = prow[j0 + cc];
-          prow[j0 + cc] = prow[j0 + pr];
-          prow[j0 + pr] = t;
+        const int q = posof[sp];
+        if (q != cc) {
+          const int s0 = phys[cc];
+          phys[cc] = sp;
+          phys[q] = s0;
+          posof[sp] = cc;
+          posof[s0] = q;
           cnt[0] += 1;
         }
-        const double u = Pn[cc * LDY + cc];
         ud[j0 + cc] = u;
         if (u == 0.0 || u != u) cnt[1] = 1;
       }
-      __syncthreads();
-      {
-        const double u = ud[j0 + cc];
-        const double ui = (u != 0.0) ? 1.0 / u : 0.0;
-        double pv[16];
+      if (sp == tid) a0 = false;
+      if (sp == tid + 256) a1 = false;
+      const double ui = (u != 0.0) ? 1.0 / u : 0.0;
+      if (a0) {
+        const double l = ra[cc] * ui;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          pv[j] = Pn[cc * LDY + j] * (double)(j > cc);
-        }
-        for (int r = cc + 1 + tid; r < K; r += 256) {
-          double* row = Pn + r * LDY;
-          const double l = row[cc] * ui;
-#pragma unroll
-          for (int j = 0; j < 16; ++j) row[j] -= l * pv[j];
-          row[cc] = l;
-        }
+        for (int j = cc + 1; j < 16; ++j) ra[j] -= l * pv[j];
+        ra[cc] = l;
       }
-      __syncthreads();
+      if (a1) {
+        const double l = rc[cc] * ui;
+#pragma unroll
+        for (int j = cc + 1; j < 16; ++j) rc[j] -= l * pv[j];
+        rc[cc] = l;
+      }
     }
+    __syncthreads();   // the position maps are final
+    // the panel back into LDS at its positions; the row map composed with the panel's
+    int pr0 = 0, pr1 = 0;
+    if (h0) {
+      const int q = posof[tid];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) Pn[q * LDY + j] = ra[j];
+      pr0 = prow[j0 + phys[tid]];
+    }
+    if (h1) {
+      const int q = posof[tid + 256];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) Pn[q * LDY + j] = rc[j];
+      pr1 = prow[j0 + phys[tid + 256]];
+    }
+    __syncthreads();
+    if (h0) prow[j0 + tid] = pr0;
+    if (h1) prow[j0 + tid + 256] = pr1;
+    __syncthreads();
     // inverses of the unit-lower L11 (wave 0) and upper U11 (wave 1), one column per lane
     if (w == 0 && lane < 16) {
       const int j = lane;
@@ -415,8 +491,8 @@ template <int NRBMAX>
 hipError_t run_lu(const double* QT, const double* V, const double* logD, const int* qsign,
                   const int* st_in, double* LU, int* prow, double* DI, const int* item_of,
                   double* lo, int8_t* so, int32_t* sto, int nb, int N, int Np, hipStream_t st) {
-  const size_t lds = (size_t)(2 * Np * LDY + 3 * Np + 2 * 16 * LDY + 8) * sizeof(double) +
-                     (size_t)(Np + 10) * sizeof(int);
+  const size_t lds = (size_t)(2 * Np * LDY + 3 * Np + 2 * 16 * LDY + 8 + 2 * 4 * 17) * sizeof(double) +
+                     (size_t)(3 * Np + 10) * sizeof(int);
   hipLaunchKernelGGL(lu_k<NRBMAX>, dim3(nb), dim3(256), lds, st, QT, V, logD, qsign, st_in, LU,
                      prow, DI, item_of, lo, so, sto, N, Np);
   return hipGetLastError();
