@@ -15,8 +15,9 @@ value = chains * steps / time  (fermion log-det + G evaluations per second).
 The headline run uses the mixed path that meets the 1e-8 relative log-det target (segment
 products on the int8 matrix cores with 5-slice splits, everything else FP64); the FP64
 path is timed the same way beside it ("mixed vs FP64").  Also printed: the roofline of
-the dominant kernel (HIP events around its launches on its own stream), and the FP64 CPU
-oracle timed on a bounded sample of the same fields.
+the dominant kernel (HIP events around its launches on its own stream), the roofline of
+the slice-product kernel in the overlapped run and with every kernel run alone, and the
+FP64 CPU oracle timed on a bounded sample of the same fields.
 """
 
 import argparse
@@ -35,7 +36,7 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "int8x5": 15}   # pe
 # HBM bytes per launch of a kernel class at the 16x16 / 128-chain workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain 1 GiB copy
 # (factors 2.0 and 1.0); valid only for the kernel versions they were taken on.
-TRAFFIC = {}
+TRAFFIC = {("qr", "int8x5"): 688.4e6, ("seg_chain", "int8x5"): 74.2e6}
 
 
 def run(slmc, torch, md, eff, xs, B, prec, args):
@@ -104,12 +105,12 @@ def sweep_rates(slmc, torch, np, chains, n_sweeps=4, reps=5):
             "working_set_MB": round(8.0 * chains * Lx * Ly * Lt / 1e6, 1)}
 
 
-def roofline(prof, prec, md, B, steps, counters_apply):
-    """Dominant kernel class (largest event time in the timed region) against its peak:
-    achieved = algorithmic work per launch / average launch time."""
+def roofline(prof, prec, md, B, steps, counters_apply, kernel=None):
+    """A kernel class (default: the dominant one, largest event time in the timed region)
+    against its peak: achieved = algorithmic work per launch / average launch time."""
     N, Lt, n_s = md["Lx"] * md["Ly"], md["Ltau"], md["n_s"]
     nseg = (Lt + n_s - 1) // n_s
-    dom = max(prof, key=lambda k: prof[k][0])
+    dom = kernel or max(prof, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     # per-evaluation algorithmic flops of each class (FP64-equivalent)
     per_eval = {
@@ -190,6 +191,21 @@ def main():
     roof = roofline(main_run["prof"], args.precision, md, B, args.steps,
                     counters_apply=(B == 128 and args.lam == 1.5))
 
+    # the slice-product kernel on its own: its event times in the overlapped run include the
+    # time it shares the compute units with the QR chain, so it is also timed with the
+    # serial schedule (every kernel alone on the caller's stream)
+    seg_rate = None
+    if "seg_chain" in main_run["prof"]:
+        keep = ("kernel", "bound", "achieved", "peak", "unit", "frac", "avg_launch_ms")
+        r_over = roofline(main_run["prof"], args.precision, md, B, args.steps, False, "seg_chain")
+        seg_rate = {"schedule_" + ("serial" if args.serial else "overlapped"): {k: r_over[k] for k in keep}}
+        if not args.serial:
+            args_alone = argparse.Namespace(**vars(args))
+            args_alone.serial = True
+            r_al = run(slmc, torch, md, eff, xs, B, args.precision, args_alone)
+            r_alone = roofline(r_al["prof"], args.precision, md, B, args.steps, False, "seg_chain")
+            seg_rate["schedule_serial"] = {k: r_alone[k] for k in keep}
+
     fp64 = None
     if args.precision != "fp64" and not args.no_fp64:
         r64 = run(slmc, torch, md, eff, xs, B, "fp64", args)
@@ -239,7 +255,8 @@ def main():
                    "precision": args.precision, "acc_chunk": args.acc_chunk,
                    "residual_steps": args.residual, "global_batch": B, "parallelism": "none",
                    "schedule": "serial" if args.serial else "overlapped"},
-        "roofline": roof, "cpu_baseline": cpu, "error_vs_oracle": err, "fp64_path": fp64,
+        "roofline": roof, "slice_products": seg_rate, "cpu_baseline": cpu, "error_vs_oracle": err,
+        "fp64_path": fp64,
         "sweep_only": sweep,
         "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
     }

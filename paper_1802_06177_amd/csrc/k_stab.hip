@@ -754,6 +754,150 @@ __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
   }
 }
 
+// A = B Q for Np <= 256: one wave per 16-row panel of B, the 4 panels of one item sharing
+// a workgroup.  The panel lives in registers as the 16x16 tiles of B^T in the matrix-core
+// accumulator layout (lane (g, c), register v: B^T[16t + g + 4v][c]), which is also the
+// layout of a B operand (k = g + 4s for slice s).  With Y_p the block of Householder
+// vectors and T_p its compact-WY factor,
+//   W^T = Y_p^T B^T,  W'^T = T_p^T W^T,  B^T -= Y_p W'^T
+// apply (I - Y_p T_p Y_p^T) from the right, block after block, without a transpose.  Y_p
+// is staged in LDS for the 4 waves; the next block is loaded into registers while the
+// current one is applied.
+constexpr int LDW = 18;   // row stride of the per-wave 16x16 transpose buffers
+
+template <int NRBMAX>
+__global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restrict__ Bsrc,
+                                                      int64_t bstride,
+                                                      const double* __restrict__ QRW,
+                                                      const double* __restrict__ Tb,
+                                                      double* __restrict__ A,
+                                                      double* __restrict__ npart,
+                                                      int transpose_out, int nb, int Np) {
+  extern __shared__ double lds[];
+  constexpr int LY = 17;                   // Y_p row stride (odd: conflict-free columns)
+  const int NRB = Np >> 4, npg = (NRB + 3) >> 2;
+  double* Ys = lds;                        // [Np][LY]: rows j0 .. Np-1 of block p, local
+  double* wb = Ys + Np * LY + (threadIdx.x >> 6) * 16 * LDW;   // [16][LDW] of this wave
+  const int id = xcd_remap(blockIdx.x, nb * npg);
+  if (id < 0) return;
+  const int b = id / npg, tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4,
+            c = lane & 15;
+  const int rp = 4 * (id % npg) + w, r0 = 16 * rp;
+  const bool act = rp < NRB;
+  const double* Y = QRW + (size_t)b * Np * Np;
+  const double* T = Tb + (size_t)b * NRB * 256;
+
+  dx4 bt[NRBMAX];
+#pragma unroll
+  for (int t = 0; t < NRBMAX; ++t) {
+    bt[t] = zero4d();
+    if (t < NRB && act) {
+      if (Bsrc) {
+        // a 16x16 tile of B, coalesced, turned around in the wave's LDS buffer
+        const double* src = Bsrc + (size_t)b * bstride + (size_t)(r0 + (lane >> 2)) * Np + 16 * t +
+                            4 * (lane & 3);
+        const double2 x01 = ((const double2*)src)[0], x23 = ((const double2*)src)[1];
+        double* d = wb + (lane >> 2) * LDW + 4 * (lane & 3);
+        ((double2*)d)[0] = x01;
+        ((double2*)d)[1] = x23;
+        wave_lds_fence();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bt[t][v] = wb[c * LDW + g + 4 * v];
+        wave_lds_fence();
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bt[t][v] = (r0 + c == 16 * t + g + 4 * v) ? 1.0 : 0.0;
+      }
+    }
+  }
+
+  // block p of Y (rows 16p .. Np-1, columns 16p .. 16p+15; unit lower on top), one element
+  // per (thread, i): local row (tid + 256 i) >> 4, column (tid + 256 i) & 15
+  double yp[NRBMAX];
+  auto yload = [&](int p) {
+    const int j0 = 16 * p, K = Np - j0;
+#pragma unroll
+    for (int i = 0; i < NRBMAX; ++i) {
+      const int idx = tid + 256 * i, r = idx >> 4, m = idx & 15;
+      yp[i] = 0.0;
+      if (r < K) {
+        const double y = Y[(size_t)(j0 + r) * Np + j0 + m];
+        yp[i] = r > 15 ? y : (r > m ? y : (r == m ? 1.0 : 0.0));
+      }
+    }
+  };
+  auto ystore = [&](int p) {
+    const int K = Np - 16 * p;
+#pragma unroll
+    for (int i = 0; i < NRBMAX; ++i) {
+      const int idx = tid + 256 * i, r = idx >> 4, m = idx & 15;
+      if (r < K) Ys[r * LY + m] = yp[i];
+    }
+  };
+  yload(0);
+  ystore(0);
+  __syncthreads();
+
+  for (int p = 0; p < NRB; ++p) {
+    if (p + 1 < NRB) yload(p + 1);
+    if (act) {
+      dx4 wt = zero4d();
+#pragma unroll
+      for (int kb = 0; kb < NRBMAX; ++kb) {
+        if (kb >= p && kb < NRB) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            wt = mfma64(Ys[(16 * (kb - p) + 4 * s + g) * LY + c], bt[kb][s], wt);
+        }
+      }
+      dx4 wp = zero4d();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) wp = mfma64(T[(size_t)p * 256 + (4 * s + g) * 16 + c], wt[s], wp);
+#pragma unroll
+      for (int cb = 0; cb < NRBMAX; ++cb) {
+        if (cb >= p && cb < NRB) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            bt[cb] = mfma64(-Ys[(16 * (cb - p) + c) * LY + 4 * s + g], wp[s], bt[cb]);
+        }
+      }
+    }
+    __syncthreads();   // every wave is done with Y_p
+    if (p + 1 < NRB) {
+      ystore(p + 1);
+      __syncthreads();
+    }
+  }
+
+  if (!act) return;
+  double* out = A + (size_t)b * Np * Np;
+#pragma unroll
+  for (int t = 0; t < NRBMAX; ++t) {
+    if (t < NRB) {
+      if (transpose_out) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[(size_t)(16 * t + g + 4 * v) * Np + r0 + c] = bt[t][v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wb[c * LDW + g + 4 * v] = bt[t][v];
+        wave_lds_fence();
+        const double* sp = wb + (lane >> 2) * LDW + 4 * (lane & 3);
+        double* dst = out + (size_t)(r0 + (lane >> 2)) * Np + 16 * t + 4 * (lane & 3);
+        ((double2*)dst)[0] = ((const double2*)sp)[0];
+        ((double2*)dst)[1] = ((const double2*)sp)[1];
+        wave_lds_fence();
+      }
+      if (npart) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double s2 = sum16(bt[t][v] * bt[t][v]);
+          if (c == 0) npart[((size_t)b * NRB + rp) * Np + 16 * t + g + 4 * v] = s2;
+        }
+      }
+    }
+  }
+}
+
 template <int NRBMAX>
 hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride, int nparts,
                   const double* logDp, double* QRW, double* Tb, int* perm, double* logD,
@@ -799,6 +943,19 @@ hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QR
                            const double* Tb, double* A, double* npart, int transpose_out,
                            int nb, int Np, hipStream_t st) {
   const int NRB = Np / 16;
+  if (NRB <= 16) {
+    // register-resident panels (Np <= 256)
+    const int npg = (NRB + 3) / 4;
+    const size_t lds_r = (size_t)(Np * 17 + 4 * 16 * LDW) * sizeof(double);
+#define WY_REG(NR)                                                                              \
+  hipLaunchKernelGGL(wy_apply_reg_k<NR>, dim3(xcd_grid(nb * npg)), dim3(256), lds_r, st, Bsrc,   \
+                     bstride, QRW, Tb, A, npart, transpose_out, nb, Np)
+    if (NRB <= 4) WY_REG(4);
+    else if (NRB <= 8) WY_REG(8);
+    else WY_REG(16);
+#undef WY_REG
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(16 * (Np + 2) + 5 * 16 * LDY) * sizeof(double);
   hipLaunchKernelGGL(wy_apply_k, dim3(xcd_grid(nb * NRB)), dim3(256), lds, st, Bsrc, bstride,
                      QRW, Tb, A, npart, transpose_out, nb, Np);
