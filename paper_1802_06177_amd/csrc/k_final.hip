@@ -413,6 +413,141 @@ __global__ __launch_bounds__(256) void lu_solve_k(int mode, const double* __rest
   }
 }
 
+// The same solve for Np <= 256 with 4 right-hand-side strips of one item per workgroup:
+// the 16 rows of L (forward) or U (backward) that block row rb needs are staged in LDS
+// once for the 4 waves (rows gathered through the pivot map, each row read coalesced),
+// double-buffered, the next block row loaded into registers while the current one is
+// applied: one barrier per block row.
+template <int NRBMAX>
+__global__ __launch_bounds__(256, 2) void lu_solve_lds_k(int mode, const double* __restrict__ QT,
+                                                         const double* __restrict__ logD,
+                                                         const double* __restrict__ R,
+                                                         const double* __restrict__ LU,
+                                                         const int* __restrict__ prow,
+                                                         const double* __restrict__ DI,
+                                                         double* __restrict__ Gint, int accumulate,
+                                                         double* __restrict__ Gout,
+                                                         const int64_t* __restrict__ goff, int nb,
+                                                         int N, int Np) {
+  extern __shared__ double lds[];
+  const int LDL = Np + 1;                  // odd row stride: the 16 rows of a slice spread over banks
+  const int NRB = Np >> 4, npg = (NRB + 3) >> 2;
+  const int id = xcd_remap(blockIdx.x, nb * npg);
+  if (id < 0) return;
+  const int b = id / npg, tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4,
+            c = lane & 15;
+  const int cb = 4 * (id % npg) + w;
+  const bool act = cb < NRB;
+  const double* Lb = LU + (size_t)b * Np * Np;
+  const int* pb = prow + (size_t)b * Np;
+  const double* DIb = DI + (size_t)b * NRB * 512;
+  const int col = 16 * cb + c;
+
+  dx4 y[NRBMAX];
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    y[rb] = zero4d();
+    if (rb < NRB && act) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pr = pb[16 * rb + drow64(g, v)];
+        if (mode == 0)
+          y[rb][v] = exp(-fmax(logD[(size_t)b * Np + pr], 0.0)) * QT[(size_t)b * Np * Np + (size_t)pr * Np + col];
+        else
+          y[rb][v] = R[(size_t)b * Np * Np + (size_t)pr * Np + col];
+      }
+    }
+  }
+
+  // staging of block row rb: row i of the block (factor row pb[16 rb + i]), columns
+  // [lo, hi): thread tid holds column tid of each of the 16 rows
+  double st[16];
+  auto sload = [&](int rb, int lo, int hi) {
+    const bool in = tid >= lo && tid < hi;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) st[i] = in ? Lb[(size_t)pb[16 * rb + i] * Np + tid] : 0.0;
+  };
+  auto sstore = [&](int buf, int lo, int hi) {
+    double* Ls = lds + buf * 16 * LDL;
+    if (tid >= lo && tid < hi) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Ls[i * LDL + tid] = st[i];
+    }
+  };
+
+  // forward: L y = P rhs (columns 0 .. 16 rb - 1 of block row rb)
+  sload(0, 0, 0);
+  for (int rb = 0; rb < NRB; ++rb) {
+    if (rb + 1 < NRB) sload(rb + 1, 0, 16 * (rb + 1));
+    if (act) {
+      const double* Ls = lds + (rb & 1) * 16 * LDL;
+#pragma unroll
+      for (int k = 0; k < NRBMAX; ++k) {
+        if (k == rb) {
+          dx4 t = y[k];
+#pragma unroll
+          for (int kb = 0; kb < k; ++kb) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) t = mfma64(-Ls[c * LDL + 16 * kb + drow64(g, s)], y[kb][s], t);
+          }
+          dx4 nv = zero4d();
+#pragma unroll
+          for (int s = 0; s < 4; ++s) nv = mfma64(DIb[(size_t)k * 512 + c * 16 + drow64(g, s)], t[s], nv);
+          y[k] = nv;
+        }
+      }
+    }
+    if (rb + 1 < NRB) sstore((rb + 1) & 1, 0, 16 * (rb + 1));
+    __syncthreads();
+  }
+  // backward: U x = y (columns 16 (rb + 1) .. Np - 1 of block row rb)
+  sload(NRB - 1, Np, Np);
+  for (int rb = NRB - 1; rb >= 0; --rb) {
+    const int buf = (NRB - 1 - rb) & 1;
+    if (rb > 0) sload(rb - 1, 16 * rb, Np);
+    if (act) {
+      const double* Ls = lds + buf * 16 * LDL;
+#pragma unroll
+      for (int k = 0; k < NRBMAX; ++k) {
+        if (k == rb) {
+          dx4 t = y[k];
+#pragma unroll
+          for (int kb = k + 1; kb < NRBMAX; ++kb) {
+            if (kb < NRB) {
+#pragma unroll
+              for (int s = 0; s < 4; ++s) t = mfma64(-Ls[c * LDL + 16 * kb + drow64(g, s)], y[kb][s], t);
+            }
+          }
+          dx4 nv = zero4d();
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            nv = mfma64(DIb[(size_t)k * 512 + 256 + c * 16 + drow64(g, s)], t[s], nv);
+          y[k] = nv;
+        }
+      }
+    }
+    if (rb > 0) sstore(buf ^ 1, 16 * rb, Np);
+    __syncthreads();
+  }
+
+  if (!act) return;
+  double* Gi = Gint + (size_t)b * Np * Np;
+  double* Go = Gout ? Gout + (goff ? goff[b] : (int64_t)b * N * N) : nullptr;
+#pragma unroll
+  for (int rb = 0; rb < NRBMAX; ++rb) {
+    if (rb < NRB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rb + drow64(g, v);
+        double val = y[rb][v];
+        if (accumulate) val += Gi[(size_t)row * Np + col];
+        Gi[(size_t)row * Np + col] = val;
+        if (Go && row < N && col < N) Go[(size_t)row * N + col] = val;
+      }
+    }
+  }
+}
+
 // R = Db^{-1} U^T - X G for every item, X = Db^{-1} U^T + Ds V formed while the tiles are
 // staged: a batched GEMM with 64 x 64 output tiles per workgroup (4 waves of 32 x 32) and
 // k steps of 16 through LDS.
@@ -502,6 +637,13 @@ template <int NRBMAX>
 hipError_t run_solve(int mode, const double* QT, const double* logD, const double* R,
                      const double* LU, const int* prow, const double* DI, double* Gint, int acc,
                      double* Gout, const int64_t* goff, int nb, int N, int Np, hipStream_t st) {
+  if (NRBMAX <= 16) {
+    const int npg = (Np / 16 + 3) / 4;
+    const size_t lds = (size_t)2 * 16 * (Np + 1) * sizeof(double);
+    hipLaunchKernelGGL(lu_solve_lds_k<NRBMAX <= 16 ? NRBMAX : 16>, dim3(xcd_grid(nb * npg)), dim3(256), lds,
+                       st, mode, QT, logD, R, LU, prow, DI, Gint, acc, Gout, goff, nb, N, Np);
+    return hipGetLastError();
+  }
   const int waves = nb * (Np / 16);
   hipLaunchKernelGGL(lu_solve_k<NRBMAX>, dim3((waves + 3) / 4), dim3(256), 0, st, mode, QT, logD,
                      R, LU, prow, DI, Gint, acc, Gout, goff, nb, N, Np);

@@ -718,14 +718,21 @@ __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
   for (int r = 0; r < RB; ++r)
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[r][cb] = zero4d();
+  // row blocks in zigzag order (w, 7 - w, 8 + w, ...): the triangle's rows are shared
+  // evenly by the 4 waves; F's next 16-column slice is loaded while the current one is used
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    const int rb = w + 4 * r;
+    const int rb = (r & 1) ? 4 * r + 3 - w : 4 * r + w;
     if (rb >= NRB) continue;
+    const double* frow = F + (size_t)(16 * rb + c) * Np + 4 * g;
+    double2 n01 = ((const double2*)(frow + 16 * rb))[0], n23 = ((const double2*)(frow + 16 * rb))[1];
     for (int kb = rb; kb < NRB; ++kb) {
       const int q0 = 16 * kb + 4 * g;
-      const double* fr = F + (size_t)(16 * rb + c) * Np + q0;
-      const double2 f01 = ((const double2*)fr)[0], f23 = ((const double2*)fr)[1];
+      const double2 f01 = n01, f23 = n23;
+      if (kb + 1 < NRB) {
+        n01 = ((const double2*)(frow + 16 * (kb + 1)))[0];
+        n23 = ((const double2*)(frow + 16 * (kb + 1)))[1];
+      }
       double av[4] = {f01.x, f01.y, f23.x, f23.y};
       if (kb == rb) {
 #pragma unroll
@@ -744,7 +751,7 @@ __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
   double* out = Vn + (size_t)b * Np * Np;
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    const int rb = w + 4 * r;
+    const int rb = (r & 1) ? 4 * r + 3 - w : 4 * r + w;
     if (rb >= NRB) continue;
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
