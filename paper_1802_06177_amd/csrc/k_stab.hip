@@ -537,6 +537,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   // ---- pre-pivoting: order columns by log ||A e_j|| + log D_prev[j], descending
   for (int j = tid; j < Np; j += QR_THREADS) {
     double s = 0.0;
+#pragma unroll 4
     for (int p = 0; p < nparts; ++p) s += norm2[(size_t)b * nstride + (size_t)p * Np + j];
     double kj = 0.5 * log(s) + (logDp ? logDp[(size_t)b * Np + j] : 0.0);
     if (kj != kj) { kj = -INFINITY; flag[0] = 1; }
@@ -546,6 +547,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   for (int j = tid; j < Np; j += QR_THREADS) {
     const double kj = key[j];
     int r = 0;
+#pragma unroll 8
     for (int jj = 0; jj < Np; ++jj) {
       const double kk = key[jj];
       r += (kk > kj) || (kk == kj && jj < j);
@@ -676,14 +678,19 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
     if (flag[0]) status[b] |= 1;
     if (flag[1]) status[b] |= 8;
   }
-  for (int idx = tid; idx < Np * Np; idx += QR_THREADS) {
+  // two adjacent entries of a row per thread and step (16-byte accesses), several steps in
+  // flight: this pass is on the chain's critical path
+#pragma unroll 4
+  for (int idx = 2 * tid; idx < Np * Np; idx += 2 * QR_THREADS) {
     const int i = idx / Np, j = idx - i * Np;
-    if (j >= i) {
-      const double bi = beta[i];
-      double fv;
-      if (j == i) fv = bi < 0.0 ? -1.0 : 1.0;
-      else fv = Q[(size_t)i * Np + j] / fabs(bi) * exp(key[j] - key[i]);
-      Q[(size_t)i * Np + j] = fv;
+    if (j + 1 >= i) {
+      double2* qp = (double2*)(Q + (size_t)i * Np + j);
+      const double2 r = *qp;
+      const double bi = beta[i], ibi = 1.0 / fabs(bi), ki = key[i];
+      double2 f;
+      f.x = (j > i) ? r.x * ibi * exp(key[j] - ki) : (j == i ? (bi < 0.0 ? -1.0 : 1.0) : r.x);
+      f.y = (j + 1 > i) ? r.y * ibi * exp(key[j + 1] - ki) : (bi < 0.0 ? -1.0 : 1.0);
+      *qp = f;
     }
   }
 }
@@ -768,8 +775,8 @@ __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
 // vectors and T_p its compact-WY factor,
 //   W^T = Y_p^T B^T,  W'^T = T_p^T W^T,  B^T -= Y_p W'^T
 // apply (I - Y_p T_p Y_p^T) from the right, block after block, without a transpose.  Y_p
-// is staged in LDS for the 4 waves; the next block is loaded into registers while the
-// current one is applied.
+// and T_p are staged in LDS for the 4 waves; the next block is loaded into registers while
+// the current one is applied.
 constexpr int LDW = 18;   // row stride of the per-wave 16x16 transpose buffers
 
 template <int NRBMAX>
@@ -784,7 +791,8 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
   constexpr int LY = 17;                   // Y_p row stride (odd: conflict-free columns)
   const int NRB = Np >> 4, npg = (NRB + 3) >> 2;
   double* Ys = lds;                        // [Np][LY]: rows j0 .. Np-1 of block p, local
-  double* wb = Ys + Np * LY + (threadIdx.x >> 6) * 16 * LDW;   // [16][LDW] of this wave
+  double* Ts = Ys + Np * LY;               // [256]: T_p
+  double* wb = Ts + 256 + (threadIdx.x >> 6) * 16 * LDW;   // [16][LDW] of this wave
   const int id = xcd_remap(blockIdx.x, nb * npg);
   if (id < 0) return;
   const int b = id / npg, tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4,
@@ -820,9 +828,10 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
 
   // block p of Y (rows 16p .. Np-1, columns 16p .. 16p+15; unit lower on top), one element
   // per (thread, i): local row (tid + 256 i) >> 4, column (tid + 256 i) & 15
-  double yp[NRBMAX];
+  double yp[NRBMAX], tpre;
   auto yload = [&](int p) {
     const int j0 = 16 * p, K = Np - j0;
+    tpre = T[(size_t)p * 256 + tid];
 #pragma unroll
     for (int i = 0; i < NRBMAX; ++i) {
       const int idx = tid + 256 * i, r = idx >> 4, m = idx & 15;
@@ -840,6 +849,7 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
       const int idx = tid + 256 * i, r = idx >> 4, m = idx & 15;
       if (r < K) Ys[r * LY + m] = yp[i];
     }
+    Ts[tid] = tpre;
   };
   yload(0);
   ystore(0);
@@ -859,7 +869,7 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
       }
       dx4 wp = zero4d();
 #pragma unroll
-      for (int s = 0; s < 4; ++s) wp = mfma64(T[(size_t)p * 256 + (4 * s + g) * 16 + c], wt[s], wp);
+      for (int s = 0; s < 4; ++s) wp = mfma64(Ts[(4 * s + g) * 16 + c], wt[s], wp);
 #pragma unroll
       for (int cb = 0; cb < NRBMAX; ++cb) {
         if (cb >= p && cb < NRB) {
@@ -953,7 +963,7 @@ hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QR
   if (NRB <= 16) {
     // register-resident panels (Np <= 256)
     const int npg = (NRB + 3) / 4;
-    const size_t lds_r = (size_t)(Np * 17 + 4 * 16 * LDW) * sizeof(double);
+    const size_t lds_r = (size_t)(Np * 17 + 256 + 4 * 16 * LDW) * sizeof(double);
 #define WY_REG(NR)                                                                              \
   hipLaunchKernelGGL(wy_apply_reg_k<NR>, dim3(xcd_grid(nb * npg)), dim3(256), lds_r, st, Bsrc,   \
                      bstride, QRW, Tb, A, npart, transpose_out, nb, Np)
