@@ -36,7 +36,7 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "int8x5": 15}   # pe
 # HBM bytes per launch of a kernel class at the 16x16 / 128-chain workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain 1 GiB copy
 # (factors 2.0 and 1.0); valid only for the kernel versions they were taken on.
-TRAFFIC = {("qr", "int8x5"): 688.4e6, ("seg_chain", "int8x5"): 74.2e6}
+TRAFFIC = {("qr", "int8x5"): 688.5e6, ("seg_chain", "int8x5"): 74.2e6}
 
 
 def run(slmc, torch, md, eff, xs, B, prec, args):
@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="keep the segment products on the caller's stream (no overlap)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-alone", action="store_true",
+                    help="skip the serial-schedule run of the slice-product kernel")
     ap.add_argument("--cpu-sample", type=int, default=6, help="oracle items for cpu_baseline (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (reference "
@@ -199,7 +201,7 @@ def main():
         keep = ("kernel", "bound", "achieved", "peak", "unit", "frac", "avg_launch_ms")
         r_over = roofline(main_run["prof"], args.precision, md, B, args.steps, False, "seg_chain")
         seg_rate = {"schedule_" + ("serial" if args.serial else "overlapped"): {k: r_over[k] for k in keep}}
-        if not args.serial:
+        if not args.serial and not args.no_alone:
             args_alone = argparse.Namespace(**vars(args))
             args_alone.serial = True
             r_al = run(slmc, torch, md, eff, xs, B, args.precision, args_alone)
