@@ -10,7 +10,7 @@
 //   wy_apply : A = B Q with Q in compact-WY blocks, row panels across all CUs.
 //   qr       : blocked Householder QR, one workgroup per item; the trailing update keeps
 //              each 16-column block in the registers of one wave and runs on FP64 MFMA.
-//   vupd     : V_k = F P^T V_{k-1}, an upper-triangular column-panel GEMM.
+//   vupd     : V_k = F P^T V_{k-1}, an upper-triangular GEMM (register strips for Np <= 256).
 #include "common.h"
 #include "launch.h"
 
@@ -915,6 +915,82 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
   }
 }
 
+// V_new = F P^T V_old for Np <= 256: one wave per 16-column strip, the 4 strips of one
+// item per workgroup.  The strip of W = P^T V_old (rows gathered through the permutation)
+// stays in registers as 16x16 tiles in the accumulator layout, which is the B-operand
+// layout; the 16 rows of F that block row rb needs (columns 16 rb .. Np-1, the stored
+// Householder vectors below the diagonal masked to zero) are staged in LDS once for the 4
+// waves, double-buffered with the next block row in registers, and each output tile is
+// finished and stored before the next block row.
+template <int NRBMAX>
+__global__ __launch_bounds__(256, 2) void vupd_strip_k(const double* __restrict__ QRW,
+                                                       const int* __restrict__ perm,
+                                                       const double* __restrict__ Vo,
+                                                       double* __restrict__ Vn, int nb, int Np) {
+  extern __shared__ double lds[];
+  const int LDF = Np + 1;                  // odd row stride: the 16 rows of a slice spread over banks
+  const int NRB = Np >> 4, npg = (NRB + 3) >> 2;
+  const int id = xcd_remap(blockIdx.x, nb * npg);
+  if (id < 0) return;
+  const int b = id / npg, tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4,
+            c = lane & 15;
+  const int cs = 4 * (id % npg) + w, col = 16 * cs + c;
+  const bool act = cs < NRB;
+  const double* F = QRW + (size_t)b * Np * Np;
+  const int* pb = perm + (size_t)b * Np;
+
+  dx4 wt[NRBMAX];
+#pragma unroll
+  for (int kb = 0; kb < NRBMAX; ++kb) {
+    wt[kb] = zero4d();
+    if (kb < NRB && act) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int src = pb[16 * kb + g + 4 * v];
+        wt[kb][v] = Vo ? Vo[(size_t)b * Np * Np + (size_t)src * Np + col] : (src == col ? 1.0 : 0.0);
+      }
+    }
+  }
+  // block row rb of F: thread tid holds column tid of its 16 rows
+  double st[16];
+  auto fload = [&](int rb) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = 16 * rb + i;
+      st[i] = (tid >= row && tid < Np) ? F[(size_t)row * Np + tid] : 0.0;
+    }
+  };
+  auto fstore = [&](int buf, int rb) {
+    double* Fs = lds + buf * 16 * LDF;
+    if (tid >= 16 * rb && tid < Np) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Fs[i * LDF + tid] = st[i];
+    }
+  };
+  fload(0);
+  fstore(0, 0);
+  __syncthreads();
+  double* out = Vn + (size_t)b * Np * Np;
+  for (int rb = 0; rb < NRB; ++rb) {
+    if (rb + 1 < NRB) fload(rb + 1);
+    if (act) {
+      const double* Fs = lds + (rb & 1) * 16 * LDF;
+      dx4 acc = zero4d();
+#pragma unroll
+      for (int kb = 0; kb < NRBMAX; ++kb) {
+        if (kb >= rb && kb < NRB) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc = mfma64(Fs[c * LDF + 16 * kb + 4 * s + g], wt[kb][s], acc);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(size_t)(16 * rb + g + 4 * v) * Np + col] = acc[v];
+    }
+    if (rb + 1 < NRB) fstore((rb + 1) & 1, rb + 1);
+    __syncthreads();
+  }
+}
+
 template <int NRBMAX>
 hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride, int nparts,
                   const double* logDp, double* QRW, double* Tb, int* perm, double* logD,
@@ -994,6 +1070,19 @@ hipError_t launch_qr(const double* A, int64_t astride, const double* norm2, int6
 hipError_t launch_vupd(const double* QRW, const int* perm, const double* Vo, double* Vn, int nb,
                        int Np, hipStream_t st) {
   const int NRB = Np / 16, RB = (NRB + 3) / 4;
+  if (NRB <= 16) {
+    // register-resident strips (Np <= 256)
+    const int npg = (NRB + 3) / 4;
+    const size_t lds = (size_t)2 * 16 * (Np + 1) * sizeof(double);
+#define VUPD_STRIP(NR)                                                                           \
+  hipLaunchKernelGGL(vupd_strip_k<NR>, dim3(xcd_grid(nb * npg)), dim3(256), lds, st, QRW, perm, Vo, \
+                     Vn, nb, Np)
+    if (NRB <= 4) VUPD_STRIP(4);
+    else if (NRB <= 8) VUPD_STRIP(8);
+    else VUPD_STRIP(16);
+#undef VUPD_STRIP
+    return hipGetLastError();
+  }
   switch (RB) {
     case 1: return run_vupd<1>(QRW, perm, Vo, Vn, nb, Np, st);
     case 2: return run_vupd<2>(QRW, perm, Vo, Vn, nb, Np, st);
