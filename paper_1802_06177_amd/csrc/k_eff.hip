@@ -99,30 +99,46 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 
 // ------------------------------------------------------------------------------ energy
 
-__global__ __launch_bounds__(256) void eff_energy_k(const double* __restrict__ x, int N, int Lx,
-                                                    int Ly, int Ltau, EffParams p,
-                                                    double* __restrict__ e) {
+// One workgroup of 1024 threads per chain (a fixed summation order, so the energy is
+// reproducible); the neighbour offsets of every site come from tables in LDS and the
+// (slice, site) pair of a thread advances by a constant step, so the loop does no integer
+// division.
+constexpr int EN_THREADS = 1024;
+__global__ __launch_bounds__(EN_THREADS) void eff_energy_k(const double* __restrict__ x, int N, int Lx,
+                                                           int Ly, int Ltau, EffParams p,
+                                                           double* __restrict__ e) {
   __shared__ double red[16];
+  __shared__ int nbr[6 * 448];   // +x, +y, +x+y, +x-y, +2x, +2y (N <= 448)
   const int ch = blockIdx.x;
   const double* xc = x + (size_t)ch * N * Ltau;
-  double s = 0.0;
-  for (int idx = threadIdx.x; idx < N * Ltau; idx += blockDim.x) {
-    const int l = idx / N, i = idx - l * N;
-    const double y = xc[idx];
-    const double yn = xc[((l + 1) % Ltau) * N + i];
-    double t = p.Jk * (yn - y) * (yn - y) + p.J2 * y * y + p.Jp * f4(y, p.a) + p.Jp6 * f6(y, p.a);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const int ix = i % Lx, iy = i / Lx;
-    const double* xs = xc + l * N;
-    // bonds counted once: from (ix, iy) in the + directions of each range
-    if (p.Js0 != 0.0)
-      t += p.Js0 * y * (xs[wrap(ix + 1, Lx) + Lx * iy] + xs[ix + Lx * wrap(iy + 1, Ly)]);
-    if (p.Js1 != 0.0)
-      t += p.Js1 * y * (xs[wrap(ix + 1, Lx) + Lx * wrap(iy + 1, Ly)] +
-                        xs[wrap(ix + 1, Lx) + Lx * wrap(iy - 1, Ly)]);
-    if (p.Js2 != 0.0)
-      t += p.Js2 * y * (xs[wrap(ix + 2, Lx) + Lx * iy] + xs[ix + Lx * wrap(iy + 2, Ly)]);
+    nbr[6 * i + 0] = wrap(ix + 1, Lx) + Lx * iy;
+    nbr[6 * i + 1] = ix + Lx * wrap(iy + 1, Ly);
+    nbr[6 * i + 2] = wrap(ix + 1, Lx) + Lx * wrap(iy + 1, Ly);
+    nbr[6 * i + 3] = wrap(ix + 1, Lx) + Lx * wrap(iy - 1, Ly);
+    nbr[6 * i + 4] = wrap(ix + 2, Lx) + Lx * iy;
+    nbr[6 * i + 5] = ix + Lx * wrap(iy + 2, Ly);
+  }
+  __syncthreads();
+  const int dl = blockDim.x / N, di = blockDim.x - dl * N;
+  int l = threadIdx.x / N, i = threadIdx.x - l * N;
+  double s = 0.0;
+#pragma unroll 4
+  for (int idx = threadIdx.x; idx < N * Ltau; idx += blockDim.x) {
+    const double* xs = xc + (size_t)l * N;
+    const double y = xs[i];
+    const double yn = xc[(size_t)(l + 1 == Ltau ? 0 : l + 1) * N + i];
+    double t = p.Jk * (yn - y) * (yn - y) + p.J2 * y * y + p.Jp * f4(y, p.a) + p.Jp6 * f6(y, p.a);
+    // bonds counted once: from site i in the + directions of each range
+    if (p.Js0 != 0.0) t += p.Js0 * y * (xs[nbr[6 * i + 0]] + xs[nbr[6 * i + 1]]);
+    if (p.Js1 != 0.0) t += p.Js1 * y * (xs[nbr[6 * i + 2]] + xs[nbr[6 * i + 3]]);
+    if (p.Js2 != 0.0) t += p.Js2 * y * (xs[nbr[6 * i + 4]] + xs[nbr[6 * i + 5]]);
     t += p.Jt * y * yn;
     s += t;
+    i += di;
+    l += dl;
+    if (i >= N) { i -= N; ++l; }
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) e[ch] = s;
@@ -181,7 +197,7 @@ __global__ __launch_bounds__(1024) void eff_sweep_k(double* __restrict__ x, int 
 
 // ------------------------------------------------------------------------------ weight
 
-__global__ __launch_bounds__(256) void log_weight_k(const double* __restrict__ x,
+__global__ __launch_bounds__(EN_THREADS) void log_weight_k(const double* __restrict__ x,
                                                     const double* __restrict__ logdet, int N,
                                                     int Ltau, double lam, double omega0,
                                                     double dtau, double c_kin,
@@ -190,12 +206,17 @@ __global__ __launch_bounds__(256) void log_weight_k(const double* __restrict__ x
   const int ch = blockIdx.x;
   const double* xc = x + (size_t)ch * N * Ltau;
   double pot = 0.0, kin = 0.0;
+  const int dl = blockDim.x / N, di = blockDim.x - dl * N;
+  int l = threadIdx.x / N, i = threadIdx.x - l * N;
+#pragma unroll 4
   for (int idx = threadIdx.x; idx < N * Ltau; idx += blockDim.x) {
-    const int l = idx / N, i = idx - l * N;
     const double y = xc[idx];
-    const double dy = xc[((l + 1) % Ltau) * N + i] - y;
+    const double dy = xc[(size_t)(l + 1 == Ltau ? 0 : l + 1) * N + i] - y;
     pot += 0.5 * omega0 * omega0 * y * y - lam * y;
     kin += dy * dy;
+    i += di;
+    l += dl;
+    if (i >= N) { i -= N; ++l; }
   }
   pot = block_sum(pot, red);
   kin = block_sum(kin, red);
@@ -237,7 +258,7 @@ __global__ __launch_bounds__(256) void accept_k(double* __restrict__ x_cur,
 
 hipError_t launch_eff_energy(const double* x, int nch, int Lx, int Ly, int Ltau, EffParams p,
                              double* e, hipStream_t st) {
-  hipLaunchKernelGGL(eff_energy_k, dim3(nch), dim3(256), 0, st, x, Lx * Ly, Lx, Ly, Ltau, p, e);
+  hipLaunchKernelGGL(eff_energy_k, dim3(nch), dim3(EN_THREADS), 0, st, x, Lx * Ly, Lx, Ly, Ltau, p, e);
   return hipGetLastError();
 }
 
@@ -261,7 +282,7 @@ hipError_t launch_eff_sweep(double* x, int nch, int Lx, int Ly, int Ltau, EffPar
 hipError_t launch_log_weight(const double* x, const double* logdet, int nch, int N, int Ltau,
                              double lam, double omega0, double dtau, double c_kin, double* logw,
                              hipStream_t st) {
-  hipLaunchKernelGGL(log_weight_k, dim3(nch), dim3(256), 0, st, x, logdet, N, Ltau, lam, omega0,
+  hipLaunchKernelGGL(log_weight_k, dim3(nch), dim3(EN_THREADS), 0, st, x, logdet, N, Ltau, lam, omega0,
                      dtau, c_kin, logw);
   return hipGetLastError();
 }
