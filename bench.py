@@ -138,6 +138,25 @@ def roofline(prof, prec, md, B, steps, counters_apply, kernel=None):
             "per_class_ms_per_step": {k: round(v[0] / steps, 3) for k, v in prof.items() if v[1]}}
 
 
+def path_roofline(prec, md, value):
+    """Whole evaluation against the matrix-core peaks: T_roof = F_lo / P_lo + F_hi / P_64 per
+    evaluation, with F_lo the segment products (2 N^3 (n_s - 1) per block, times the number of
+    split products, in the precision of the path) and F_hi the FP64 rest (S U, Householder QR
+    with Q and R P^T V: (2 + 11/3) N^3 per block; LU and N-column solve (8/3) N^3; residual
+    step 8 N^3 when the path runs it)."""
+    N, Lt, n_s = md["Lx"] * md["Ly"], md["Ltau"], md["n_s"]
+    m = (Lt + n_s - 1) // n_s
+    n3 = float(N) ** 3
+    seg = 2.0 * n3 * (Lt - m)
+    f_hi = (2.0 + 11.0 / 3.0) * n3 * m + (8.0 / 3.0) * n3 + (8.0 * n3 if prec != "fp64" else 0.0)
+    if prec == "fp64":
+        t = (seg + f_hi) / (PEAK["f64"] * 1e12)
+    else:
+        t = seg * PRODUCTS[prec] / (PEAK[DTYPE[prec]] * 1e12) + f_hi / (PEAK["f64"] * 1e12)
+    return {"t_roof_us_per_eval": round(t * 1e6, 2), "ceiling_evals_per_s": round(1.0 / t, 1),
+            "frac": round(value * t, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,9 +230,11 @@ def main():
     fp64 = None
     if args.precision != "fp64" and not args.no_fp64:
         r64 = run(slmc, torch, md, eff, xs, B, "fp64", args)
-        fp64 = {"value": round(B * args.steps / (r64["ms"] / 1e3), 3),
+        v64 = B * args.steps / (r64["ms"] / 1e3)
+        fp64 = {"value": round(v64, 3),
                 "ms_per_step": round(r64["ms"] / args.steps, 4),
-                "mixed_over_fp64": round(r64["ms"] / main_run["ms"], 4)}
+                "mixed_over_fp64": round(r64["ms"] / main_run["ms"], 4),
+                "path_roofline": path_roofline("fp64", md, v64)}
 
     # the effective-model sweep alone on the 12x12 shape: 64 chains (L2-resident) and 2048
     # chains (a working set above the 256 MB last-level cache)
@@ -257,7 +278,8 @@ def main():
                    "precision": args.precision, "acc_chunk": args.acc_chunk,
                    "residual_steps": args.residual, "global_batch": B, "parallelism": "none",
                    "schedule": "serial" if args.serial else "overlapped"},
-        "roofline": roof, "slice_products": seg_rate, "cpu_baseline": cpu, "error_vs_oracle": err,
+        "roofline": roof, "slice_products": seg_rate, "path_roofline": path_roofline(args.precision, md, value),
+        "cpu_baseline": cpu, "error_vs_oracle": err,
         "fp64_path": fp64,
         "sweep_only": sweep,
         "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
