@@ -240,12 +240,23 @@ __device__ __forceinline__ void panel_sync(int* cnt, int& epoch, int lane, int* 
   const int target = QR_PANEL_WAVES * epoch;
   int spins = 0;
   while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
-    __builtin_amdgcn_s_sleep(1);
+    // the first polls back to back (the other panel waves are usually a few hundred
+    // cycles behind), then with a sleep between polls
+    if (spins >= 16) __builtin_amdgcn_s_sleep(1);
     if (++spins > QR_SPIN_LIMIT) {
       *timeout = 1;
       break;
     }
   }
+}
+
+// 1 / d from the hardware reciprocal and two Newton steps (within an ulp; the Householder
+// scalars need no correctly rounded quotient, and this is on the per-column critical path)
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  return r;
 }
 
 template <bool TWO>
@@ -300,8 +311,8 @@ __device__ __forceinline__ void panel_factor_all(double (&row0)[16], double (&ro
         tau = 0.0; bt = alpha; sc = 0.0;
       } else {
         bt = -copysign(sqrt(alpha * alpha + ss), alpha);
-        tau = (bt - alpha) / bt;
-        sc = 1.0 / (alpha - bt);
+        tau = (bt - alpha) * rcp_nr(bt);
+        sc = rcp_nr(alpha - bt);
       }
       // g_j = v^T row_j: Y^T v for j < cc, the reflector's product with column j for j > cc
       double gv[16];
