@@ -89,7 +89,7 @@ __host__ __device__ __forceinline__ void slice4x5(const double (&v)[4], double s
 
 // NW waves per workgroup, two waves per SIMD: 8 (one workgroup per CU) or 4 (two
 // workgroups per CU, so that one slices its panel while the other is on the matrix cores)
-template <int NW, int RB, int CB, bool TAB>
+template <int NW, int RB, int CB, bool TAB, bool REG>
 __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __restrict__ Eq,
                                                     const double* __restrict__ Esc,
                                                     const double* __restrict__ E64, FieldRef f,
@@ -102,7 +102,8 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
   extern __shared__ double lds[];
   constexpr int KBB = NSL * W * 64;             // bytes of one 64-row k block of slices
   double* vbuf = lds;                           // [2][Np]
-  double* red = vbuf + 2 * Np;                  // [NW][W]
+  double* escs = vbuf + 2 * Np;                 // [Np] E's row scales
+  double* red = escs + Np;                      // [NW][W]
   int8_t* Bsl = (int8_t*)(red + NW * W);  // [Npk/64][NSL][W][64]
   int8_t* E0 = Bsl + (Npk >> 6) * KBB;          // tab mode: [NSL][trow][LDE]
   const int npan = Np / W;
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
   double* nout = snorm + ((size_t)b * m + k) * Np;
 
   fill_v(vbuf, xb, l0, N, Np, ldl);
+  for (int i = tid; i < Np; i += 64 * NW) escs[i] = Esc[i];
   if (len > 1) fill_v(vbuf + Np, xb, l0 + 1, N, Np, ldl);
   // zero the k padding of the slices once (rows Np .. Npk-1 are never written later)
   for (int idx = tid; idx < NSL * W * (Npk - Np); idx += 64 * NW) {
@@ -238,6 +240,20 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
   make_slices();
 
   const int nkb = Npk >> 6;
+  // REG (base rows = one row block, 4 waves, Np a multiple of 64): the A operand of row
+  // block w + 4 r and k block kb is chunk (4 (kb - r) + g - w) mod (Np / 16) of the base
+  // rows, so a wave needs only RB distinct operands (by (kb - r) mod RB): loaded into
+  // registers once, and the product loop reads only the panel's slices from LDS
+  ix4 eA[REG ? RB : 1][NSL];
+  if constexpr (REG) {
+    const int Nc = Np >> 4;
+#pragma unroll
+    for (int e = 0; e < RB; ++e) {
+      const int src = (4 * e + g - w + Nc) % Nc;
+#pragma unroll
+      for (int p = 0; p < NSL; ++p) eA[e][p] = *(const ix4*)(E0 + (p * 16 + c) * LDE + 16 * src);
+    }
+  }
   for (int t = 1; t < len; ++t) {
     const bool last = (t == len - 1);
     double* vnext = vbuf + ((t + 1) & 1) * Np;   // v of slice l0+t+1 (unused when last)
@@ -248,7 +264,28 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
       for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int d = 0; d < NDIAG; ++d) acc[r][cb][d] = ix4{0, 0, 0, 0};
-    if constexpr (TAB) {
+    if constexpr (REG) {
+#pragma unroll
+      for (int kb = 0; kb < RB; ++kb) {
+        const int8_t* bk = Bsl + kb * KBB + 64 * c + 16 * g;
+        ix4 bq[CB][NSL];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int q = 0; q < NSL; ++q) bq[cb][q] = *(const ix4*)(bk + (q * W + 16 * cb) * 64);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int e = (kb - r + RB) % RB;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int p = 0; p < NSL; ++p)
+#pragma unroll
+              for (int q = 0; q + p < NSL; ++q)
+                acc[r][cb][p + q] = mfma_i8(eA[e][p], bq[cb][q], acc[r][cb][p + q]);
+        }
+      }
+    } else if constexpr (TAB) {
       // A operands from the LDS copy of the base rows; the panel's slices stay in registers
       // across the row blocks
       const int Nc = Np >> 4, nbase = trow >> 4;
@@ -322,13 +359,18 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
             const int row = 16 * (w + NW * r) + drow32(g, i);
             const double x = recombine5(acc[r][cb][0][i], acc[r][cb][1][i], acc[r][cb][2][i],
                                         acc[r][cb][3][i], acc[r][cb][4][i]);
-            vals[r][cb][i] = (w + NW * r < NRB) ? vnext[row] * (Esc[row] * fcur[cb] * x) : 0.0;
+            vals[r][cb][i] = (w + NW * r < NRB) ? vnext[row] * (escs[row] * fcur[cb] * x) : 0.0;
           }
       make_slices();
     } else {
       double s2[CB];
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) s2[cb] = 0.0;
+      // opaque copies of the lane coordinates: the output addresses are formed here, not
+      // hoisted to the start of the kernel (where they would be spilled)
+      int go = g, co = c;
+      __asm__ volatile("" : "+v"(go), "+v"(co));
+      double* so = Sout + c0 + co;
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int rb = w + NW * r;
@@ -337,11 +379,11 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
           for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int row = 16 * rb + drow32(g, i);
+              const int row = 16 * rb + drow32(go, i);
               const double x = recombine5(acc[r][cb][0][i], acc[r][cb][1][i], acc[r][cb][2][i],
                                           acc[r][cb][3][i], acc[r][cb][4][i]);
-              const double val = Esc[row] * fcur[cb] * x;
-              Sout[(size_t)row * Np + c0 + 16 * cb + c] = val;
+              const double val = escs[row] * fcur[cb] * x;
+              so[(size_t)row * Np + 16 * cb] = val;
               s2[cb] += val * val;
             }
         }
@@ -364,16 +406,16 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
   }
 }
 
-template <int NW, int RB, int CB, bool TAB>
+template <int NW, int RB, int CB, bool TAB, bool REG>
 hipError_t run_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f, int nb,
                   int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
                   double* sn, int trow, int LDE, hipStream_t st) {
   constexpr int W = 16 * CB;
   const int Npk = (Np + 63) / 64 * 64;
   const int count = nb * kc * (Np / W);
-  const size_t lds = (size_t)(2 * Np + NW * W) * sizeof(double) + (size_t)NSL * W * Npk +
+  const size_t lds = (size_t)(3 * Np + NW * W) * sizeof(double) + (size_t)NSL * W * Npk +
                      (TAB ? (size_t)NSL * trow * LDE : 0);
-  hipLaunchKernelGGL((seg_chain_i8<NW, RB, CB, TAB>), dim3(xcd_grid(count)), dim3(64 * NW), lds, st, Eq,
+  hipLaunchKernelGGL((seg_chain_i8<NW, RB, CB, TAB, REG>), dim3(xcd_grid(count)), dim3(64 * NW), lds, st, Eq,
                      Esc, E64, f, nb, N, Np, Npk, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE);
   return hipGetLastError();
 }
@@ -382,9 +424,13 @@ template <int NW, int RB, int CB>
 hipError_t pick_tab(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f, int nb,
                     int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
                     double* sn, int trow, int LDE, hipStream_t st) {
+  // registers for the A operands when the base rows are one row block and the 4 waves'
+  // row blocks cover Np in whole k blocks
+  if (NW == 4 && trow == 16 && Np % 64 == 0 && Np / 64 == RB)
+    return run_i8<NW, RB, CB, true, NW == 4>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
   if (trow > 0)
-    return run_i8<NW, RB, CB, true>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
-  return run_i8<NW, RB, CB, false>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, 0, 0, st);
+    return run_i8<NW, RB, CB, true, false>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
+  return run_i8<NW, RB, CB, false, false>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, 0, 0, st);
 }
 
 }  // namespace
