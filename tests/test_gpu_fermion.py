@@ -284,8 +284,11 @@ def test_int8x5_ragged_and_padded_shapes(Lx, Ly, Ltau, n_s):
 # lcm(16, Lx) rows when N is a multiple of 16; the int8 kernel then keeps the base rows'
 # slices in LDS.  Integer sums are exact, so the result must equal the streaming mode's
 # bit for bit, and both must meet the oracle bar.
+# (16x16, 8x8, 16x8 and 16x12 also take the register variant: one base row block, Np a
+# multiple of 64, each wave's few distinct A operands held in registers)
 @pytest.mark.parametrize("Lx,Ly,Ltau,n_s", [(16, 16, 40, 8), (12, 12, 36, 10), (8, 6, 24, 6),
-                                             (4, 4, 20, 5), (16, 28, 16, 8), (8, 10, 20, 7)])
+                                             (4, 4, 20, 5), (16, 28, 16, 8), (8, 10, 20, 7),
+                                             (8, 8, 24, 6), (16, 8, 20, 5), (16, 12, 16, 8)])
 def test_int8x5_lds_base_rows_equal_streamed_bitwise(Lx, Ly, Ltau, n_s):
     md = _md(Lx, Ltau, n_s, 1.5, Ly=Ly, mu=0.1)
     g = gen(95, Lx * 1000 + Ly * 100 + Ltau)
