@@ -610,8 +610,9 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
           row1[2 * h] = u1.x;
           row1[2 * h + 1] = u1.y;
         }
-        // every panel wave has its rows before any overwrites them with the factored panel
-        panel_sync(cnt, epoch, lane, flag + 1);
+        // (no sync needed before the factored panel overwrites Yq: every panel wave uses its
+        // rows in the first column step, before that step's sync, and a wave stores the
+        // panel only after the last column's sync)
       }
       panel_factor_all<TWO>(row0, row1, trow, tid, Kq, red, prow, wsum, Tq, tauA + jq, beta + jq,
                             cnt, epoch, flag + 1);
