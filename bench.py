@@ -105,6 +105,74 @@ def sweep_rates(slmc, torch, np, chains, n_sweeps=4, reps=5):
             "working_set_MB": round(8.0 * chains * Lx * Ly * Lt / 1e6, 1)}
 
 
+def uneven_rates(slmc, torch, np, prec, reps=3, check=False):
+    """The uneven packed batch: 32 fields for each of L = 8, 12, 16, 20 (Ltau = 10 L,
+    n_s = 10, lam = 1.5), items interleaved across the four sizes, log-det + G of all 128 in
+    one packed call; then each size class alone (32 items, one call).  Evaluations per
+    second from HIP events; with check, the relative log-det error and max |dG| of the first
+    item of every class against the oracle."""
+    from synth import workload_item, workload_models
+    dev = torch.device("cuda:0")
+    mds = workload_models("W5")
+    models = [slmc.model_from_dict(d) for d in mds]
+    order = [(7 * k) % 128 for k in range(128)]
+    xs, midx = [], []
+    for b in order:
+        mi, x = workload_item("W5", b)
+        xs.append(x)
+        midx.append(mi)
+    opt = slmc.options(prec, 1 if prec != "fp64" else 0)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps
+
+    def packed(sel):
+        xsel = [xs[j] for j in sel]
+        msel = [midx[j] for j in sel]
+        x_off = np.cumsum([0] + [a.size for a in xsel[:-1]])
+        g_sizes = [(mds[k]["Lx"] * mds[k]["Ly"]) ** 2 for k in msel]
+        g_off = np.cumsum([0] + g_sizes[:-1])
+        x = torch.tensor(np.concatenate([a.ravel() for a in xsel]), dtype=torch.float64, device=dev)
+        G = torch.empty(int(sum(g_sizes)), dtype=torch.float64, device=dev)
+        ws = torch.empty(slmc.workspace_bytes(models, len(sel), opt, model_idx=msel, x_off=x_off,
+                                              g_off=g_off), dtype=torch.uint8, device=dev)
+        return lambda: slmc.green(models, x, opt, model_idx=msel, x_off=x_off, g_off=g_off,
+                                  n_items=len(sel), G=G, ws=ws), G, g_off
+
+    fn, G, g_off = packed(list(range(128)))
+    t_all = timed(fn)
+    out = {"packed_128": {"evals_per_s": round(128 / t_all, 1), "ms_per_call": round(t_all * 1e3, 3)}}
+    for mi, d in enumerate(mds):
+        sel = [j for j in range(128) if midx[j] == mi]
+        fc, _, _ = packed(sel)
+        tc = timed(fc)
+        out["L%d_Ltau%d" % (d["Lx"], d["Ltau"])] = {"items": len(sel), "evals_per_s": round(len(sel) / tc, 1),
+                                                     "ms_per_call": round(tc * 1e3, 3)}
+    if check:
+        import oracle
+        ld, _, Gp, _ = fn()
+        torch.cuda.synchronize()
+        ld, Gh = ld.cpu().numpy(), Gp.cpu().numpy()
+        for mi, d in enumerate(mds):
+            j = midx.index(mi)
+            N = d["Lx"] * d["Ly"]
+            E = oracle.expk(oracle.hopping_matrix(d["Lx"], d["Ly"], d["t"], d["mu"]), d["dtau"])
+            ref, _, rG = oracle.logdet_green(E, xs[j], d["dtau"], d["lam"], d["n_s"])[:3]
+            Gj = Gh[g_off[j]:g_off[j] + N * N].reshape(N, N)
+            key = "L%d_Ltau%d" % (d["Lx"], d["Ltau"])
+            out[key]["rel_logdet_err_item0"] = float(abs(ld[j] - ref) / abs(ref))
+            out[key]["max_abs_dG_item0"] = float(np.max(np.abs(Gj - rG)))
+    return out
+
+
 def roofline(prof, prec, md, B, steps, counters_apply, kernel=None):
     """A kernel class (default: the dominant one, largest event time in the timed region)
     against its peak: achieved = algorithmic work per launch / average launch time."""
@@ -173,6 +241,9 @@ def main():
     ap.add_argument("--no-alone", action="store_true",
                     help="skip the serial-schedule run of the slice-product kernel")
     ap.add_argument("--cpu-sample", type=int, default=6, help="oracle items for cpu_baseline (0: skip)")
+    ap.add_argument("--uneven", action="store_true",
+                    help="also time the uneven packed batch (L = 8, 12, 16, 20), headline "
+                         "precision and FP64, with one oracle-checked item per size class")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (reference "
                          "for the HBM byte counters) and exit")
@@ -268,6 +339,11 @@ def main():
                "max_abs_G": float(max(np.max(np.abs(G_g[k] - refs[k][2])) for k in range(ns))),
                "items": ns, "precision": args.precision}
 
+    uneven = None
+    if args.uneven:
+        uneven = {args.precision: uneven_rates(slmc, torch, np, args.precision, check=True),
+                  "fp64": uneven_rates(slmc, torch, np, "fp64", check=True)}
+
     out = {
         "metric": "fermion logdet+G evals/s at N=256,Ltau=160: mixed vs FP64, <=1e-8 rel err",
         "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -282,6 +358,7 @@ def main():
         "cpu_baseline": cpu, "error_vs_oracle": err,
         "fp64_path": fp64,
         "sweep_only": sweep,
+        "uneven_packed": uneven,
         "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
     }
     print(json.dumps(out), flush=True)

@@ -517,6 +517,9 @@ int fermion_call(const slmc_model* models, int32_t n_models, const slmc_batch* b
     return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
   Arena a(ws);
   hipStream_t st = (hipStream_t)stream;
+  // a packed batch may need item tables uploaded into the workspace (synchronous copies),
+  // which kernels of an earlier call on this stream may still read
+  if (batch->model_idx || batch->x_off || batch->g_off) HIPCHK(hipStreamSynchronize(st));
   for (auto& g : groups) {
     const slmc_model* m = &models[g.model];
     GroupBufs w;

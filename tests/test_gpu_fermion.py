@@ -165,6 +165,54 @@ def test_uneven_batch_one_call():
         assert np.max(np.abs(Gj - rG)) < 1e-9
 
 
+@pytest.mark.parametrize("prec", ["fp64", "int8x5"])
+def test_packed_groups_overlapped_match_serial_bitwise(prec):
+    # six lattice sizes in one call, items interleaved (item tables go into the workspace);
+    # two calls back to back on one workspace with different packings, no synchronization
+    # between them, overlapped schedule against the serial one (everything in order on the
+    # caller's stream); then one item of each size against the oracle
+    mds = [_md(4, 20, 5), _md(6, 30, 5), _md(8, 24, 8), _md(4, 16, 4, Ly=6), _md(10, 20, 10),
+           _md(12, 24, 6)]
+    models = [slmc.model_from_dict(d) for d in mds]
+    g = gen(98, 6)
+    packs = []
+    for order in ([0, 1, 2, 3, 4, 5, 5, 4, 3, 2, 1, 0], [5, 3, 1, 0, 2, 4, 1]):
+        xs = [g.normal(size=(mds[k]["Ltau"], mds[k]["Lx"] * mds[k]["Ly"])) for k in order]
+        x_off = np.cumsum([0] + [a.size for a in xs[:-1]])
+        g_sizes = [(mds[k]["Lx"] * mds[k]["Ly"]) ** 2 for k in order]
+        g_off = np.cumsum([0] + g_sizes[:-1])
+        x = torch.tensor(np.concatenate([a.ravel() for a in xs]), dtype=torch.float64, device=DEV)
+        packs.append((order, x, x_off, g_off, int(sum(g_sizes))))
+    opt0 = slmc.options(prec, 1)
+    nbytes = max(slmc.workspace_bytes(models, len(o), opt0, model_idx=o, x_off=xo, g_off=go)
+                 for o, _, xo, go, _ in packs)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=DEV)
+    res = {}
+    for serial in (True, False):
+        print("case: packed six sizes, prec=%s serial=%s" % (prec, serial), flush=True)
+        opt = slmc.options(prec, 1, serial=serial)
+        outs = [slmc.green(models, x, opt, model_idx=o, x_off=xo, g_off=go, n_items=len(o),
+                           G=torch.empty(ng, dtype=torch.float64, device=DEV), ws=ws)
+                for o, x, xo, go, ng in packs]
+        torch.cuda.synchronize()
+        res[serial] = [[t.cpu().numpy() for t in r] for r in outs]
+    for a, b in zip(res[True], res[False]):
+        assert np.all(a[3] == 0) and np.all(b[3] == 0)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+    o, x, xo, go, _ = packs[0]
+    xh = x.cpu().numpy()
+    ld, _, Gh, _ = res[False][0]
+    bar = 1e-11 if prec == "fp64" else 1e-8
+    for j in range(6):
+        md = mds[o[j]]
+        N = md["Lx"] * md["Ly"]
+        xj = xh[xo[j]:xo[j] + md["Ltau"] * N].reshape(md["Ltau"], N)
+        ref, _, rG = _ref(md, xj)
+        assert abs(ld[j] - ref) <= bar * abs(ref)
+        assert np.max(np.abs(Gh[go[j]:go[j] + N * N].reshape(N, N) - rG)) < 1e3 * bar
+
+
 def test_nonfinite_input_flags_only_that_item():
     md = _md(4, 20, 5)
     g = gen(96, 1)
