@@ -210,6 +210,12 @@ __device__ __forceinline__ double reduce_scatter16(const double (&v)[16], int la
   return d;
 }
 
+// Lane l's value of v, for a lane index that is the same in every lane.
+__device__ __forceinline__ double readlane64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -225,7 +231,7 @@ __device__ __forceinline__ void wave_lds_fence() {
 // T_l,cc = -tau sum_m T_l,m (Y^T v)_m); lane l & 15 keeps row l & 15 of T in trow and
 // threads 0-15 store it to Tl.  The sums go through a wave reduce-scatter and one sync of
 // the 4 panel waves per column (panel_sync); red [2][4][16] and prow [2][16] are
-// double-buffered by column parity, wsum [4][16] is a per-wave broadcast slot.
+// double-buffered by column parity.
 constexpr int QR_PANEL_WAVES = 4;
 constexpr int QR_SPIN_LIMIT = 1 << 16;   // about 2 ms of s_sleep(1) polls
 
@@ -262,7 +268,7 @@ __device__ __forceinline__ double rcp_nr(double d) {
 template <bool TWO>
 __device__ __forceinline__ void panel_factor_all(double (&row0)[16], double (&row1)[16],
                                                  double (&trow)[16], int t, int K, double* red,
-                                                 double* prow, double* wsum, double* Tl,
+                                                 double* prow, double* Tl,
                                                  double* tau_out, double* beta_out, int* cnt,
                                                  int& epoch, int* timeout) {
   const int lane = t & 63, w = t >> 6, tl = lane & 15;
@@ -287,25 +293,14 @@ __device__ __forceinline__ void panel_factor_all(double (&row0)[16], double (&ro
     }
     panel_sync(cnt, epoch, lane, timeout);
     {
-      // column totals: lanes 0-15 of each panel wave add the wave partials and pass them
-      // to the whole wave through the wave's own LDS slot (LDS is in order within a wave)
+      // column totals: lane l adds the 4 wave partials of column l & 15 and reads the
+      // pivot row's entry of that column; the wave-uniform scalars below are taken from
+      // lane cc, and g_j from lane j, with readlane (no LDS round trip)
       double tot = 0.0;
 #pragma unroll
       for (int ww = 0; ww < QR_PANEL_WAVES; ++ww) tot += rb[ww * 16 + tl];
-      double* wsm = wsum + w * 16;
-      if (lane < 16) wsm[lane] = tot;
-      wave_lds_fence();
-      double P[16], rc[16];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double2 u = ((const double2*)pb)[q];
-        const double2 z = ((const double2*)wsm)[q];
-        rc[2 * q] = u.x;
-        rc[2 * q + 1] = u.y;
-        P[2 * q] = z.x;
-        P[2 * q + 1] = z.y;
-      }
-      const double alpha = rc[cc], ss = P[cc];
+      const double rcl = pb[tl];
+      const double alpha = readlane64(rcl, cc), ss = readlane64(tot, cc);
       double tau, bt, sc;
       if (ss == 0.0) {
         tau = 0.0; bt = alpha; sc = 0.0;
@@ -315,9 +310,10 @@ __device__ __forceinline__ void panel_factor_all(double (&row0)[16], double (&ro
         sc = rcp_nr(alpha - bt);
       }
       // g_j = v^T row_j: Y^T v for j < cc, the reflector's product with column j for j > cc
+      const double gl = rcl + sc * tot;
       double gv[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) gv[j] = rc[j] + sc * P[j];
+      for (int j = 0; j < 16; ++j) gv[j] = readlane64(gl, j);
       double tp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int m = 0; m < cc; ++m) tp[m & 3] += trow[m] * gv[m];
@@ -528,8 +524,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   double* Tl0 = Pn0 + 2 * Np * LDY;         // [2][16][LDY] T of panel p / panel p+1
   double* red = Tl0 + 2 * 16 * LDY;         // [2][4][16]
   double* prow = red + 2 * QR_PANEL_WAVES * 16;   // [2][16]
-  double* wsum = prow + 32;                 // [4][16]
-  double* wpart = wsum + QR_PANEL_WAVES * 16;     // [4][64][4] partial Y^T blk
+  double* wpart = prow + 32;                // [4][64][4] partial Y^T blk
   double* key = wpart + QR_PANEL_WAVES * 256;     // [Np]
   double* beta = key + Np;                  // [Np]
   double* tauA = beta + Np;                 // [Np]
@@ -614,7 +609,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
         // rows in the first column step, before that step's sync, and a wave stores the
         // panel only after the last column's sync)
       }
-      panel_factor_all<TWO>(row0, row1, trow, tid, Kq, red, prow, wsum, Tq, tauA + jq, beta + jq,
+      panel_factor_all<TWO>(row0, row1, trow, tid, Kq, red, prow, Tq, tauA + jq, beta + jq,
                             cnt, epoch, flag + 1);
       // the factored panel: R rows and Householder vectors to Q, Y to LDS; T (already in
       // LDS) to Q's T blocks
@@ -1007,7 +1002,7 @@ template <int NRBMAX>
 hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride, int nparts,
                   const double* logDp, double* QRW, double* Tb, int* perm, double* logD,
                   int* qsign, int* status, int nb, int Np, hipStream_t st) {
-  const size_t lds = (size_t)(2 * Np * LDY + 2 * 16 * LDY + 3 * QR_PANEL_WAVES * 16 + 32 +
+  const size_t lds = (size_t)(2 * Np * LDY + 2 * 16 * LDY + 2 * QR_PANEL_WAVES * 16 + 32 +
                               QR_PANEL_WAVES * 256 + 3 * Np + 8) *
                          sizeof(double) + (size_t)(Np + 6) * sizeof(int);
   hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(QR_THREADS), lds, st, A, astride, norm2, nstride, nparts,
@@ -1036,7 +1031,29 @@ __global__ void fill_i32_k(int* dst, int n, int value) {
   if (i < n) dst[i] = value;
 }
 
+__global__ void gate_delay_k(long long ticks) {
+  const long long t0 = wall_clock64();
+  for (int i = 0; i < 4096; ++i) {
+    if (wall_clock64() - t0 >= ticks) break;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_gate_delay(int us, hipStream_t st) {
+  static int khz[64] = {0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (khz[dev] <= 0) {
+    e = hipDeviceGetAttribute(&khz[dev], hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(gate_delay_k, dim3(1), dim3(64), 0, st, (long long)us * khz[dev] / 1000);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_i32(int* dst, int n, int value, hipStream_t st) {
   if (n <= 0) return hipSuccess;

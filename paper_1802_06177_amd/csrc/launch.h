@@ -52,6 +52,9 @@ hipError_t launch_qr(const double* A, int64_t astride, const double* norm2, int6
 
 // dst[0..n) = value (a plain kernel, safe inside captured graphs)
 hipError_t launch_fill_i32(int* dst, int n, int value, hipStream_t st);
+// One wave that waits about `us` microseconds of the constant-rate wall clock (at most
+// 4096 short polls, so it always ends)
+hipError_t launch_gate_delay(int us, hipStream_t st);
 
 // Vn[b] = F[b] Vo[b][perm[b], :] with F the upper triangle of QRW[b]
 // (Vo == nullptr: identity).

@@ -392,16 +392,21 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     if (16 / a * m->Lx <= N) trow = 16 / a * m->Lx;
   }
   const bool overlap = !(o->flags & SLMC_FLAG_SERIAL) && mseg > 1;
+  // Gated side work (below) where a segment block and a V update fit in the time of a QR
+  // on the CUs it leaves free; the heavier FP64 and bf16x6 segment products are all
+  // released at once instead and fill the chip from the start.
+  const bool gated = overlap && o->precision != SLMC_FP64 && o->precision != SLMC_BF16X6;
   std::unique_lock<std::mutex> side_lock(g_side_mu, std::defer_lock);
   SideStream* ss = nullptr;
   if (overlap) {
     side_lock.lock();
-    rc = side_stream_locked(3 * mseg + 1, &ss);
+    rc = side_stream_locked(5 * mseg + 1, &ss);
     if (rc) return rc;
     HIPCHK(hipEventRecord(ss->ev[mseg], st));
     HIPCHK(hipStreamWaitEvent(ss->s, ss->ev[mseg], 0));
     HIPCHK(hipStreamWaitEvent(ss->s2, ss->ev[mseg], 0));
-    for (int k = 0; k < mseg; ++k) {
+    // (gated: block 0 only, block k + 1 is released while QR k runs)
+    for (int k = 0; k < (gated ? 1 : mseg); ++k) {
       ProfScope ps(0, ss->s);
       HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb, N,
                               Np, m->Ltau, m->n_s, mseg, k, 1, ldl, w.S, w.snorm, trow, ss->s));
@@ -415,16 +420,33 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   // a3: stabilized accumulation
   double* logD[2] = {w.logD0, w.logD1};
   double* Vb[2] = {w.V0, w.V1};
-  // events: ev[k] segment k done (s), ev[mseg+1+k] QR k done (st), ev[2 mseg+1+k] V update k
-  // done (s2).  QR k+2 reuses the buffers that V update k reads, so it waits for it.
+  // Overlapped schedules.  The chain alternates wy_apply k (all CUs, 2 workgroups per CU)
+  // and QR k (one workgroup per item holding a whole CU: half the chip at 128 items).
+  // Gated: the side work, segment products k + 1 on s and V update k - 1 on s2, is
+  // released when wy_apply k is done, so it runs on the CUs that QR k leaves free and not
+  // beside wy_apply.  A short gate kernel on s goes first: released at the same moment as
+  // the QR, the side work's workgroups would take CUs that the QR's (a whole CU each) are
+  // waiting for.  Eager: all segment products are queued on s up front, and V update k
+  // follows QR k on s2.  Events: ev[k] segment k done (s), ev[mseg+1+k] QR k done (st),
+  // ev[2 mseg+1+k] V update k done (s2), ev[3 mseg+1+k] wy_apply k done (st),
+  // ev[4 mseg+1+k] gate k passed (s).  QR k+2 reuses the buffers that V update k reads,
+  // so it waits for it.
+  constexpr int kGateUs = 2;
   hipEvent_t* ev_qr = overlap ? &ss->ev[mseg + 1] : nullptr;
   hipEvent_t* ev_vu = overlap ? &ss->ev[2 * mseg + 1] : nullptr;
+  hipEvent_t* ev_ph = overlap ? &ss->ev[3 * mseg + 1] : nullptr;
+  hipEvent_t* ev_gt = overlap ? &ss->ev[4 * mseg + 1] : nullptr;
+  auto vupd = [&](int kk, hipStream_t sv) -> int {
+    ProfScope ps(3, sv);
+    HIPCHK(launch_vupd(w.QRW[kk & 1], w.perm[kk & 1], kk == 0 ? nullptr : Vb[(kk + 1) & 1], Vb[kk & 1],
+                       nb, Np, sv));
+    return SLMC_OK;
+  };
   for (int k = 0; k < mseg; ++k) {
     double* QRWk = w.QRW[k & 1];
     double* Tbk = w.Tb[k & 1];
     int* permk = w.perm[k & 1];
     if (overlap) HIPCHK(hipStreamWaitEvent(st, ss->ev[k], 0));
-    if (overlap && k >= 2) HIPCHK(hipStreamWaitEvent(st, ev_vu[k - 2], 0));
     const double* Ain;
     int64_t astride, nstride;
     const double* nrm;
@@ -446,22 +468,41 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
       nparts = Np / 16;
       nstride = (int64_t)nparts * Np;
     }
+    if (overlap && !gated && k >= 2) HIPCHK(hipStreamWaitEvent(st, ev_vu[k - 2], 0));
+    if (gated) {
+      HIPCHK(hipEventRecord(ev_ph[k], st));
+      HIPCHK(hipStreamWaitEvent(ss->s, ev_ph[k], 0));
+      HIPCHK(launch_gate_delay(kGateUs, ss->s));
+      HIPCHK(hipEventRecord(ev_gt[k], ss->s));
+      if (k + 1 < mseg) {
+        ProfScope ps(0, ss->s);
+        HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb,
+                                N, Np, m->Ltau, m->n_s, mseg, k + 1, 1, ldl, w.S, w.snorm, trow, ss->s));
+        HIPCHK(hipEventRecord(ss->ev[k + 1], ss->s));
+      }
+      if (k >= 1) {
+        HIPCHK(hipStreamWaitEvent(ss->s2, ev_gt[k], 0));
+        rc = vupd(k - 1, ss->s2);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(ev_vu[k - 1], ss->s2));
+      }
+      if (k >= 2) HIPCHK(hipStreamWaitEvent(st, ev_vu[k - 2], 0));
+    }
     {
     ProfScope ps(2, st);
     HIPCHK(launch_qr(Ain, astride, nrm, nstride, nparts, k == 0 ? nullptr : logD[(k + 1) & 1], QRWk,
                      Tbk, permk, logD[k & 1], w.qsign, w.status, nb, Np, st));
     }
     // V_k = F P^T V_{k-1} is needed only by the recombination: off the chain's critical
-    // path on s2 when overlapping
+    // path on s2 when overlapping (gated: released above one step later, the last one here)
+    if (gated && k < mseg - 1) continue;
     hipStream_t sv = overlap ? ss->s2 : st;
     if (overlap) {
       HIPCHK(hipEventRecord(ev_qr[k], st));
       HIPCHK(hipStreamWaitEvent(sv, ev_qr[k], 0));
     }
-    {
-    ProfScope ps(3, sv);
-    HIPCHK(launch_vupd(QRWk, permk, k == 0 ? nullptr : Vb[(k + 1) & 1], Vb[k & 1], nb, Np, sv));
-    }
+    rc = vupd(k, sv);
+    if (rc) return rc;
     if (overlap) HIPCHK(hipEventRecord(ev_vu[k], sv));
   }
   if (overlap) HIPCHK(hipStreamWaitEvent(st, ev_vu[mseg - 1], 0));
