@@ -505,15 +505,15 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     if (rc) return rc;
     if (overlap) HIPCHK(hipEventRecord(ev_vu[k], sv));
   }
-  if (overlap) HIPCHK(hipStreamWaitEvent(st, ev_vu[mseg - 1], 0));
   const double* logDf = logD[(mseg - 1) & 1];
   const double* Vf = Vb[(mseg - 1) & 1];
   double* Gint = Vb[mseg & 1];   // the other V buffer is free now
   double* QT = w.A;
   double* LU = w.S;
-  // U^T = Q_m^T explicitly, then a4: recombination
+  // U^T = Q_m^T explicitly (beside the last V update), then a4: recombination
   HIPCHK(launch_wy_apply(nullptr, 0, w.QRW[(mseg - 1) & 1], w.Tb[(mseg - 1) & 1], QT, nullptr, 1,
                          nb, Np, st));
+  if (overlap) HIPCHK(hipStreamWaitEvent(st, ev_vu[mseg - 1], 0));
   {
   ProfScope ps(4, st);
   HIPCHK(launch_lu(QT, Vf, logDf, w.qsign, w.status, LU, w.prow, w.DI, item_of, ld_out, sg_out,
