@@ -263,8 +263,11 @@ struct Arena {
 };
 
 struct GroupBufs {
-  double *S, *snorm, *A, *npart, *QRW[2], *Tb[2], *logD0, *logD1, *V0, *V1, *DI;
-  int *perm[2], *qsign, *status, *prow, *item_of;
+  // QR outputs (Householder vectors and the V-update factor, T blocks, column order) of
+  // the last kQB steps: QR k reuses the buffers of step k - kQB
+  static constexpr int kQB = 3;
+  double *S, *snorm, *A, *npart, *QRW[kQB], *Tb[kQB], *logD0, *logD1, *V0, *V1, *DI;
+  int *perm[kQB], *qsign, *status, *prow, *item_of;
   int64_t *xoff, *goff;
 };
 
@@ -274,7 +277,7 @@ void carve(Arena& a, int nb, int Np, int m, GroupBufs& g) {
   g.snorm = a.take<double>((size_t)nb * m * Np);
   g.A = a.take<double>((size_t)nb * n2);
   g.npart = a.take<double>((size_t)nb * Np * (Np / 16));
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < GroupBufs::kQB; ++h) {
     g.QRW[h] = a.take<double>((size_t)nb * n2);
     g.Tb[h] = a.take<double>((size_t)nb * Np * 16);
     g.perm[h] = a.take<int>((size_t)nb * Np);
@@ -405,7 +408,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     HIPCHK(hipEventRecord(ss->ev[mseg], st));
     HIPCHK(hipStreamWaitEvent(ss->s, ss->ev[mseg], 0));
     HIPCHK(hipStreamWaitEvent(ss->s2, ss->ev[mseg], 0));
-    // (gated: block 0 only, block k + 1 is released while QR k runs)
+    // (gated: block 0 only, the later blocks are released while the QRs run)
     for (int k = 0; k < (gated ? 1 : mseg); ++k) {
       ProfScope ps(0, ss->s);
       HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb, N,
@@ -422,31 +425,35 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   double* Vb[2] = {w.V0, w.V1};
   // Overlapped schedules.  The chain alternates wy_apply k (all CUs, 2 workgroups per CU)
   // and QR k (one workgroup per item holding a whole CU: half the chip at 128 items).
-  // Gated: the side work, segment products k + 1 on s and V update k - 1 on s2, is
-  // released when wy_apply k is done, so it runs on the CUs that QR k leaves free and not
-  // beside wy_apply.  A short gate kernel on s goes first: released at the same moment as
-  // the QR, the side work's workgroups would take CUs that the QR's (a whole CU each) are
-  // waiting for.  Eager: all segment products are queued on s up front, and V update k
-  // follows QR k on s2.  Events: ev[k] segment k done (s), ev[mseg+1+k] QR k done (st),
+  // Gated: the side work, segment block k + 2 (blocks 1 and 2 at k = 0) on s and V update
+  // k - 1 on s2, is released when wy_apply k is done, so it runs on the CUs that QR k
+  // leaves free rather than beside wy_apply; a segment block is ready a whole step before
+  // the chain needs it.  A short gate kernel on s goes first: released at the same moment
+  // as the QR, the side work's workgroups would take CUs that the QR's (a whole CU each)
+  // are waiting for.  Eager: all segment products are queued on s up front, and V update
+  // k follows QR k on s2.  Events: ev[k] segment k done (s), ev[mseg+1+k] QR k done (st),
   // ev[2 mseg+1+k] V update k done (s2), ev[3 mseg+1+k] wy_apply k done (st),
-  // ev[4 mseg+1+k] gate k passed (s).  QR k+2 reuses the buffers that V update k reads,
-  // so it waits for it.
-  constexpr int kGateUs = 2;
+  // ev[4 mseg+1+k] gate k passed (s).  QR k reuses the buffers that V update k - kQB
+  // reads, so step k waits for it (with the wait for segment k, before wy_apply k).
+  constexpr int kGateUs = 2, kSegAhead = 2, kQB = GroupBufs::kQB;
   hipEvent_t* ev_qr = overlap ? &ss->ev[mseg + 1] : nullptr;
   hipEvent_t* ev_vu = overlap ? &ss->ev[2 * mseg + 1] : nullptr;
   hipEvent_t* ev_ph = overlap ? &ss->ev[3 * mseg + 1] : nullptr;
   hipEvent_t* ev_gt = overlap ? &ss->ev[4 * mseg + 1] : nullptr;
   auto vupd = [&](int kk, hipStream_t sv) -> int {
     ProfScope ps(3, sv);
-    HIPCHK(launch_vupd(w.QRW[kk & 1], w.perm[kk & 1], kk == 0 ? nullptr : Vb[(kk + 1) & 1], Vb[kk & 1],
+    HIPCHK(launch_vupd(w.QRW[kk % kQB], w.perm[kk % kQB], kk == 0 ? nullptr : Vb[(kk + 1) & 1], Vb[kk & 1],
                        nb, Np, sv));
     return SLMC_OK;
   };
   for (int k = 0; k < mseg; ++k) {
-    double* QRWk = w.QRW[k & 1];
-    double* Tbk = w.Tb[k & 1];
-    int* permk = w.perm[k & 1];
-    if (overlap) HIPCHK(hipStreamWaitEvent(st, ss->ev[k], 0));
+    double* QRWk = w.QRW[k % kQB];
+    double* Tbk = w.Tb[k % kQB];
+    int* permk = w.perm[k % kQB];
+    if (overlap) {
+      HIPCHK(hipStreamWaitEvent(st, ss->ev[k], 0));
+      if (k >= kQB) HIPCHK(hipStreamWaitEvent(st, ev_vu[k - kQB], 0));
+    }
     const double* Ain;
     int64_t astride, nstride;
     const double* nrm;
@@ -460,25 +467,24 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
       nparts = 1;
     } else {
       ProfScope ps(1, st);
-      HIPCHK(launch_wy_apply(w.S + (size_t)k * n2, (int64_t)mseg * n2, w.QRW[(k + 1) & 1],
-                             w.Tb[(k + 1) & 1], w.A, w.npart, 0, nb, Np, st));
+      HIPCHK(launch_wy_apply(w.S + (size_t)k * n2, (int64_t)mseg * n2, w.QRW[(k - 1) % kQB],
+                             w.Tb[(k - 1) % kQB], w.A, w.npart, 0, nb, Np, st));
       Ain = w.A;
       astride = (int64_t)n2;
       nrm = w.npart;
       nparts = Np / 16;
       nstride = (int64_t)nparts * Np;
     }
-    if (overlap && !gated && k >= 2) HIPCHK(hipStreamWaitEvent(st, ev_vu[k - 2], 0));
     if (gated) {
       HIPCHK(hipEventRecord(ev_ph[k], st));
       HIPCHK(hipStreamWaitEvent(ss->s, ev_ph[k], 0));
       HIPCHK(launch_gate_delay(kGateUs, ss->s));
       HIPCHK(hipEventRecord(ev_gt[k], ss->s));
-      if (k + 1 < mseg) {
+      for (int j = (k == 0 ? 1 : k + kSegAhead); j <= k + kSegAhead && j < mseg; ++j) {
         ProfScope ps(0, ss->s);
         HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb,
-                                N, Np, m->Ltau, m->n_s, mseg, k + 1, 1, ldl, w.S, w.snorm, trow, ss->s));
-        HIPCHK(hipEventRecord(ss->ev[k + 1], ss->s));
+                                N, Np, m->Ltau, m->n_s, mseg, j, 1, ldl, w.S, w.snorm, trow, ss->s));
+        HIPCHK(hipEventRecord(ss->ev[j], ss->s));
       }
       if (k >= 1) {
         HIPCHK(hipStreamWaitEvent(ss->s2, ev_gt[k], 0));
@@ -486,7 +492,6 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
         if (rc) return rc;
         HIPCHK(hipEventRecord(ev_vu[k - 1], ss->s2));
       }
-      if (k >= 2) HIPCHK(hipStreamWaitEvent(st, ev_vu[k - 2], 0));
     }
     {
     ProfScope ps(2, st);
@@ -511,7 +516,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   double* QT = w.A;
   double* LU = w.S;
   // U^T = Q_m^T explicitly (beside the last V update), then a4: recombination
-  HIPCHK(launch_wy_apply(nullptr, 0, w.QRW[(mseg - 1) & 1], w.Tb[(mseg - 1) & 1], QT, nullptr, 1,
+  HIPCHK(launch_wy_apply(nullptr, 0, w.QRW[(mseg - 1) % kQB], w.Tb[(mseg - 1) % kQB], QT, nullptr, 1,
                          nb, Np, st));
   if (overlap) HIPCHK(hipStreamWaitEvent(st, ev_vu[mseg - 1], 0));
   {
@@ -528,7 +533,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     }
     if (resid) {
       // a5: R = Db^-1 U^T - X G, G += X^-1 R
-      double* R = w.QRW[mseg & 1];   // the other QR buffer is free now
+      double* R = w.QRW[mseg % kQB];   // a QR buffer that is free now
       {
         ProfScope pr(6, st);
         HIPCHK(launch_residual(QT, Vf, logDf, Gint, R, nb, Np, st));
