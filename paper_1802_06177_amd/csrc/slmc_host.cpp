@@ -395,10 +395,10 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     if (16 / a * m->Lx <= N) trow = 16 / a * m->Lx;
   }
   const bool overlap = !(o->flags & SLMC_FLAG_SERIAL) && mseg > 1;
-  // Gated side work (below) where a segment block and a V update fit in the time of a QR
-  // on the CUs it leaves free; the heavier FP64 and bf16x6 segment products are all
-  // released at once instead and fill the chip from the start.
-  const bool gated = overlap && o->precision != SLMC_FP64 && o->precision != SLMC_BF16X6;
+  // Gated side work (below) where a segment block and a V update about fit in the time of
+  // a QR on the CUs it leaves free (int8x5, bf16x3); the heavier FP64, FP32 and bf16x6
+  // segment products are all released at once instead and fill the chip from the start.
+  const bool gated = overlap && (o->precision == SLMC_INT8X5 || o->precision == SLMC_BF16X3);
   std::unique_lock<std::mutex> side_lock(g_side_mu, std::defer_lock);
   SideStream* ss = nullptr;
   if (overlap) {

@@ -234,9 +234,11 @@ def test_run_twice_bitwise_identical():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "int8x5", "bf16x3"])
 def test_overlapped_and_serial_schedules_are_bitwise_identical(prec):
-    # segment products on the library's side stream (default) or on the caller's stream
+    # segment products and V updates on the library's side streams (default; all queued up
+    # front for FP64 and FP32, released step by step for int8x5 and bf16x3) or everything
+    # on the caller's stream
     md = workload_models("W2")[0]
     xs = [workload_item("W2", b)[1] for b in range(5)]
     m = slmc.model_from_dict(md)
