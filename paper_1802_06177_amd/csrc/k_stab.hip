@@ -922,56 +922,64 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
   }
 }
 
-// V_new = F P^T V_old for Np <= 256: one wave per 16-column strip, the 4 strips of one
-// item per workgroup.  The strip of W = P^T V_old (rows gathered through the permutation)
-// stays in registers as 16x16 tiles in the accumulator layout, which is the B-operand
-// layout; the 16 rows of F that block row rb needs (columns 16 rb .. Np-1, the stored
-// Householder vectors below the diagonal masked to zero) are staged in LDS once for the 4
-// waves, double-buffered with the next block row in registers, and each output tile is
-// finished and stored before the next block row.
+// V_new = F P^T V_old for Np <= 256, each output strip split over k between two waves:
+// the 4 strips of one item per workgroup of 8 waves; wave (strip w, parity h) holds the
+// tiles of W = P^T V_old for the block rows kb = 2 i + h only (half the registers of one
+// wave holding them all, so 4 waves per SIMD), and for every block row rb of F both waves
+// of a strip sum their tiles kb >= rb.  One of them leaves its partial tile in LDS and the
+// other adds it after the block row's barrier and stores the output tile; the two swap
+// roles every block row, so a single partial buffer is never written before it is read.
+// The 16 rows of F that block row rb needs (columns 16 rb .. Np-1, the stored Householder
+// vectors below the diagonal masked to zero) are staged in LDS once for the 8 waves,
+// double-buffered with the next block row in registers.
 template <int NRBMAX>
-__global__ __launch_bounds__(256, 2) void vupd_strip_k(const double* __restrict__ QRW,
+__global__ __launch_bounds__(512, 4) void vupd_split_k(const double* __restrict__ QRW,
                                                        const int* __restrict__ perm,
                                                        const double* __restrict__ Vo,
                                                        double* __restrict__ Vn, int nb, int Np) {
   extern __shared__ double lds[];
-  const int LDF = Np + 1;                  // odd row stride: the 16 rows of a slice spread over banks
+  constexpr int NH = (NRBMAX + 1) / 2;
+  const int LDF = Np + 1;
   const int NRB = Np >> 4, npg = (NRB + 3) >> 2;
   const int id = xcd_remap(blockIdx.x, nb * npg);
   if (id < 0) return;
-  const int b = id / npg, tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4,
+  const int b = id / npg, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4,
             c = lane & 15;
+  const int w = wv & 3, h = wv >> 2;
   const int cs = 4 * (id % npg) + w, col = 16 * cs + c;
   const bool act = cs < NRB;
   const double* F = QRW + (size_t)b * Np * Np;
   const int* pb = perm + (size_t)b * Np;
+  double* part = lds + 2 * 16 * LDF + (w * 64 + lane) * 4;   // [4 strips][64 lanes][4]
 
-  dx4 wt[NRBMAX];
+  dx4 wt[NH];
 #pragma unroll
-  for (int kb = 0; kb < NRBMAX; ++kb) {
-    wt[kb] = zero4d();
+  for (int i = 0; i < NH; ++i) {
+    const int kb = 2 * i + h;
+    wt[i] = zero4d();
     if (kb < NRB && act) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int src = pb[16 * kb + g + 4 * v];
-        wt[kb][v] = Vo ? Vo[(size_t)b * Np * Np + (size_t)src * Np + col] : (src == col ? 1.0 : 0.0);
+        wt[i][v] = Vo ? Vo[(size_t)b * Np * Np + (size_t)src * Np + col] : (src == col ? 1.0 : 0.0);
       }
     }
   }
-  // block row rb of F: thread tid holds column tid of its 16 rows
-  double st[16];
+  // block row rb of F: thread tid holds column tid & 255 of rows 8 (tid >> 8) .. + 7
+  const int fc = tid & 255, fr = 8 * (tid >> 8);
+  double st[8];
   auto fload = [&](int rb) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int row = 16 * rb + i;
-      st[i] = (tid >= row && tid < Np) ? F[(size_t)row * Np + tid] : 0.0;
+    for (int i = 0; i < 8; ++i) {
+      const int row = 16 * rb + fr + i;
+      st[i] = (fc >= row && fc < Np) ? F[(size_t)row * Np + fc] : 0.0;
     }
   };
   auto fstore = [&](int buf, int rb) {
     double* Fs = lds + buf * 16 * LDF;
-    if (tid >= 16 * rb && tid < Np) {
+    if (fc >= 16 * rb && fc < Np) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) Fs[i * LDF + tid] = st[i];
+      for (int i = 0; i < 8; ++i) Fs[(fr + i) * LDF + fc] = st[i];
     }
   };
   fload(0);
@@ -980,21 +988,27 @@ __global__ __launch_bounds__(256, 2) void vupd_strip_k(const double* __restrict_
   double* out = Vn + (size_t)b * Np * Np;
   for (int rb = 0; rb < NRB; ++rb) {
     if (rb + 1 < NRB) fload(rb + 1);
+    const bool fin = h == (rb & 1);   // this wave finishes the tile of block row rb
+    dx4 acc = zero4d();
     if (act) {
       const double* Fs = lds + (rb & 1) * 16 * LDF;
-      dx4 acc = zero4d();
 #pragma unroll
-      for (int kb = 0; kb < NRBMAX; ++kb) {
+      for (int i = 0; i < NH; ++i) {
+        const int kb = 2 * i + h;
         if (kb >= rb && kb < NRB) {
 #pragma unroll
-          for (int s = 0; s < 4; ++s) acc = mfma64(Fs[c * LDF + 16 * kb + 4 * s + g], wt[kb][s], acc);
+          for (int s = 0; s < 4; ++s) acc = mfma64(Fs[c * LDF + 16 * kb + 4 * s + g], wt[i][s], acc);
         }
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) out[(size_t)(16 * rb + g + 4 * v) * Np + col] = acc[v];
+      if (!fin) *(dx4*)part = acc;
     }
     if (rb + 1 < NRB) fstore((rb + 1) & 1, rb + 1);
     __syncthreads();
+    if (act && fin) {
+      acc += *(const dx4*)part;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(size_t)(16 * rb + g + 4 * v) * Np + col] = acc[v];
+    }
   }
 }
 
@@ -1100,16 +1114,16 @@ hipError_t launch_vupd(const double* QRW, const int* perm, const double* Vo, dou
                        int Np, hipStream_t st) {
   const int NRB = Np / 16, RB = (NRB + 3) / 4;
   if (NRB <= 16) {
-    // register-resident strips (Np <= 256)
+    // register-resident strips (Np <= 256): two F block rows and the partial tiles in LDS
     const int npg = (NRB + 3) / 4;
-    const size_t lds = (size_t)2 * 16 * (Np + 1) * sizeof(double);
-#define VUPD_STRIP(NR)                                                                           \
-  hipLaunchKernelGGL(vupd_strip_k<NR>, dim3(xcd_grid(nb * npg)), dim3(256), lds, st, QRW, perm, Vo, \
-                     Vn, nb, Np)
-    if (NRB <= 4) VUPD_STRIP(4);
-    else if (NRB <= 8) VUPD_STRIP(8);
-    else VUPD_STRIP(16);
-#undef VUPD_STRIP
+    const size_t lds = ((size_t)2 * 16 * (Np + 1) + 4 * 64 * 4) * sizeof(double);
+#define VUPD_SPLIT(NR)                                                                        \
+  hipLaunchKernelGGL(vupd_split_k<NR>, dim3(xcd_grid(nb * npg)), dim3(512), lds, st, QRW, perm, \
+                     Vo, Vn, nb, Np)
+    if (NRB <= 4) VUPD_SPLIT(4);
+    else if (NRB <= 8) VUPD_SPLIT(8);
+    else VUPD_SPLIT(16);
+#undef VUPD_SPLIT
     return hipGetLastError();
   }
   switch (RB) {
