@@ -513,6 +513,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
                                                    double* __restrict__ QRW,
                                                    double* __restrict__ Tb,
                                                    int* __restrict__ perm,
+                                                   double* __restrict__ keyo,
                                                    double* __restrict__ logD,
                                                    int* __restrict__ qsign,
                                                    int* __restrict__ status, int Np) {
@@ -668,15 +669,30 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
     }
   }
 
-  // ---- outputs: log D, det Q, perm, and the V-update factor in the upper triangle
+  // ---- outputs: log D, det Q, perm, and the V-update factor F = S_r R S_c: for Np > 256
+  // formed here in the upper triangle; for Np <= 256 only the two diagonal scalings go out
+  // (S_c = e^(key_j - kref), S_r = e^(kref - key_i) / |R_ii|, with kref the middle of the
+  // key range so that neither overflows before F itself would) and the V update applies
+  // them to its operand rows and output rows, off the chain's critical path
   int ntau = 0;
+  double kmax = -INFINITY, kmin = INFINITY;
   for (int i = tid; i < Np; i += QR_THREADS) {
     logD[(size_t)b * Np + i] = log(fabs(beta[i])) + key[i];
     perm[(size_t)b * Np + i] = iperm[i];
     ntau += tauA[i] != 0.0;
+    kmax = fmax(kmax, key[i]);
+    kmin = fmin(kmin, key[i]);
   }
-  for (int off = 32; off >= 1; off >>= 1) ntau += __shfl_xor(ntau, off, 64);
-  if (lane == 0) nt[w] = (double)ntau;
+  for (int off = 32; off >= 1; off >>= 1) {
+    ntau += __shfl_xor(ntau, off, 64);
+    kmax = fmax(kmax, __shfl_xor(kmax, off, 64));
+    kmin = fmin(kmin, __shfl_xor(kmin, off, 64));
+  }
+  if (lane == 0) {
+    nt[w] = (double)ntau;
+    red[w] = kmax;
+    red[8 + w] = kmin;
+  }
   __syncthreads();
   if (tid == 0) {
     int tot = 0;
@@ -684,6 +700,20 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
     qsign[b] = (tot & 1) ? -1 : 1;
     if (flag[0]) status[b] |= 1;
     if (flag[1]) status[b] |= 8;
+  }
+  if constexpr (NRBMAX <= 16) {
+    double hi = red[0], lo = red[8];
+    for (int k = 1; k < QR_THREADS / 64; ++k) {
+      hi = fmax(hi, red[k]);
+      lo = fmin(lo, red[8 + k]);
+    }
+    // (a non-finite key comes from a non-finite input, already flagged in status)
+    const double kref = (isfinite(hi) && isfinite(lo)) ? 0.5 * (hi + lo) : 0.0;
+    for (int i = tid; i < Np; i += QR_THREADS) {
+      keyo[(size_t)b * 2 * Np + i] = exp(key[i] - kref);
+      keyo[(size_t)b * 2 * Np + Np + i] = exp(kref - key[i]) / fabs(beta[i]);
+    }
+    return;
   }
   // two adjacent entries of a row per thread and step (16-byte accesses), several steps in
   // flight: this pass is on the chain's critical path
@@ -935,6 +965,7 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
 template <int NRBMAX>
 __global__ __launch_bounds__(512, 4) void vupd_split_k(const double* __restrict__ QRW,
                                                        const int* __restrict__ perm,
+                                                       const double* __restrict__ scales,
                                                        const double* __restrict__ Vo,
                                                        double* __restrict__ Vn, int nb, int Np) {
   extern __shared__ double lds[];
@@ -952,6 +983,10 @@ __global__ __launch_bounds__(512, 4) void vupd_split_k(const double* __restrict_
   const int* pb = perm + (size_t)b * Np;
   double* part = lds + 2 * 16 * LDF + (w * 64 + lane) * 4;   // [4 strips][64 lanes][4]
 
+  // the factor is S_r R S_c (diagonal scalings from the QR): W = S_c P^T V_old here, the
+  // output rows scaled by S_r when stored
+  const double* csc = scales + (size_t)b * 2 * Np;
+  const double* rsc = csc + Np;
   dx4 wt[NH];
 #pragma unroll
   for (int i = 0; i < NH; ++i) {
@@ -960,12 +995,14 @@ __global__ __launch_bounds__(512, 4) void vupd_split_k(const double* __restrict_
     if (kb < NRB && act) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int src = pb[16 * kb + g + 4 * v];
-        wt[i][v] = Vo ? Vo[(size_t)b * Np * Np + (size_t)src * Np + col] : (src == col ? 1.0 : 0.0);
+        const int q = 16 * kb + g + 4 * v, src = pb[q];
+        const double x = Vo ? Vo[(size_t)b * Np * Np + (size_t)src * Np + col] : (src == col ? 1.0 : 0.0);
+        wt[i][v] = csc[q] * x;
       }
     }
   }
-  // block row rb of F: thread tid holds column tid & 255 of rows 8 (tid >> 8) .. + 7
+  // block row rb of R (upper triangle of QRW): thread tid holds column tid & 255 of rows
+  // 8 (tid >> 8) .. + 7
   const int fc = tid & 255, fr = 8 * (tid >> 8);
   double st[8];
   auto fload = [&](int rb) {
@@ -1007,20 +1044,23 @@ __global__ __launch_bounds__(512, 4) void vupd_split_k(const double* __restrict_
     if (act && fin) {
       acc += *(const dx4*)part;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(size_t)(16 * rb + g + 4 * v) * Np + col] = acc[v];
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rb + g + 4 * v;
+        out[(size_t)row * Np + col] = rsc[row] * acc[v];
+      }
     }
   }
 }
 
 template <int NRBMAX>
 hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride, int nparts,
-                  const double* logDp, double* QRW, double* Tb, int* perm, double* logD,
-                  int* qsign, int* status, int nb, int Np, hipStream_t st) {
+                  const double* logDp, double* QRW, double* Tb, int* perm, double* key,
+                  double* logD, int* qsign, int* status, int nb, int Np, hipStream_t st) {
   const size_t lds = (size_t)(2 * Np * LDY + 2 * 16 * LDY + 2 * QR_PANEL_WAVES * 16 + 32 +
                               QR_PANEL_WAVES * 256 + 3 * Np + 8) *
                          sizeof(double) + (size_t)(Np + 6) * sizeof(int);
   hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(QR_THREADS), lds, st, A, astride, norm2, nstride, nparts,
-                     logDp, QRW, Tb, perm, logD, qsign, status, Np);
+                     logDp, QRW, Tb, perm, key, logD, qsign, status, Np);
   return hipGetLastError();
 }
 
@@ -1100,18 +1140,19 @@ hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QR
 
 hipError_t launch_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride,
                      int nparts, const double* logDp, double* QRW, double* Tb, int* perm,
-                     double* logD, int* qsign, int* status, int nb, int Np, hipStream_t st) {
+                     double* key, double* logD, int* qsign, int* status, int nb, int Np,
+                     hipStream_t st) {
   const int NRB = Np / 16;
-  if (NRB <= 4) return run_qr<4>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, logD, qsign, status, nb, Np, st);
-  if (NRB <= 8) return run_qr<8>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, logD, qsign, status, nb, Np, st);
-  if (NRB <= 16) return run_qr<16>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, logD, qsign, status, nb, Np, st);
-  if (NRB <= 25) return run_qr<25>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, logD, qsign, status, nb, Np, st);
-  if (NRB <= 32) return run_qr<32>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, logD, qsign, status, nb, Np, st);
+  if (NRB <= 4) return run_qr<4>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, key, logD, qsign, status, nb, Np, st);
+  if (NRB <= 8) return run_qr<8>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, key, logD, qsign, status, nb, Np, st);
+  if (NRB <= 16) return run_qr<16>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, key, logD, qsign, status, nb, Np, st);
+  if (NRB <= 25) return run_qr<25>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, key, logD, qsign, status, nb, Np, st);
+  if (NRB <= 32) return run_qr<32>(A, astride, norm2, nstride, nparts, logDp, QRW, Tb, perm, key, logD, qsign, status, nb, Np, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_vupd(const double* QRW, const int* perm, const double* Vo, double* Vn, int nb,
-                       int Np, hipStream_t st) {
+hipError_t launch_vupd(const double* QRW, const int* perm, const double* key, const double* Vo,
+                       double* Vn, int nb, int Np, hipStream_t st) {
   const int NRB = Np / 16, RB = (NRB + 3) / 4;
   if (NRB <= 16) {
     // register-resident strips (Np <= 256): two F block rows and the partial tiles in LDS
@@ -1119,7 +1160,7 @@ hipError_t launch_vupd(const double* QRW, const int* perm, const double* Vo, dou
     const size_t lds = ((size_t)2 * 16 * (Np + 1) + 4 * 64 * 4) * sizeof(double);
 #define VUPD_SPLIT(NR)                                                                        \
   hipLaunchKernelGGL(vupd_split_k<NR>, dim3(xcd_grid(nb * npg)), dim3(512), lds, st, QRW, perm, \
-                     Vo, Vn, nb, Np)
+                     key, Vo, Vn, nb, Np)
     if (NRB <= 4) VUPD_SPLIT(4);
     else if (NRB <= 8) VUPD_SPLIT(8);
     else VUPD_SPLIT(16);

@@ -42,13 +42,16 @@ hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QR
                            int nb, int Np, hipStream_t st);
 
 // Column-pivoted (pre-sorted) blocked Householder QR of A[b] (one workgroup per item).
-// Sort key of column j: 0.5 log(sum_p norm2[b*nstride + p*Np + j]) + logDp[b][j].  Outputs: QRW[b]
-// (strict lower: Householder vectors; upper incl. diagonal: the V-update factor
-// F[i][j] = R[i][j]/|R[i][i]| exp(logDp[perm j] - logDp[perm i])), Tb, perm[b][Np],
-// logD[b][Np] = log|R_ii| + logDp[perm i], qsign[b] = det Q, status[b] |= 1 on NaN.
+// Sort key of column j: 0.5 log(sum_p norm2[b*nstride + p*Np + j]) + logDp[b][j]; key[j] =
+// logDp[b][perm j] (0 without logDp).  The V-update factor is F = S_r R S_c, F[i][j] =
+// R[i][j]/|R[i][i]| exp(key[j] - key[i]) (j >= i).  Outputs: QRW[b] (strict lower:
+// Householder vectors; upper incl. diagonal: R for Np <= 256, else F), for Np <= 256
+// scales[b][2 Np] = (S_c, S_r) = (e^(key_j - kref), e^(kref - key_i)/|R_ii|), Tb,
+// perm[b][Np], logD[b][Np] = log|R_ii| + key[i], qsign[b] = det Q, status[b] |= 1 on NaN.
 hipError_t launch_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride,
                      int nparts, const double* logDp, double* QRW, double* Tb, int* perm,
-                     double* logD, int* qsign, int* status, int nb, int Np, hipStream_t st);
+                     double* scales, double* logD, int* qsign, int* status, int nb, int Np,
+                     hipStream_t st);
 
 // dst[0..n) = value (a plain kernel, safe inside captured graphs)
 hipError_t launch_fill_i32(int* dst, int n, int value, hipStream_t st);
@@ -56,10 +59,10 @@ hipError_t launch_fill_i32(int* dst, int n, int value, hipStream_t st);
 // 4096 short polls, so it always ends)
 hipError_t launch_gate_delay(int us, hipStream_t st);
 
-// Vn[b] = F[b] Vo[b][perm[b], :] with F the upper triangle of QRW[b]
-// (Vo == nullptr: identity).
-hipError_t launch_vupd(const double* QRW, const int* perm, const double* Vo, double* Vn,
-                       int nb, int Np, hipStream_t st);
+// Vn[b] = F[b] Vo[b][perm[b], :] with F the V-update factor of launch_qr (for Np <= 256
+// S_r R S_c from R in the upper triangle of QRW[b] and scales[b]; Vo == nullptr: identity).
+hipError_t launch_vupd(const double* QRW, const int* perm, const double* scales, const double* Vo,
+                       double* Vn, int nb, int Np, hipStream_t st);
 
 // LU with partial pivoting of X = Db^-1 QT + Ds V (Db = max(e^logD,1), Ds = min(e^logD,1))
 // and logdet = sum max(logD, 0) + log|det X| - (Np-N) log 2, sign = qsign * sign det X.

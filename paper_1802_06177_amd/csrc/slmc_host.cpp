@@ -266,7 +266,7 @@ struct GroupBufs {
   // QR outputs (Householder vectors and the V-update factor, T blocks, column order) of
   // the last kQB steps: QR k reuses the buffers of step k - kQB
   static constexpr int kQB = 3;
-  double *S, *snorm, *A, *npart, *QRW[kQB], *Tb[kQB], *logD0, *logD1, *V0, *V1, *DI;
+  double *S, *snorm, *A, *npart, *QRW[kQB], *Tb[kQB], *key[kQB], *logD0, *logD1, *V0, *V1, *DI;
   int *perm[kQB], *qsign, *status, *prow, *item_of;
   int64_t *xoff, *goff;
 };
@@ -280,6 +280,7 @@ void carve(Arena& a, int nb, int Np, int m, GroupBufs& g) {
   for (int h = 0; h < GroupBufs::kQB; ++h) {
     g.QRW[h] = a.take<double>((size_t)nb * n2);
     g.Tb[h] = a.take<double>((size_t)nb * Np * 16);
+    g.key[h] = a.take<double>((size_t)nb * 2 * Np);
     g.perm[h] = a.take<int>((size_t)nb * Np);
   }
   g.logD0 = a.take<double>((size_t)nb * Np);
@@ -442,7 +443,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   hipEvent_t* ev_gt = overlap ? &ss->ev[4 * mseg + 1] : nullptr;
   auto vupd = [&](int kk, hipStream_t sv) -> int {
     ProfScope ps(3, sv);
-    HIPCHK(launch_vupd(w.QRW[kk % kQB], w.perm[kk % kQB], kk == 0 ? nullptr : Vb[(kk + 1) & 1], Vb[kk & 1],
+    HIPCHK(launch_vupd(w.QRW[kk % kQB], w.perm[kk % kQB], w.key[kk % kQB], kk == 0 ? nullptr : Vb[(kk + 1) & 1], Vb[kk & 1],
                        nb, Np, sv));
     return SLMC_OK;
   };
@@ -496,7 +497,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     {
     ProfScope ps(2, st);
     HIPCHK(launch_qr(Ain, astride, nrm, nstride, nparts, k == 0 ? nullptr : logD[(k + 1) & 1], QRWk,
-                     Tbk, permk, logD[k & 1], w.qsign, w.status, nb, Np, st));
+                     Tbk, permk, w.key[k % kQB], logD[k & 1], w.qsign, w.status, nb, Np, st));
     }
     // V_k = F P^T V_{k-1} is needed only by the recombination: off the chain's critical
     // path on s2 when overlapping (gated: released above one step later, the last one here)
