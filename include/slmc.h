@@ -98,8 +98,10 @@ typedef struct {
  * segment products and the V updates run on two streams the library owns (per device,
  * default priority, created on first use, destroyed by slmc_cache_clear), forked from and
  * joined back to the caller's stream with events, so that the sequential QR chain
- * overlaps the remaining segment products and the V updates.  Results are identical either way; calls from several
- * host threads on one device serialize while they enqueue. */
+ * overlaps the remaining segment products and the V updates (for SLMC_INT8X5 and
+ * SLMC_BF16X3 released step by step into the time of each QR, otherwise queued up
+ * front).  Results are identical either way; calls from several host threads on one
+ * device serialize while they enqueue. */
 enum slmc_flags {
   SLMC_FLAG_SERIAL = 1,  /* run every kernel on the caller's stream, in order           */
   SLMC_FLAG_STREAM_E = 2 /* SLMC_INT8X5: read every E slice from device memory in each
