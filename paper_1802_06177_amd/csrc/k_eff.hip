@@ -40,6 +40,8 @@ __device__ __forceinline__ double u01(uint32_t r) {
 }
 
 __device__ __forceinline__ int wrap(int a, int L) { a %= L; return a < 0 ? a + L : a; }
+// periodic wrap of -L <= a < 2 L without a division
+__device__ __forceinline__ int wrap1(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
 
 __device__ __forceinline__ double f4(double y, double a) {
   return 0.25 * y * y * y * y - 0.5 * a * a * y * y;
@@ -58,25 +60,26 @@ __device__ __forceinline__ double nbr_sum(const double* xs, int ix, int iy, int 
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    s += xs[wrap(ix + d[k][0], Lx) + Lx * wrap(iy + d[k][1], Ly)];
-    s += xs[wrap(ix - d[k][0], Lx) + Lx * wrap(iy - d[k][1], Ly)];
+    s += xs[wrap1(ix + d[k][0], Lx) + Lx * wrap1(iy + d[k][1], Ly)];
+    s += xs[wrap1(ix - d[k][0], Lx) + Lx * wrap1(iy - d[k][1], Ly)];
   }
   return s;
 }
 
 // E_eff(x with x[l][i] -> xn) - E_eff(x): the terms touching (i, l)
 __device__ __forceinline__ double local_delta(const double* x, int N, int Lx, int Ly, int Ltau,
-                                              const EffParams& p, int i, int l, double xn) {
+                                              const EffParams& p, int ix, int iy, int l,
+                                              double xn) {
+  const int i = ix + Lx * iy;
   const double xo = x[l * N + i];
-  const double xp = x[((l + 1) % Ltau) * N + i];
-  const double xm = x[((l - 1 + Ltau) % Ltau) * N + i];
+  const double xp = x[(l + 1 == Ltau ? 0 : l + 1) * N + i];
+  const double xm = x[(l == 0 ? Ltau - 1 : l - 1) * N + i];
   const double d = xn - xo;
   double de = p.Jk * ((xp - xn) * (xp - xn) - (xp - xo) * (xp - xo) + (xn - xm) * (xn - xm) -
                       (xo - xm) * (xo - xm));
   de += p.J2 * (xn * xn - xo * xo);
   de += p.Jp * (f4(xn, p.a) - f4(xo, p.a));
   de += p.Jp6 * (f6(xn, p.a) - f6(xo, p.a));
-  const int ix = i % Lx, iy = i / Lx;
   const double* xs = x + l * N;
   if (p.Js0 != 0.0) de += p.Js0 * d * nbr_sum(xs, ix, iy, Lx, Ly, 0);
   if (p.Js1 != 0.0) de += p.Js1 * d * nbr_sum(xs, ix, iy, Lx, Ly, 1);
@@ -165,24 +168,36 @@ __global__ __launch_bounds__(1024) void eff_sweep_k(double* __restrict__ x, int 
   const int nx = Lx / mod, ny = Ly / mod, per_l = nx * ny, cnt = (Ltau / 2) * per_l;
   const U4 cc = philox(U4{0xFFFFFFFFu, 0xFFFFFFFEu, prop, (uint32_t)ch}, k0, k1);
   const bool forward = cc.x < 0x80000000u;
+  // Work item t = lq per_l + ry nx + rx of a phase is the site (sx + mod rx, sy + mod ry) of
+  // slice tc + 2 lq.  A thread's items are t0, t0 + blockDim, ..., the same in every phase:
+  // their (lq, ry, rx) start from t0 and advance by blockDim's (dq, dry, drx) with carries,
+  // so the site loop does no integer division.
+  const int t0 = threadIdx.x, bd = blockDim.x;
+  const int lq0 = t0 / per_l, ry0 = (t0 - lq0 * per_l) / nx, rx0 = t0 - lq0 * per_l - ry0 * nx;
+  const int dq = bd / per_l, dry = (bd - dq * per_l) / nx, drx = bd - dq * per_l - dry * nx;
   int64_t acc = 0;
   for (int s = 0; s < n_sweeps; ++s) {
     for (int pi = 0; pi < P; ++pi) {
       const int ph = forward ? pi : P - 1 - pi;
       const int tc = ph / m2, sc = ph - tc * m2, sx = sc % mod, sy = sc / mod;
-      for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-        const int lq = t / per_l, rem = t - lq * per_l;
+      int lq = lq0, ry = ry0, rx = rx0;
+      for (int t = t0; t < cnt; t += bd) {
         const int l = tc + 2 * lq;
-        const int ix = sx + mod * (rem % nx), iy = sy + mod * (rem / nx);
+        const int ix = sx + mod * rx, iy = sy + mod * ry;
         const int i = ix + Lx * iy;
         const U4 r = philox(U4{(uint32_t)(i + N * l), (uint32_t)s, prop, (uint32_t)ch}, k0, k1);
         const double xo = xs[l * N + i];
         const double xn = xo + p.delta * (2.0 * u01(r.x) - 1.0);
-        const double de = local_delta(xs, N, Lx, Ly, Ltau, p, i, l, xn);
+        const double de = local_delta(xs, N, Lx, Ly, Ltau, p, ix, iy, l, xn);
         if (log(u01(r.y)) < -de) {
           xs[l * N + i] = xn;
           ++acc;
         }
+        rx += drx;
+        ry += dry;
+        lq += dq;
+        if (rx >= nx) { rx -= nx; ++ry; }
+        if (ry >= ny) { ry -= ny; ++lq; }
       }
       if (!IN_LDS) __threadfence_block();
       __syncthreads();
