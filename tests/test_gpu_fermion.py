@@ -165,6 +165,31 @@ def test_uneven_batch_one_call():
         assert np.max(np.abs(Gj - rG)) < 1e-9
 
 
+@pytest.mark.parametrize("prec", ["int8x5", "bf16x3", "fp64"])
+@pytest.mark.parametrize("Ltau,n_s", [(16, 8), (24, 8), (32, 8), (20, 5), (18, 8)])
+def test_few_blocks_overlapped_match_serial_bitwise(prec, Ltau, n_s):
+    # 2, 3 and 4 stabilization blocks (and a short last block): the step-by-step release of
+    # the side work and the reuse of the three QR output buffers at their smallest counts
+    md = _md(8, Ltau, n_s)
+    g = gen(99, Ltau + n_s)
+    xs = [g.normal(size=(Ltau, 64)) for _ in range(3)]
+    m = slmc.model_from_dict(md)
+    x = torch.tensor(np.stack(xs), dtype=torch.float64, device=DEV)
+    print("case: 8x8 Ltau=%d n_s=%d prec=%s overlapped vs serial" % (Ltau, n_s, prec), flush=True)
+    outs = []
+    for serial in (False, True):
+        ld, sg, G, st = slmc.green(m, x, slmc.options(prec, 1, serial=serial))
+        torch.cuda.synchronize()
+        outs.append((ld.cpu().numpy(), sg.cpu().numpy(), G.cpu().numpy(), st.cpu().numpy()))
+    assert np.all(outs[0][3] == 0)
+    for u, v in zip(outs[0], outs[1]):
+        assert np.array_equal(u, v)
+    bar = 1e-11 if prec == "fp64" else (1e-8 if prec == "int8x5" else 1e-3)
+    for k in range(3):
+        ref = _ref(md, xs[k])[0]
+        assert abs(outs[0][0][k] - ref) <= bar * abs(ref)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "int8x5"])
 def test_packed_groups_overlapped_match_serial_bitwise(prec):
     # six lattice sizes in one call, items interleaved (item tables go into the workspace);
