@@ -244,7 +244,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-alone", action="store_true",
                     help="skip the serial-schedule run of the slice-product kernel")
-    ap.add_argument("--cpu-sample", type=int, default=6, help="oracle items for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=20,
+                    help="oracle items for cpu_baseline, about 10-30 s of CPU work (0: skip)")
     ap.add_argument("--uneven", action="store_true",
                     help="also time the uneven packed batch (L = 8, 12, 16, 20), headline "
                          "precision and FP64, with one oracle-checked item per size class")
