@@ -204,33 +204,34 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
     if (h0) prow[j0 + tid] = pr0;
     if (h1) prow[j0 + tid + 256] = pr1;
     __syncthreads();
-    // inverses of the unit-lower L11 (wave 0) and upper U11 (wave 1), one column per lane
+    // inverses of the unit-lower L11 (wave 0) and upper U11 (wave 1), one column per lane,
+    // the column in registers (its zero entries add exact zeros to the sums, which keep the
+    // order l = j .. i-1, resp. i+1 .. j, of the nonzero terms)
     if (w == 0 && lane < 16) {
       const int j = lane;
+      double x[16];
+#pragma unroll
       for (int i = 0; i < 16; ++i) {
-        double x;
-        if (i < j) x = 0.0;
-        else if (i == j) x = 1.0;
-        else {
-          double s = 0.0;
-          for (int l = j; l < i; ++l) s += Pn[i * LDY + l] * Li[l * LDY + j];
-          x = -s;
-        }
-        Li[i * LDY + j] = x;
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < i; ++l) s += Pn[i * LDY + l] * x[l];
+        x[i] = (i < j) ? 0.0 : (i == j ? 1.0 : -s);
       }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Li[i * LDY + j] = x[i];
     } else if (w == 1 && lane < 16) {
       const int j = lane;
+      double x[16];
+#pragma unroll
       for (int i = 15; i >= 0; --i) {
-        double x;
-        if (i > j) x = 0.0;
-        else {
-          double s = (i == j) ? 1.0 : 0.0;
-          for (int l = i + 1; l <= j; ++l) s -= Pn[i * LDY + l] * Ui[l * LDY + j];
-          const double u = Pn[i * LDY + i];
-          x = (u != 0.0) ? s / u : 0.0;
-        }
-        Ui[i * LDY + j] = x;
+        double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = i + 1; l < 16; ++l) s -= Pn[i * LDY + l] * x[l];
+        const double u = Pn[i * LDY + i];
+        x[i] = (i > j) ? 0.0 : ((u != 0.0) ? s / u : 0.0);
       }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Ui[i * LDY + j] = x[i];
     }
     __syncthreads();
     for (int idx = tid; idx < 512; idx += 256) {
