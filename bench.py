@@ -36,7 +36,7 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "int8x5": 15}   # pe
 # HBM bytes per launch of a kernel class at the 16x16 / 128-chain workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain 1 GiB copy
 # (factors 2.0 and 1.0); valid only for the kernel versions they were taken on.
-TRAFFIC = {("qr", "int8x5"): 615.3e6, ("seg_chain", "int8x5"): 82.5e6}
+TRAFFIC = {("qr", "int8x5"): 619.7e6, ("seg_chain", "int8x5"): 82.5e6}
 
 
 def run(slmc, torch, md, eff, xs, B, prec, args):
