@@ -669,11 +669,10 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
     }
   }
 
-  // ---- outputs: log D, det Q, perm, and the V-update factor F = S_r R S_c: for Np > 256
-  // formed here in the upper triangle; for Np <= 256 only the two diagonal scalings go out
-  // (S_c = e^(key_j - kref), S_r = e^(kref - key_i) / |R_ii|, with kref the middle of the
-  // key range so that neither overflows before F itself would) and the V update applies
-  // them to its operand rows and output rows, off the chain's critical path
+  // ---- outputs: log D, det Q, perm, and the two diagonal scalings of the V-update factor
+  // F = S_r R S_c (S_c = e^(key_j - kref), S_r = e^(kref - key_i) / |R_ii|, with kref the
+  // middle of the key range so that neither overflows before F itself would); the V update
+  // applies them to its operand rows and output rows, off the chain's critical path
   int ntau = 0;
   double kmax = -INFINITY, kmin = INFINITY;
   for (int i = tid; i < Np; i += QR_THREADS) {
@@ -701,7 +700,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
     if (flag[0]) status[b] |= 1;
     if (flag[1]) status[b] |= 8;
   }
-  if constexpr (NRBMAX <= 16) {
+  {
     double hi = red[0], lo = red[8];
     for (int k = 1; k < QR_THREADS / 64; ++k) {
       hi = fmax(hi, red[k]);
@@ -713,22 +712,6 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
       keyo[(size_t)b * 2 * Np + i] = exp(key[i] - kref);
       keyo[(size_t)b * 2 * Np + Np + i] = exp(kref - key[i]) / fabs(beta[i]);
     }
-    return;
-  }
-  // two adjacent entries of a row per thread and step (16-byte accesses), several steps in
-  // flight: this pass is on the chain's critical path
-#pragma unroll 4
-  for (int idx = 2 * tid; idx < Np * Np; idx += 2 * QR_THREADS) {
-    const int i = idx / Np, j = idx - i * Np;
-    if (j + 1 >= i) {
-      double2* qp = (double2*)(Q + (size_t)i * Np + j);
-      const double2 r = *qp;
-      const double bi = beta[i], ibi = 1.0 / fabs(bi), ki = key[i];
-      double2 f;
-      f.x = (j > i) ? r.x * ibi * exp(key[j] - ki) : (j == i ? (bi < 0.0 ? -1.0 : 1.0) : r.x);
-      f.y = (j + 1 > i) ? r.y * ibi * exp(key[j + 1] - ki) : (bi < 0.0 ? -1.0 : 1.0);
-      *qp = f;
-    }
   }
 }
 
@@ -737,6 +720,7 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
 template <int RB, int CB>
 __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
                                               const int* __restrict__ perm,
+                                              const double* __restrict__ scales,
                                               const double* __restrict__ Vo,
                                               double* __restrict__ Vn, int nb, int Np) {
   constexpr int W = 16 * CB;
@@ -748,13 +732,18 @@ __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
   if (id < 0) return;
   const int pan = id % npan, b = id / npan, c0 = pan * W;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
-  const double* F = QRW + (size_t)b * Np * Np;
+  const double* F = QRW + (size_t)b * Np * Np;   // R in the upper triangle
   const int* pb = perm + (size_t)b * Np;
+  // the factor is S_r R S_c (diagonal scalings from the QR): P = S_c P^T V_old here, the
+  // output rows scaled by S_r when stored
+  const double* csc = scales + (size_t)b * 2 * Np;
+  const double* rsc = csc + Np;
   for (int idx = tid; idx < W * Np; idx += 256) {
     const int q = idx / W, j = idx - q * W;
     const int src = pb[q];
-    P[j * LDP + q] = Vo ? Vo[(size_t)b * Np * Np + (size_t)src * Np + c0 + j]
+    const double x = Vo ? Vo[(size_t)b * Np * Np + (size_t)src * Np + c0 + j]
                         : (src == c0 + j ? 1.0 : 0.0);
+    P[j * LDP + q] = csc[q] * x;
   }
   __syncthreads();
   dx4 acc[RB][CB];
@@ -800,8 +789,10 @@ __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        out[(size_t)(16 * rb + drow64(g, v)) * Np + c0 + 16 * cb + c] = acc[r][cb][v];
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rb + drow64(g, v);
+        out[(size_t)row * Np + c0 + 16 * cb + c] = rsc[row] * acc[r][cb][v];
+      }
   }
 }
 
@@ -1065,17 +1056,17 @@ hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t
 }
 
 template <int RB>
-hipError_t run_vupd(const double* QRW, const int* perm, const double* Vo, double* Vn, int nb,
-                    int Np, hipStream_t st) {
+hipError_t run_vupd(const double* QRW, const int* perm, const double* scales, const double* Vo,
+                    double* Vn, int nb, int Np, hipStream_t st) {
   constexpr int CB = 2;
   if (Np % 32 == 0) {
     const size_t lds = (size_t)(16 * CB) * (Np + 2) * sizeof(double);
     hipLaunchKernelGGL((vupd_k<RB, CB>), dim3(xcd_grid(nb * (Np / 32))), dim3(256), lds, st, QRW,
-                       perm, Vo, Vn, nb, Np);
+                       perm, scales, Vo, Vn, nb, Np);
   } else {
     const size_t lds = (size_t)16 * (Np + 2) * sizeof(double);
     hipLaunchKernelGGL((vupd_k<RB, 1>), dim3(xcd_grid(nb * (Np / 16))), dim3(256), lds, st, QRW,
-                       perm, Vo, Vn, nb, Np);
+                       perm, scales, Vo, Vn, nb, Np);
   }
   return hipGetLastError();
 }
@@ -1168,14 +1159,14 @@ hipError_t launch_vupd(const double* QRW, const int* perm, const double* key, co
     return hipGetLastError();
   }
   switch (RB) {
-    case 1: return run_vupd<1>(QRW, perm, Vo, Vn, nb, Np, st);
-    case 2: return run_vupd<2>(QRW, perm, Vo, Vn, nb, Np, st);
-    case 3: return run_vupd<3>(QRW, perm, Vo, Vn, nb, Np, st);
-    case 4: return run_vupd<4>(QRW, perm, Vo, Vn, nb, Np, st);
-    case 5: return run_vupd<5>(QRW, perm, Vo, Vn, nb, Np, st);
-    case 6: return run_vupd<6>(QRW, perm, Vo, Vn, nb, Np, st);
-    case 7: return run_vupd<7>(QRW, perm, Vo, Vn, nb, Np, st);
-    case 8: return run_vupd<8>(QRW, perm, Vo, Vn, nb, Np, st);
+    case 1: return run_vupd<1>(QRW, perm, key, Vo, Vn, nb, Np, st);
+    case 2: return run_vupd<2>(QRW, perm, key, Vo, Vn, nb, Np, st);
+    case 3: return run_vupd<3>(QRW, perm, key, Vo, Vn, nb, Np, st);
+    case 4: return run_vupd<4>(QRW, perm, key, Vo, Vn, nb, Np, st);
+    case 5: return run_vupd<5>(QRW, perm, key, Vo, Vn, nb, Np, st);
+    case 6: return run_vupd<6>(QRW, perm, key, Vo, Vn, nb, Np, st);
+    case 7: return run_vupd<7>(QRW, perm, key, Vo, Vn, nb, Np, st);
+    case 8: return run_vupd<8>(QRW, perm, key, Vo, Vn, nb, Np, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -45,9 +45,9 @@ hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QR
 // Sort key of column j: 0.5 log(sum_p norm2[b*nstride + p*Np + j]) + logDp[b][j]; key[j] =
 // logDp[b][perm j] (0 without logDp).  The V-update factor is F = S_r R S_c, F[i][j] =
 // R[i][j]/|R[i][i]| exp(key[j] - key[i]) (j >= i).  Outputs: QRW[b] (strict lower:
-// Householder vectors; upper incl. diagonal: R for Np <= 256, else F), for Np <= 256
-// scales[b][2 Np] = (S_c, S_r) = (e^(key_j - kref), e^(kref - key_i)/|R_ii|), Tb,
-// perm[b][Np], logD[b][Np] = log|R_ii| + key[i], qsign[b] = det Q, status[b] |= 1 on NaN.
+// Householder vectors; upper incl. diagonal: R), scales[b][2 Np] = (S_c, S_r) =
+// (e^(key_j - kref), e^(kref - key_i)/|R_ii|), Tb, perm[b][Np], logD[b][Np] = log|R_ii| +
+// key[i], qsign[b] = det Q, status[b] |= 1 on NaN.
 hipError_t launch_qr(const double* A, int64_t astride, const double* norm2, int64_t nstride,
                      int nparts, const double* logDp, double* QRW, double* Tb, int* perm,
                      double* scales, double* logD, int* qsign, int* status, int nb, int Np,
@@ -59,8 +59,8 @@ hipError_t launch_fill_i32(int* dst, int n, int value, hipStream_t st);
 // 4096 short polls, so it always ends)
 hipError_t launch_gate_delay(int us, hipStream_t st);
 
-// Vn[b] = F[b] Vo[b][perm[b], :] with F the V-update factor of launch_qr (for Np <= 256
-// S_r R S_c from R in the upper triangle of QRW[b] and scales[b]; Vo == nullptr: identity).
+// Vn[b] = F[b] Vo[b][perm[b], :] with F = S_r R S_c the V-update factor of launch_qr, from R
+// in the upper triangle of QRW[b] and scales[b] (Vo == nullptr: identity).
 hipError_t launch_vupd(const double* QRW, const int* perm, const double* scales, const double* Vo,
                        double* Vn, int nb, int Np, hipStream_t st);
 
