@@ -101,7 +101,10 @@ typedef struct {
  * overlaps the remaining segment products and the V updates (for SLMC_INT8X5 and
  * SLMC_BF16X3 released step by step into the time of each QR, otherwise queued up
  * front).  Results are identical either way; calls from several host threads on one
- * device serialize while they enqueue. */
+ * device serialize while they enqueue.  A call on one model can be captured into a HIP
+ * graph on the caller's stream (the library's streams fork from it and join back through
+ * events; no memset, no host synchronization); a packed call whose items are not laid out
+ * at a constant stride uploads its item tables synchronously and cannot be captured. */
 enum slmc_flags {
   SLMC_FLAG_SERIAL = 1,  /* run every kernel on the caller's stream, in order           */
   SLMC_FLAG_STREAM_E = 2 /* SLMC_INT8X5: read every E slice from device memory in each
