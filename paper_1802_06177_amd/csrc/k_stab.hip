@@ -428,6 +428,73 @@ __device__ __forceinline__ void update_block(int nrbK, int j0, int cb, bool from
   }
 }
 
+// update_block for large Np: the column block goes through registers CH row blocks at a
+// time (all of it would not fit beside the other role's registers): one pass accumulates
+// W = Y^T blk over all row blocks, a second reloads each chunk, applies the update and
+// stores it.  The MFMA accumulation order is that of apply_panel, so the result is the same.
+template <int CH>
+__device__ __forceinline__ void update_block_chunked(int nrbK, int j0, int cb, bool from_a,
+                                                     const double* __restrict__ Ab,
+                                                     const int* __restrict__ iperm,
+                                                     double* __restrict__ Q, int Np,
+                                                     const double* Pc, const double* Tc, int lane) {
+  int c = lane & 15, g = lane >> 4;
+  __asm__ volatile("" : "+v"(c), "+v"(g));
+  const int col = 16 * cb + c;
+  const double* src = from_a ? Ab + iperm[col] : Q + (size_t)j0 * Np + col;
+  double* dst = Q + (size_t)j0 * Np + col;
+  dx4 aw[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
+  for (int r0 = 0; r0 < nrbK; r0 += CH) {
+    dx4 blk[CH];
+#pragma unroll
+    for (int rb = 0; rb < CH; ++rb) {
+      if (r0 + rb < nrbK) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) blk[rb][v] = src[(16 * (r0 + rb) + drow64(g, v)) * Np];
+      }
+    }
+#pragma unroll
+    for (int rb = 0; rb < CH; ++rb) {
+      if (r0 + rb < nrbK) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          aw[s] = mfma64(yval(Pc, 16 * (r0 + rb) + drow64(g, s), c), blk[rb][s], aw[s]);
+      }
+    }
+  }
+  const dx4 W = aw[0] + aw[1] + aw[2] + aw[3];
+  double tv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) tv[s] = Tc[drow64(g, s) * LDY + c];
+  dx4 Wt = zero4d();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) Wt = mfma64(tv[s], W[s], Wt);
+  for (int r0 = 0; r0 < nrbK; r0 += CH) {
+    dx4 blk[CH];
+#pragma unroll
+    for (int rb = 0; rb < CH; ++rb) {
+      if (r0 + rb < nrbK) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) blk[rb][v] = src[(16 * (r0 + rb) + drow64(g, v)) * Np];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int rb = 0; rb < CH; ++rb) {
+        if (r0 + rb < nrbK) blk[rb] = mfma64(-yval(Pc, 16 * (r0 + rb) + c, drow64(g, s)), Wt[s], blk[rb]);
+      }
+    }
+#pragma unroll
+    for (int rb = 0; rb < CH; ++rb) {
+      if (r0 + rb < nrbK) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(16 * (r0 + rb) + drow64(g, v)) * Np] = blk[rb][v];
+      }
+    }
+  }
+}
+
 // Rows of a column block owned by panel wave w in the split update below (row blocks w,
 // w+4, .. of the rows j0 ..), loaded ahead of use: from A through the column order on the
 // first step (from_a), from Q after.
@@ -656,6 +723,10 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
         // trailing column blocks q+1 .. with panel p; the first (wave 4) is announced to the
         // panel waves, which prefetch it for the next step
         for (int cb = q + 1 + (w - QR_PANEL_WAVES); cb < NRB; cb += QR_THREADS / 64 - QR_PANEL_WAVES) {
+          if constexpr (NRBMAX > 16)
+            update_block_chunked<13>(NRB - p, 16 * p, cb, p == 0, Ab, iperm, Q, Np,
+                                     Pn0 + (p & 1) * Np * LDY, Tl0 + (p & 1) * 16 * LDY, lane);
+          else
           update_block<NRBMAX>(NRB - p, 16 * p, cb, p == 0, Ab, iperm, Q, Np,
                                Pn0 + (p & 1) * Np * LDY, Tl0 + (p & 1) * 16 * LDY, nullptr, lane);
           if (cb == q + 1) {
