@@ -177,6 +177,31 @@ def uneven_rates(slmc, torch, np, prec, reps=3, check=False):
     return out
 
 
+def small_rates(slmc, torch, np, reps=20):
+    """The small workload (4x4, Ltau = 40, n_s = 10, lam = 1.5, its 64 fields: 48 Gaussian
+    and 16 staggered): log-det + G of all 64 in one call, per precision, from HIP events
+    over reps calls (latency-bound: a handful of small launches per call)."""
+    from synth import workload_item, workload_models
+    md = workload_models("W1")[0]
+    m = slmc.model_from_dict(md)
+    x = torch.tensor(np.stack([workload_item("W1", b)[1] for b in range(64)]), dtype=torch.float64,
+                     device="cuda:0")
+    out = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for prec in ("fp64", "int8x5"):
+        opt = slmc.options(prec, 1 if prec != "fp64" else 0)
+        slmc.green(m, x, opt)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            slmc.green(m, x, opt)
+        ev1.record()
+        torch.cuda.synchronize()
+        t = ev0.elapsed_time(ev1) / 1e3 / reps
+        out[prec] = {"evals_per_s": round(64 / t, 1), "ms_per_call": round(t * 1e3, 4)}
+    return out
+
+
 def roofline(prof, prec, md, B, steps, counters_apply, kernel=None):
     """A kernel class (default: the dominant one, largest event time in the timed region)
     against its peak: achieved = algorithmic work per launch / average launch time."""
@@ -249,6 +274,8 @@ def main():
     ap.add_argument("--uneven", action="store_true",
                     help="also time the uneven packed batch (L = 8, 12, 16, 20), headline "
                          "precision and FP64, with one oracle-checked item per size class")
+    ap.add_argument("--small", action="store_true",
+                    help="also time the small 4x4, Ltau 40 workload (64 fields, one call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (reference "
                          "for the HBM byte counters) and exit")
@@ -363,6 +390,8 @@ def main():
         uneven = {args.precision: uneven_rates(slmc, torch, np, args.precision, check=True),
                   "fp64": uneven_rates(slmc, torch, np, "fp64", check=True)}
 
+    small = small_rates(slmc, torch, np) if args.small else None
+
     out = {
         "metric": "fermion logdet+G evals/s at N=256,Ltau=160: mixed vs FP64, <=1e-8 rel err",
         "value": round(value, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -378,6 +407,7 @@ def main():
         "fp64_path": fp64,
         "sweep_only": sweep,
         "uneven_packed": uneven,
+        "small_4x4": small,
         "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
     }
     print(json.dumps(out), flush=True)
