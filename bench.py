@@ -16,8 +16,14 @@ The headline run uses the mixed path that meets the 1e-8 relative log-det target
 products on the int8 matrix cores with 5-slice splits, everything else FP64); the FP64
 path is timed the same way beside it ("mixed vs FP64").  Also printed: the roofline of
 the dominant kernel (HIP events around its launches on its own stream), the roofline of
-the slice-product kernel in the overlapped run and with every kernel run alone, and the
-FP64 CPU oracle timed on a bounded sample of the same fields.
+the slice-product kernel in the overlapped run and with every kernel run alone, the
+effective-model sweeps alone, and the other workloads: 4x4 Ltau 40 (64 fields), 8x8
+Ltau 80 (256 fields in one call, FP64 against FP32 matrix cores and the int8 split),
+the 12x12 Ltau 120 proposal step of 64 chains (sweep + FP64 cumulative accept), the
+uneven packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
+The cpu_baseline leg times the FP64 CPU oracle on a bounded sample of the 16x16 fields
+(one BLAS thread) and runs it over every GPU output of the other legs in a pool of
+one-thread workers, which gives each leg's error against it.
 """
 
 import argparse
@@ -35,8 +41,12 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "int8
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "int8x5": 15}   # per slice product
 # HBM bytes per launch of a kernel class at the 16x16 / 128-chain workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain 1 GiB copy
-# (factors 2.0 and 1.0); valid only for the kernel versions they were taken on.
+# (factors 2.0 and 1.0).  They are not measured by this script: they are read from the
+# committed summary named in TRAFFIC_SOURCE and are valid only for the kernel versions it
+# was taken on (the bench line carries the source with the figure).
 TRAFFIC = {("qr", "int8x5"): 619.7e6, ("seg_chain", "int8x5"): 82.5e6}
+TRAFFIC_SOURCE = ("profiles/fermion_step_16x16_ltau160_int8x5_128chains.md (rocprofv3 --pmc "
+                  "FETCH_SIZE / WRITE_SIZE of the seg_chain_i8 and qr_k kernels as committed in 28bbe9a)")
 
 
 def run(slmc, torch, md, eff, xs, B, prec, args):
@@ -48,7 +58,7 @@ def run(slmc, torch, md, eff, xs, B, prec, args):
     x_cur = torch.tensor(xs, dtype=torch.float64, device=dev)
     x_prop = torch.empty_like(x_cur)
     G = torch.empty((B, N, N), dtype=torch.float64, device=dev)
-    logw = slmc.log_weight(m, x_cur, opt)
+    logw, _ = slmc.log_weight(m, x_cur, opt)
     eeff = slmc.eff_energy(m, eff, x_cur)
     seed = 20180216
 
@@ -65,7 +75,7 @@ def run(slmc, torch, md, eff, xs, B, prec, args):
     t0 = time.perf_counter()
     accs = []
     for k in range(args.warmup, args.warmup + args.steps):
-        a, _ = step(k)
+        a, _, _ = step(k)
         accs.append(a)
     ev1.record()
     torch.cuda.synchronize()
@@ -109,12 +119,11 @@ def sweep_rates(slmc, torch, np, chains, n_sweeps=4, reps=5):
             "working_set_MB": round(8.0 * chains * Lx * Ly * Lt / 1e6, 1)}
 
 
-def uneven_rates(slmc, torch, np, prec, reps=3, check=False):
+def uneven_rates(slmc, torch, np, prec, reps=3):
     """The uneven packed batch: 32 fields for each of L = 8, 12, 16, 20 (Ltau = 10 L,
     n_s = 10, lam = 1.5), items interleaved across the four sizes, log-det + G of all 128 in
     one packed call; then each size class alone (32 items, one call).  Evaluations per
-    second from HIP events; with check, the relative log-det error and max |dG| of the first
-    item of every class against the oracle."""
+    second from HIP events.  Also returns the packed call's outputs (for the oracle check)."""
     from synth import workload_item, workload_models
     dev = torch.device("cuda:0")
     mds = workload_models("W5")
@@ -126,17 +135,6 @@ def uneven_rates(slmc, torch, np, prec, reps=3, check=False):
         xs.append(x)
         midx.append(mi)
     opt = slmc.options(prec, 1 if prec != "fp64" else 0)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(reps):
-            fn()
-        ev1.record()
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / 1e3 / reps
 
     def packed(sel):
         xsel = [xs[j] for j in sel]
@@ -149,32 +147,52 @@ def uneven_rates(slmc, torch, np, prec, reps=3, check=False):
         ws = torch.empty(slmc.workspace_bytes(models, len(sel), opt, model_idx=msel, x_off=x_off,
                                               g_off=g_off), dtype=torch.uint8, device=dev)
         return lambda: slmc.green(models, x, opt, model_idx=msel, x_off=x_off, g_off=g_off,
-                                  n_items=len(sel), G=G, ws=ws), G, g_off
+                                  n_items=len(sel), G=G, ws=ws), g_off
 
-    fn, G, g_off = packed(list(range(128)))
-    t_all = timed(fn)
+    fn, g_off = packed(list(range(128)))
+    t_all = _timed(torch, fn, reps)
     out = {"packed_128": {"evals_per_s": round(128 / t_all, 1), "ms_per_call": round(t_all * 1e3, 3)}}
     for mi, d in enumerate(mds):
         sel = [j for j in range(128) if midx[j] == mi]
-        fc, _, _ = packed(sel)
-        tc = timed(fc)
+        fc, _ = packed(sel)
+        tc = _timed(torch, fc, reps)
         out["L%d_Ltau%d" % (d["Lx"], d["Ltau"])] = {"items": len(sel), "evals_per_s": round(len(sel) / tc, 1),
                                                      "ms_per_call": round(tc * 1e3, 3)}
-    if check:
-        import oracle
-        ld, _, Gp, _ = fn()
-        torch.cuda.synchronize()
-        ld, Gh = ld.cpu().numpy(), Gp.cpu().numpy()
-        for mi, d in enumerate(mds):
-            j = midx.index(mi)
-            N = d["Lx"] * d["Ly"]
-            E = oracle.expk(oracle.hopping_matrix(d["Lx"], d["Ly"], d["t"], d["mu"]), d["dtau"])
-            ref, _, rG = oracle.logdet_green(E, xs[j], d["dtau"], d["lam"], d["n_s"])[:3]
-            Gj = Gh[g_off[j]:g_off[j] + N * N].reshape(N, N)
-            key = "L%d_Ltau%d" % (d["Lx"], d["Ltau"])
-            out[key]["rel_logdet_err_item0"] = float(abs(ld[j] - ref) / abs(ref))
-            out[key]["max_abs_dG_item0"] = float(np.max(np.abs(Gj - rG)))
-    return out
+    out["sum_of_classes_ms"] = round(sum(v["ms_per_call"] for k, v in out.items() if k.startswith("L")), 3)
+    ld, sg, Gp, st = fn()
+    torch.cuda.synchronize()
+    ld, sg, Gh, st = ld.cpu().numpy(), sg.cpu().numpy(), Gp.cpu().numpy(), st.cpu().numpy()
+    checks = []
+    for j in range(128):
+        d = mds[midx[j]]
+        N = d["Lx"] * d["Ly"]
+        checks.append(("L%d_Ltau%d" % (d["Lx"], d["Ltau"]), d, xs[j], float(ld[j]), int(st[j]),
+                       Gh[g_off[j]:g_off[j] + N * N].reshape(N, N), int(sg[j])))
+    return out, checks
+
+
+def _timed(torch, fn, reps):
+    """Seconds per call of fn from HIP events (one untimed call first)."""
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3 / reps
+
+
+def _green_all(slmc, torch, np, md, xs, prec, resid, chunk=0, reps=10):
+    """log-det + G of all fields in one call: seconds per call and the outputs."""
+    m = slmc.model_from_dict(md)
+    x = torch.tensor(np.stack(xs), dtype=torch.float64, device="cuda:0")
+    opt = slmc.options(prec, resid, chunk)
+    t = _timed(torch, lambda: slmc.green(m, x, opt), reps)
+    ld, sg, G, st = slmc.green(m, x, opt)
+    torch.cuda.synchronize()
+    return t, (ld.cpu().numpy(), sg.cpu().numpy(), G.cpu().numpy(), st.cpu().numpy())
 
 
 def small_rates(slmc, torch, np, reps=20):
@@ -183,23 +201,91 @@ def small_rates(slmc, torch, np, reps=20):
     over reps calls (latency-bound: a handful of small launches per call)."""
     from synth import workload_item, workload_models
     md = workload_models("W1")[0]
-    m = slmc.model_from_dict(md)
-    x = torch.tensor(np.stack([workload_item("W1", b)[1] for b in range(64)]), dtype=torch.float64,
-                     device="cuda:0")
-    out = {}
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    xs = [workload_item("W1", b)[1] for b in range(64)]
+    out, checks = {}, []
     for prec in ("fp64", "int8x5"):
-        opt = slmc.options(prec, 1 if prec != "fp64" else 0)
-        slmc.green(m, x, opt)
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(reps):
-            slmc.green(m, x, opt)
-        ev1.record()
-        torch.cuda.synchronize()
-        t = ev0.elapsed_time(ev1) / 1e3 / reps
+        t, res = _green_all(slmc, torch, np, md, xs, prec, 1 if prec != "fp64" else 0, reps=reps)
         out[prec] = {"evals_per_s": round(64 / t, 1), "ms_per_call": round(t * 1e3, 4)}
-    return out
+        checks += [(prec, md, xs[b], float(res[0][b]), int(res[3][b]), res[2][b], int(res[1][b]))
+                   for b in range(64)]
+    return out, checks
+
+
+def fields_8x8_rates(slmc, torch, np, reps=10):
+    """8x8 (N = 64), Ltau = 80, n_s = 10, lam = 1.5: 256 seeded Gaussian fields in one
+    call, log-det + G: the FP64 path against FP32 matrix-core segment products (FP64
+    promotion every k-step of 4, compensation of E's rounding, one residual step) and
+    against the int8-slice path, FP64 QR/UDV in all three."""
+    from synth import workload_item, workload_models
+    md = workload_models("W2")[0]
+    xs = [workload_item("W2", b)[1] for b in range(256)]
+    out, checks = {}, []
+    for prec, resid, chunk in (("fp64", 0, 0), ("fp32", 1, 1), ("int8x5", 1, 0)):
+        t, res = _green_all(slmc, torch, np, md, xs, prec, resid, chunk, reps=reps)
+        out[prec] = {"evals_per_s": round(256 / t, 1), "ms_per_call": round(t * 1e3, 4)}
+        checks += [(prec, md, xs[b], float(res[0][b]), int(res[3][b]), res[2][b], int(res[1][b]))
+                   for b in range(256)]
+    out["fp32_over_fp64"] = round(out["fp32"]["evals_per_s"] / out["fp64"]["evals_per_s"], 4)
+    out["int8x5_over_fp64"] = round(out["int8x5"]["evals_per_s"] / out["fp64"]["evals_per_s"], 4)
+    return out, checks
+
+
+def errors_16x16(slmc, torch, np, prec, lam_idx):
+    """GPU outputs of the headline path on all 128 fields of the 16x16 workload at one
+    coupling (for the oracle check)."""
+    from synth import workload_item, workload_models
+    md = workload_models("W4", lam_idx)[0]
+    xs = [workload_item("W4", b, lam_idx)[1] for b in range(128)]
+    _, res = _green_all(slmc, torch, np, md, xs, prec, 1, reps=1)
+    return [(prec, md, xs[b], float(res[0][b]), int(res[3][b]), res[2][b], int(res[1][b]))
+            for b in range(128)]
+
+
+def accept_12x12(slmc, torch, np, steps=10):
+    """64 chains of the 12x12, Ltau = 120 shape (n_s = 10, lam = 1.5) with the seeded
+    effective model (couplings out to the third neighbour): one proposal = copy, one
+    checkerboard sweep (N Ltau site updates), FP64 cumulative accept (log-det of every
+    proposal, bosonic action, effective energy, Eq. 6).  Proposals per second of the whole
+    step and of the accept call alone (HIP events), and the first proposal's inputs and
+    outputs for the oracle check."""
+    from synth import gen, eff_coefficients, workload_models
+    md = workload_models("W3")[0]
+    m = slmc.model_from_dict(md)
+    effd = eff_coefficients(3, 0, md["lam"], delta=0.5)
+    eff = slmc.eff_model(**effd)
+    chains = 64
+    x0 = gen(3, 500).normal(size=(chains, md["Ltau"], md["Lx"] * md["Ly"]))
+    x_cur = torch.tensor(x0, dtype=torch.float64, device="cuda:0")
+    x_prop = torch.empty_like(x_cur)
+    opt = slmc.options("fp64")
+    logw, _ = slmc.log_weight(m, x_cur, opt)
+    eeff = slmc.eff_energy(m, eff, x_cur)
+    seed = 1802061770
+    logw0, eeff0 = logw.cpu().numpy(), eeff.cpu().numpy()
+    x_prop.copy_(x_cur)
+    slmc.eff_sweep(m, eff, x_prop, 1, seed, 0)
+    xp0 = x_prop.cpu().numpy()
+    acc0, lr0, st0 = slmc.cumulative_accept(m, eff, x_cur, x_prop, logw, eeff, seed, 0, opt)
+    first = dict(md=md, eff=effd, seed=seed, x_cur=x0, x_prop=xp0, logw=logw0, eeff=eeff0,
+                 accepted=acc0.cpu().numpy(), log_ratio=lr0.cpu().numpy(), status=st0.cpu().numpy())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for k in range(1, steps + 1):
+        x_prop.copy_(x_cur)
+        slmc.eff_sweep(m, eff, x_prop, 1, seed, k)
+        ev[2 * k].record()
+        slmc.cumulative_accept(m, eff, x_cur, x_prop, logw, eeff, seed, k, opt)
+        ev[2 * k + 1].record()
+    torch.cuda.synchronize()
+    total = ev[0].elapsed_time(ev[2 * steps + 1]) / 1e3
+    acc_t = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(1, steps + 1)) / 1e3
+    out = {"chains": chains, "steps": steps,
+           "proposals_per_s": round(chains * steps / total, 1),
+           "accept_only_proposals_per_s": round(chains * steps / acc_t, 1),
+           "ms_per_step": round(total * 1e3 / steps, 4),
+           "accept_ms_per_step": round(acc_t * 1e3 / steps, 4)}
+    return out, first
 
 
 def roofline(prof, prec, md, B, steps, counters_apply, kernel=None):
@@ -229,6 +315,7 @@ def roofline(prof, prec, md, B, steps, counters_apply, kernel=None):
     return {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[dtype],
             "unit": "TOP/s" if dtype == "i8" else "TFLOP/s", "frac": round(achieved / PEAK[dtype], 4),
             "traffic": TRAFFIC.get((dom, prec)) if counters_apply else None,
+            "traffic_source": TRAFFIC_SOURCE if counters_apply and (dom, prec) in TRAFFIC else None,
             "avg_launch_ms": round(t_launch * 1e3, 4),
             "work_per_launch": ops,
             "fp64_equiv_tflops": round(work_per_launch / t_launch / 1e12, 3) if dom_n else None,
@@ -271,11 +358,9 @@ def main():
                     help="skip the serial-schedule run of the slice-product kernel")
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="oracle items for cpu_baseline, about 10-30 s of CPU work (0: skip)")
-    ap.add_argument("--uneven", action="store_true",
-                    help="also time the uneven packed batch (L = 8, 12, 16, 20), headline "
-                         "precision and FP64, with one oracle-checked item per size class")
-    ap.add_argument("--small", action="store_true",
-                    help="also time the small 4x4, Ltau 40 workload (64 fields, one call)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the legs of the other workloads (4x4, 8x8, 12x12 accept, uneven "
+                         "packed batch, 16x16 error by coupling), e.g. for profiling runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (reference "
                          "for the HBM byte counters) and exit")
@@ -344,8 +429,25 @@ def main():
     sweep = {"12x12x120_64": sweep_rates(slmc, torch, np, 64),
              "12x12x120_2048": sweep_rates(slmc, torch, np, 2048, n_sweeps=1, reps=3)}
 
-    # CPU oracle on a bounded sample of the same fields (log-det + G), and the error of the
-    # GPU path (headline precision) on those items
+    # the other workloads, timed on the GPU; their outputs are checked against the oracle in
+    # the cpu_baseline leg below
+    legs, checks = {}, {}
+    if not args.no_workloads:
+        legs["small_4x4"], checks["small_4x4"] = small_rates(slmc, torch, np)
+        legs["fields_8x8_ltau80"], checks["fields_8x8_ltau80"] = fields_8x8_rates(slmc, torch, np)
+        legs["accept_12x12_ltau120"], checks["accept_12x12_ltau120"] = accept_12x12(slmc, torch, np)
+        legs["uneven_packed"] = {}
+        checks["uneven_packed"] = []
+        for prec in (args.precision, "fp64"):
+            legs["uneven_packed"][prec], ch = uneven_rates(slmc, torch, np, prec)
+            checks["uneven_packed"] += [(prec + ":" + c[0],) + c[1:] for c in ch]
+        checks["errors_16x16_by_lam"] = []
+        for li in (0, 2):
+            checks["errors_16x16_by_lam"] += errors_16x16(slmc, torch, np, args.precision, li)
+
+    # CPU oracle: timed on one BLAS thread on a bounded sample of the 16x16 fields (the
+    # baseline), and run over every output of the GPU legs above in a pool of one-thread
+    # workers, which gives the error of each leg against it
     cpu = None
     err = None
     if args.cpu_sample > 0:
@@ -353,9 +455,9 @@ def main():
         E = oracle.expk(oracle.hopping_matrix(md["Lx"], md["Ly"], md["t"], md["mu"]), md["dtau"])
         ns = min(args.cpu_sample, B)
         xsamp = xs[:ns]
-        ld_g, _, G_g, _ = slmc.green(main_run["m"], torch.tensor(xsamp, device="cuda:0"), main_run["opt"])
+        ld_g, sg_g, G_g, st_g = slmc.green(main_run["m"], torch.tensor(xsamp, device="cuda:0"), main_run["opt"])
         torch.cuda.synchronize()
-        ld_g, G_g = ld_g.cpu().numpy(), G_g.cpu().numpy()
+        ld_g, sg_g, G_g, st_g = ld_g.cpu().numpy(), sg_g.cpu().numpy(), G_g.cpu().numpy(), st_g.cpu().numpy()
 
         def oracle_rate(items):
             t1 = time.perf_counter()
@@ -364,33 +466,37 @@ def main():
 
         what = ("of the %d fields (16x16, Ltau=160, n_s=8, lam=%.1f), log-det + G, numpy/scipy FP64 "
                 "(LAPACK QRP + LU)" % (B, md["lam"]))
-        try:
-            from threadpoolctl import threadpool_info, threadpool_limits
-            threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-            # one thread is the faster setting for these 256 x 256 factorizations (the BLAS
-            # threads cost more than they bring), so it is the baseline; the library's
-            # default thread count is timed beside it on a few fields
-            with threadpool_limits(limits=1):
-                refs, r1 = oracle_rate(range(ns))
-            _, rall = oracle_rate(range(min(6, ns)))
-            cpu = {"value": round(r1, 4), "unit": "evals/s", "cores": 1, "kind": "oracle",
-                   "sample": "%d %s, one BLAS thread" % (ns, what),
-                   "all_threads": {"value": round(rall, 4), "cores": int(threads),
-                                   "sample": "%d of the same fields" % min(6, ns)}}
-        except ImportError:
-            refs, rall = oracle_rate(range(ns))
-            cpu = {"value": round(rall, 4), "unit": "evals/s", "cores": os.cpu_count() or 1,
-                   "kind": "oracle", "sample": "%d %s" % (ns, what)}
+        host = _host_info()
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        # one thread is the faster setting for these 256 x 256 factorizations (the BLAS
+        # threads cost more than they bring), so it is the baseline; the library's default
+        # thread count is timed beside it on a few fields
+        with threadpool_limits(limits=1):
+            refs, r1 = oracle_rate(range(ns))
+        _, rall = oracle_rate(range(min(6, ns)))
+        cpu = {"value": round(r1, 4), "unit": "evals/s", "cores": 1, "kind": "oracle",
+               "sample": "%d %s, one BLAS thread" % (ns, what),
+               "cpu_model": host["cpu_model"], "host_cpus": host["cpus"],
+               "all_threads": {"value": round(rall, 4), "cores": int(threads),
+                               "sample": "%d of the same fields" % min(6, ns)}}
         err = {"max_rel_logdet": float(max(abs(ld_g[k] - refs[k][0]) / abs(refs[k][0]) for k in range(ns))),
+               "max_per_site_logdet": float(max(abs(ld_g[k] - refs[k][0]) for k in range(ns)) / (md["Lx"] * md["Ly"])),
                "max_abs_G": float(max(np.max(np.abs(G_g[k] - refs[k][2])) for k in range(ns))),
-               "items": ns, "precision": args.precision}
-
-    uneven = None
-    if args.uneven:
-        uneven = {args.precision: uneven_rates(slmc, torch, np, args.precision, check=True),
-                  "fp64": uneven_rates(slmc, torch, np, "fp64", check=True)}
-
-    small = small_rates(slmc, torch, np) if args.small else None
+               "signs_equal": bool(all(int(sg_g[k]) == refs[k][1] for k in range(ns))),
+               "status_ok": bool(np.all(st_g == 0)),
+               "items": ns, "precision": args.precision, "lam": md["lam"]}
+        if checks:
+            t1 = time.perf_counter()
+            summary, n_eval, workers = _oracle_checks(checks)
+            cpu["workload_checks"] = {"oracle_evaluations": n_eval, "workers": workers,
+                                      "one_thread_each": True,
+                                      "wall_s": round(time.perf_counter() - t1, 2)}
+            for name, tab in summary.items():
+                legs.setdefault(name, {})["error_vs_oracle"] = tab
+            err["by_lam"] = legs.pop("errors_16x16_by_lam")["error_vs_oracle"]
+            err["by_lam"]["lam=1.5"] = {args.precision: {k: err[k] for k in (
+                "max_rel_logdet", "max_per_site_logdet", "max_abs_G", "items")}}
 
     out = {
         "metric": "fermion logdet+G evals/s at N=256,Ltau=160: mixed vs FP64, <=1e-8 rel err",
@@ -406,11 +512,125 @@ def main():
         "cpu_baseline": cpu, "error_vs_oracle": err,
         "fp64_path": fp64,
         "sweep_only": sweep,
-        "uneven_packed": uneven,
-        "small_4x4": small,
         "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
     }
+    out.update(legs)
     print(json.dumps(out), flush=True)
+
+
+def _host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = os.cpu_count() or 1
+    return {"cpu_model": model, "cpus": cpus}
+
+
+_E_CACHE = {}
+
+
+def _oracle_init():
+    from threadpoolctl import threadpool_limits
+    global _LIMIT
+    _LIMIT = threadpool_limits(limits=1)
+
+
+def _oracle_fermion(task):
+    """One oracle evaluation against one GPU result: (label, rel log-det error, per-site
+    error, max |dG|, sign equal, status ok)."""
+    import numpy as np
+    import oracle
+    label, d, x, ld, st, G, sg = task
+    key = (d["Lx"], d["Ly"], d["t"], d["mu"], d["dtau"])
+    if key not in _E_CACHE:
+        _E_CACHE[key] = oracle.expk(oracle.hopping_matrix(d["Lx"], d["Ly"], d["t"], d["mu"]), d["dtau"])
+    ref, rs, rG = oracle.logdet_green(_E_CACHE[key], x, d["dtau"], d["lam"], d["n_s"])
+    return (label, abs(ld - ref) / abs(ref), abs(ld - ref) / (d["Lx"] * d["Ly"]),
+            float(np.max(np.abs(G - rG))), sg == rs, st == 0, d["lam"])
+
+
+def _oracle_accept(task):
+    """The oracle's sweep and cumulative accept of one chain's first proposal against the
+    GPU's: (max |x'_gpu - x'_oracle|, decision equal, |log r - log r_oracle|, near-tie)."""
+    import numpy as np
+    import oracle
+    from oracle.effective import EffModel
+    from oracle.philox import philox4x32_10, uniform01
+    d, effd, seed, c, x_cur, x_prop, logw, eeff, acc, lr = task
+    key = (d["Lx"], d["Ly"], d["t"], d["mu"], d["dtau"])
+    if key not in _E_CACHE:
+        _E_CACHE[key] = oracle.expk(oracle.hopping_matrix(d["Lx"], d["Ly"], d["t"], d["mu"]), d["dtau"])
+    E = _E_CACHE[key]
+    om = EffModel(**{**effd, "Js": tuple(effd["Js"])})
+    xo = x_cur.copy()
+    margins = []
+    oracle.sweep(xo, d["Lx"], d["Ly"], om, 1, seed, 0, c, margins=margins)
+    ld = oracle.logdet_green(E, x_cur, d["dtau"], d["lam"], d["n_s"])[0]
+    lw0 = oracle.log_weight(ld, x_cur, d["lam"], d["omega0"], d["dtau"], d["c_kin"])
+    e0 = oracle.eff_energy(x_cur, d["Lx"], d["Ly"], om)
+    a, log_r, _, _ = oracle.cumulative_accept(E, d["Lx"], d["Ly"], d["dtau"], d["lam"], d["omega0"],
+                                              d["c_kin"], d["n_s"], om, x_cur, xo, lw0, e0, seed, 0, c)
+    kk = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    u = float(uniform01(philox4x32_10((0xFFFFFFFF, 0xFFFFFFFF, 0, c), kk)[0]))
+    return (float(np.max(np.abs(x_prop - xo))), bool(acc) == a, abs(lr - log_r),
+            int(abs(np.log(u) - log_r) <= 1e-8), int(np.sum(np.abs(margins) <= 1e-12)),
+            abs(logw - lw0) / abs(lw0), bool(a))
+
+
+def _oracle_checks(checks):
+    """Runs the oracle over every GPU output of the workload legs in a pool of one-thread
+    worker processes (as many as the host CPUs this process may use, at most 16)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    workers = max(1, min(16, _host_info()["cpus"]))
+    ferm = [(name, t) for name, lst in checks.items() if name != "accept_12x12_ltau120" for t in lst]
+    acc = checks.get("accept_12x12_ltau120")
+    acc_tasks = []
+    if acc:
+        for c in range(len(acc["accepted"])):
+            acc_tasks.append((acc["md"], acc["eff"], acc["seed"], c, acc["x_cur"][c], acc["x_prop"][c],
+                              float(acc["logw"][c]), float(acc["eeff"][c]), int(acc["accepted"][c]),
+                              float(acc["log_ratio"][c])))
+    # the slowest evaluations first, so the pool drains evenly
+    order = sorted(range(len(ferm)), key=lambda k: -ferm[k][1][2].size * ferm[k][1][1]["Lx"] ** 2)
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                             initializer=_oracle_init) as ex:
+        fa = ex.map(_oracle_accept, acc_tasks, chunksize=1) if acc_tasks else []
+        ff = list(ex.map(_oracle_fermion, [ferm[k][1] for k in order], chunksize=1))
+        fa = list(fa)
+    summary = {}
+    for k, r in zip(order, ff):
+        name = ferm[k][0]
+        label, rel, site, dg, sg_ok, st_ok, lam = r
+        sub = summary.setdefault(name, {})
+        if name == "errors_16x16_by_lam":
+            sub = sub.setdefault("lam=%.1f" % lam, {})
+        t = sub.setdefault(label, {"max_rel_logdet": 0.0, "max_per_site_logdet": 0.0, "max_abs_G": 0.0,
+                                   "items": 0, "signs_equal": True, "status_ok": True})
+        t["max_rel_logdet"] = max(t["max_rel_logdet"], rel)
+        t["max_per_site_logdet"] = max(t["max_per_site_logdet"], site)
+        t["max_abs_G"] = max(t["max_abs_G"], dg)
+        t["items"] += 1
+        t["signs_equal"] &= bool(sg_ok)
+        t["status_ok"] &= bool(st_ok)
+    if fa:
+        a = np.array([[r[0], r[1], r[2], r[3], r[4], r[5], r[6]] for r in fa], dtype=float)
+        summary["accept_12x12_ltau120"] = {
+            "chains": len(fa), "max_abs_dx_after_sweep": float(a[:, 0].max()),
+            "decisions_equal": int(a[:, 1].sum()), "accepted_by_oracle": int(a[:, 6].sum()),
+            "max_abs_dlog_r": float(a[:, 2].max()), "accept_near_ties": int(a[:, 3].sum()),
+            "sweep_near_ties": int(a[:, 4].sum()), "max_rel_logw_current": float(a[:, 5].max())}
+    return summary, len(ferm) + len(acc_tasks), workers
 
 
 if __name__ == "__main__":

@@ -175,7 +175,7 @@ int slmc_eff_energy(const slmc_model* model, const slmc_eff* eff, int32_t n_chai
                     const double* x, double* e_eff, void* stream);
 
 /* n_sweeps checkerboard Metropolis sweeps of every chain, in place (main text "SLMC" and
- * the last paragraph of SM Sec. III: local updates of the effective model).
+ * the last paragraph of SM Sec. IV: local updates of the effective model).
  *   Colouring: spatial colour (ix mod m) + m (iy mod m), m = 2 when Js[2] == 0 (m = 3 if
  *   2 does not divide Lx, Ly), else m = 4 (or 3); temporal colour l mod 2; phase
  *   p = spatial colour + m*m*temporal colour, P = 2 m^2 phases; Ltau must be even.
@@ -204,18 +204,27 @@ size_t slmc_accept_workspace_bytes(const slmc_model* model, int32_t n_chains,
  *   of the current state, replaced on accept); accepted device [n_chains] uint8;
  *   log_ratio device [n_chains] double; G_prop device [n_chains][N][N] or NULL: the
  *   equal-time Green's function of every proposal (for measurements), computed by the
- *   same evaluation that gives its log-det; ws device workspace. */
+ *   same evaluation that gives its log-det; status device [n_chains] int32 or NULL: the
+ *   status of each proposal's log-det evaluation (SLMC_OK, SLMC_E_NONFINITE for a
+ *   non-finite field or result, SLMC_E_DEVICE for a QR wait that hit its spin limit).
+ *   A proposal whose status is not SLMC_OK has log_ratio NaN and is rejected, so the
+ *   chain keeps its state; status tells the caller which chains that happened to.
+ *   ws device workspace. */
 int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff,
                            const slmc_options* opt, int32_t n_chains, double* x_cur,
                            const double* x_prop, double* logw_cur, double* eeff_cur,
                            uint64_t seed, uint64_t proposal_idx, uint8_t* accepted,
-                           double* log_ratio, double* G_prop, void* ws, size_t ws_bytes,
-                           void* stream);
+                           double* log_ratio, double* G_prop, int32_t* status, void* ws,
+                           size_t ws_bytes, void* stream);
 
 /* log w = -dtau S_Bose(x) + 2 logdet for every chain (seeds the cached logw_cur of
- * slmc_cumulative_accept).  Same workspace as slmc_cumulative_accept. */
+ * slmc_cumulative_accept).  status device [n_chains] int32 or NULL, as in
+ * slmc_cumulative_accept (a chain with a non-OK status gets logw NaN, and a NaN cached
+ * weight makes every later proposal of that chain be rejected).  Same workspace as
+ * slmc_cumulative_accept. */
 int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_chains,
-                    const double* x, double* logw, void* ws, size_t ws_bytes, void* stream);
+                    const double* x, double* logw, int32_t* status, void* ws, size_t ws_bytes,
+                    void* stream);
 
 /* Kernel timing with HIP events recorded around each launch on its stream (off by
  * default; costs two events per launch while on).  Classes: 0 seg_chain, 1 wy_apply,

@@ -3,11 +3,11 @@ infrastructure only).
 
 Paper, Eq. (4) (= SM Eq. S7): the effective model is a polynomial in the phonon field
 with a time-kinetic term J_k, two symmetric double-well functions
-    f4(y) = y^4/4 - alpha^2 y^2/2,   f6(y) = y^6/6 - alpha^2 y^4/4   (Fig. 1, SM Sec. II),
+    f4(y) = y^4/4 - alpha^2 y^2/2,   f6(y) = y^6/6 - alpha^2 y^4/4   (Fig. 1, SM Sec. III),
 with y = X - alpha, spatial nearest-neighbour products J_nn and temporal
 nearest-neighbour products J'_nn; it is invariant under the mirror y -> -y.  The
 simulation proposes moves with cheap local updates on this model (main text, "SLMC";
-SM Sec. III, last paragraph).
+SM Sec. IV, last paragraph).
 
 Build frame and readings:
   A1  y = x (axis at 0); the wells sit at +-a with a = lam/omega0^2;
@@ -130,11 +130,12 @@ def colouring(Lx, Ly, Ltau, m):
     return mod, ph, 2 * mod * mod
 
 
-def sweep(x, Lx, Ly, m, n_sweeps, seed, proposal_idx, chain):
-    """n_sweeps checkerboard Metropolis sweeps of one chain, in place (SM Sec. III, last
+def sweep(x, Lx, Ly, m, n_sweeps, seed, proposal_idx, chain, margins=None):
+    """n_sweeps checkerboard Metropolis sweeps of one chain, in place (SM Sec. IV, last
     paragraph: local updates over the space-time lattice).  Sites are visited one at a
     time, phase by phase, in increasing site order inside a phase.  Returns the number of
-    accepted moves."""
+    accepted moves.  If `margins` is a list, the decision margin log u2 + dE of every
+    visited site is appended to it (for counting near-ties; it changes nothing else)."""
     Ltau, N = x.shape
     _, ph, P = colouring(Lx, Ly, Ltau, m)
     key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
@@ -156,6 +157,8 @@ def sweep(x, Lx, Ly, m, n_sweeps, seed, proposal_idx, chain):
                 u2 = float(uniform01(w[1]))
                 xn = x[l, i] + m.delta * (2.0 * u1 - 1.0)
                 de = eff_local_delta(x, Lx, Ly, m, i, l, xn)
+                if margins is not None:
+                    margins.append(float(np.log(u2) + de))
                 if np.log(u2) < -de:
                     x[l, i] = xn
                     acc += 1

@@ -112,6 +112,25 @@ def _dev_f64(t, name):
     return C.c_void_p(t.data_ptr())
 
 
+def _shape(t, shape, name):
+    """The library takes raw pointers and cannot see sizes: every tensor is checked here,
+    before its pointer is passed, so a mis-shaped input is a ValueError and never an
+    out-of-bounds device access."""
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def _fits(t, ends, name):
+    """Every packed item [off, off + size) must lie inside t."""
+    if len(ends) and int(max(ends)) > t.numel():
+        raise ValueError("%s holds %d elements, the packed items need %d"
+                         % (name, t.numel(), int(max(ends))))
+
+
+def _dims(m):
+    return m.Ltau, m.Lx * m.Ly
+
+
 class _BatchArgs:
     """Host-side slmc_batch with the arrays kept alive."""
 
@@ -133,17 +152,30 @@ def _models_arr(models):
     return arr, len(models)
 
 
+# One workspace per (device, stream).  Calls on one stream run in order, so they can share
+# a buffer; calls on different streams get different buffers, each allocated while its
+# stream is current, so that torch's caching allocator keeps a replaced (smaller) buffer
+# away from other streams until the work queued on its own stream has finished with it.
 _ws_cache = {}
 
 
-def _workspace(nbytes, device):
+def _workspace(nbytes, device, stream=None):
     torch = _torch()
-    key = str(device)
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (str(device), int(s.cuda_stream))
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
-        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws_cache.pop(key, None)
+        with torch.cuda.stream(s):
+            buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
         _ws_cache[key] = buf
     return buf
+
+
+def _ws_args(buf):
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("ws must be a contiguous GPU tensor")
+    return C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()
 
 
 def workspace_bytes(models, n_items, opt=None, model_idx=None, x_off=None, g_off=None):
@@ -153,6 +185,36 @@ def workspace_bytes(models, n_items, opt=None, model_idx=None, x_off=None, g_off
     return _abi.lib().slmc_workspace_bytes(arr, nm, C.byref(ba.batch), C.byref(opt))
 
 
+def _check_fermion_shapes(arr, nm, x, n_items, model_idx, x_off, g_off, G):
+    mi = np.zeros(n_items, dtype=np.int64) if model_idx is None else np.asarray(model_idx, dtype=np.int64)
+    if mi.shape != (n_items,) or (n_items and (mi.min() < 0 or mi.max() >= nm)):
+        raise ValueError("model_idx must hold n_items entries in [0, %d)" % nm)
+    xs = np.array([arr[k].Ltau * arr[k].Lx * arr[k].Ly for k in range(nm)], dtype=np.int64)[mi]
+    gs = np.array([(arr[k].Lx * arr[k].Ly) ** 2 for k in range(nm)], dtype=np.int64)[mi]
+    if x_off is None:
+        if nm == 1 and x.dim() == 3:
+            _shape(x, (n_items,) + _dims(arr[0]), "x")
+        else:
+            _fits(x, np.cumsum(xs), "x")
+    else:
+        xo = np.asarray(x_off, dtype=np.int64)
+        if xo.shape != (n_items,) or (n_items and xo.min() < 0):
+            raise ValueError("x_off must hold n_items non-negative offsets")
+        _fits(x, xo + xs, "x")
+    if G is not None:
+        if g_off is None:
+            if nm == 1 and G.dim() == 3:
+                N = arr[0].Lx * arr[0].Ly
+                _shape(G, (n_items, N, N), "G")
+            else:
+                _fits(G, np.cumsum(gs), "G")
+        else:
+            go = np.asarray(g_off, dtype=np.int64)
+            if go.shape != (n_items,) or (n_items and go.min() < 0):
+                raise ValueError("g_off must hold n_items non-negative offsets")
+            _fits(G, go + gs, "G")
+
+
 def _fermion(models, x, opt, model_idx, x_off, g_off, n_items, want_g, G, stream, ws):
     torch = _torch()
     arr, nm = _models_arr(models)
@@ -160,30 +222,30 @@ def _fermion(models, x, opt, model_idx, x_off, g_off, n_items, want_g, G, stream
         if nm != 1 or x.dim() != 3:
             raise ValueError("x must be [items, Ltau, N] for a single model, else pass n_items")
         n_items = x.shape[0]
+    if want_g and G is None and nm != 1:
+        raise ValueError("pass G for several models")
+    _check_fermion_shapes(arr, nm, x, n_items, model_idx, x_off, g_off, G)
     xp = _dev_f64(x, "x")
     opt = opt or options()
     ba = _BatchArgs(n_items, model_idx, x_off, g_off)
     L = _abi.lib()
     need = L.slmc_workspace_bytes(arr, nm, C.byref(ba.batch), C.byref(opt))
-    wsb = ws if ws is not None else _workspace(need, x.device)
+    wsp, wsn = _ws_args(ws if ws is not None else _workspace(need, x.device, stream))
     logdet = torch.empty(n_items, dtype=torch.float64, device=x.device)
     sign = torch.empty(n_items, dtype=torch.int8, device=x.device)
     status = torch.empty(n_items, dtype=torch.int32, device=x.device)
     vp = C.c_void_p
     if want_g:
         if G is None:
-            if nm != 1:
-                raise ValueError("pass G for several models")
             N = arr[0].Lx * arr[0].Ly
             G = torch.empty((n_items, N, N), dtype=torch.float64, device=x.device)
         _abi.check(L.slmc_green(arr, nm, C.byref(ba.batch), C.byref(opt), xp,
                                 vp(logdet.data_ptr()), vp(sign.data_ptr()), _dev_f64(G, "G"),
-                                vp(status.data_ptr()), vp(wsb.data_ptr()), wsb.numel(),
-                                _stream(stream)))
+                                vp(status.data_ptr()), wsp, wsn, _stream(stream)))
         return logdet, sign, G, status
     _abi.check(L.slmc_logdet(arr, nm, C.byref(ba.batch), C.byref(opt), xp,
                              vp(logdet.data_ptr()), vp(sign.data_ptr()), vp(status.data_ptr()),
-                             vp(wsb.data_ptr()), wsb.numel(), _stream(stream)))
+                             wsp, wsn, _stream(stream)))
     return logdet, sign, status
 
 
@@ -199,10 +261,18 @@ def green(models, x, opt=None, model_idx=None, x_off=None, g_off=None, n_items=N
     return _fermion(models, x, opt, model_idx, x_off, g_off, n_items, True, G, stream, ws)
 
 
+def _chains(m, x, name="x"):
+    if x.dim() != 3:
+        raise ValueError("%s must be [chains, Ltau, N]" % name)
+    _shape(x, (x.shape[0],) + _dims(m), name)
+    return x.shape[0]
+
+
 def eff_energy(m, eff, x, stream=None):
     torch = _torch()
-    e = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
-    _abi.check(_abi.lib().slmc_eff_energy(C.byref(m), C.byref(eff), x.shape[0], _dev_f64(x, "x"),
+    n = _chains(m, x)
+    e = torch.empty(n, dtype=torch.float64, device=x.device)
+    _abi.check(_abi.lib().slmc_eff_energy(C.byref(m), C.byref(eff), n, _dev_f64(x, "x"),
                                           C.c_void_p(e.data_ptr()), _stream(stream)))
     return e
 
@@ -211,44 +281,57 @@ def eff_sweep(m, eff, x, n_sweeps, seed, proposal_idx, stream=None):
     """n_sweeps checkerboard Metropolis sweeps of every chain of x [chains, Ltau, N], in
     place; returns the accepted-move count per chain."""
     torch = _torch()
-    nacc = torch.empty(x.shape[0], dtype=torch.int64, device=x.device)
-    _abi.check(_abi.lib().slmc_eff_sweep(C.byref(m), C.byref(eff), x.shape[0], _dev_f64(x, "x"),
+    n = _chains(m, x)
+    nacc = torch.empty(n, dtype=torch.int64, device=x.device)
+    _abi.check(_abi.lib().slmc_eff_sweep(C.byref(m), C.byref(eff), n, _dev_f64(x, "x"),
                                          int(n_sweeps), C.c_uint64(seed), C.c_uint64(proposal_idx),
                                          C.c_void_p(nacc.data_ptr()), _stream(stream)))
     return nacc
 
 
 def log_weight(m, x, opt=None, stream=None, ws=None):
+    """log w = -dtau S_Bose + 2 log|det M| per chain of x [chains, Ltau, N].  Returns
+    (logw, status): status[c] != 0 marks a chain whose log-det failed (logw NaN)."""
     torch = _torch()
+    n = _chains(m, x)
     opt = opt or options()
     L = _abi.lib()
-    need = L.slmc_accept_workspace_bytes(C.byref(m), x.shape[0], C.byref(opt))
-    wsb = ws if ws is not None else _workspace(need, x.device)
-    lw = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
-    _abi.check(L.slmc_log_weight(C.byref(m), C.byref(opt), x.shape[0], _dev_f64(x, "x"),
-                                 C.c_void_p(lw.data_ptr()), C.c_void_p(wsb.data_ptr()), wsb.numel(),
+    need = L.slmc_accept_workspace_bytes(C.byref(m), n, C.byref(opt))
+    wsp, wsn = _ws_args(ws if ws is not None else _workspace(need, x.device, stream))
+    lw = torch.empty(n, dtype=torch.float64, device=x.device)
+    st = torch.empty(n, dtype=torch.int32, device=x.device)
+    _abi.check(L.slmc_log_weight(C.byref(m), C.byref(opt), n, _dev_f64(x, "x"),
+                                 C.c_void_p(lw.data_ptr()), C.c_void_p(st.data_ptr()), wsp, wsn,
                                  _stream(stream)))
-    return lw
+    return lw, st
 
 
 def cumulative_accept(m, eff, x_cur, x_prop, logw_cur, eeff_cur, seed, proposal_idx, opt=None,
                       stream=None, ws=None, G_prop=None):
     """Eq. 6 for one proposal per chain; x_cur, logw_cur, eeff_cur are updated in place on
     accept.  G_prop (optional, [chains, N, N]) receives the proposals' Green's functions.
-    Returns (accepted uint8, log_ratio float64)."""
+    Returns (accepted uint8, log_ratio float64, status int32): a proposal whose log-det
+    failed (status != 0) has log_ratio NaN and is rejected."""
     torch = _torch()
     opt = opt or options()
     L = _abi.lib()
-    n = x_cur.shape[0]
+    n = _chains(m, x_cur, "x_cur")
+    _shape(x_prop, tuple(x_cur.shape), "x_prop")
+    _shape(logw_cur, (n,), "logw_cur")
+    _shape(eeff_cur, (n,), "eeff_cur")
+    if G_prop is not None:
+        N = m.Lx * m.Ly
+        _shape(G_prop, (n, N, N), "G_prop")
     need = L.slmc_accept_workspace_bytes(C.byref(m), n, C.byref(opt))
-    wsb = ws if ws is not None else _workspace(need, x_cur.device)
+    wsp, wsn = _ws_args(ws if ws is not None else _workspace(need, x_cur.device, stream))
     acc = torch.empty(n, dtype=torch.uint8, device=x_cur.device)
     lr = torch.empty(n, dtype=torch.float64, device=x_cur.device)
+    st = torch.empty(n, dtype=torch.int32, device=x_cur.device)
     vp = C.c_void_p
     _abi.check(L.slmc_cumulative_accept(
         C.byref(m), C.byref(eff), C.byref(opt), n, _dev_f64(x_cur, "x_cur"),
         _dev_f64(x_prop, "x_prop"), _dev_f64(logw_cur, "logw_cur"), _dev_f64(eeff_cur, "eeff_cur"),
         C.c_uint64(seed), C.c_uint64(proposal_idx), vp(acc.data_ptr()), vp(lr.data_ptr()),
-        None if G_prop is None else _dev_f64(G_prop, "G_prop"), vp(wsb.data_ptr()), wsb.numel(),
+        None if G_prop is None else _dev_f64(G_prop, "G_prop"), vp(st.data_ptr()), wsp, wsn,
         _stream(stream)))
-    return acc, lr
+    return acc, lr, st

@@ -65,13 +65,13 @@ def lib():
     L.slmc_accept_workspace_bytes.restype = sz
     L.slmc_accept_workspace_bytes.argtypes = [P(Model), i32, P(Options)]
     L.slmc_cumulative_accept.argtypes = [P(Model), P(Eff), P(Options), i32, vp, vp, vp, vp, u64,
-                                         u64, vp, vp, vp, vp, sz, vp]
+                                         u64, vp, vp, vp, vp, vp, sz, vp]
     L.slmc_profile.argtypes = [C.c_int]
     L.slmc_profile_read.argtypes = [i32, P(C.c_double), P(C.c_int64)]
     L.slmc_profile_reset.restype = None
     L.slmc_profile_name.restype = C.c_char_p
     L.slmc_profile_name.argtypes = [i32]
-    L.slmc_log_weight.argtypes = [P(Model), P(Options), i32, vp, vp, vp, sz, vp]
+    L.slmc_log_weight.argtypes = [P(Model), P(Options), i32, vp, vp, vp, vp, sz, vp]
     L.slmc_cache_clear.restype = None
     _lib = L
     return L

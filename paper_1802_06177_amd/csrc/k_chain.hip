@@ -208,7 +208,29 @@ hipError_t pick_f64(int CB, const double* E, FieldRef f, int nb, int N, int Np, 
   return run_f64<RB, 1>(E, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, st);
 }
 
+// status[b] = 1 if any entry of item b's field is not finite, else 0 (one workgroup per
+// item).  Every precision then reports such an item as non-finite, whatever its kernels
+// make of the value (the int8 split, for one, cuts a NaN into finite digits).
+__global__ __launch_bounds__(256) void field_status_k(FieldRef f, int nelem, int* __restrict__ status) {
+  __shared__ int bad;
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const double* xb = field_of(f, b);
+  int mine = 0;
+  for (int e = threadIdx.x; e < nelem; e += blockDim.x) mine |= !isfinite(xb[e]);
+  if (mine) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) status[b] = bad;
+}
+
 }  // namespace
+
+hipError_t launch_field_status(FieldRef f, int nb, int nelem, int* status, hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(field_status_k, dim3(nb), dim3(256), 0, st, f, nelem, status);
+  return hipGetLastError();
+}
 
 hipError_t launch_seg_bf16(int pieces, const double* E64, const uint16_t* Ebf, FieldRef f,
                            int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl,

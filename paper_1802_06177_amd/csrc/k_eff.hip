@@ -1,6 +1,6 @@
 // Symmetric effective boson model (Eq. 4 / S7 in the shifted frame, weight e^{-E_eff}),
 // its checkerboard Metropolis sweeps (local updates of the cumulative proposal, main text
-// "SLMC" and SM Sec. III), the full log-weight -dtau S_Bose + 2 log|det M| (SM Eq. S2)
+// "SLMC" and the last paragraph of SM Sec. IV), the full log-weight -dtau S_Bose + 2 log|det M| (SM Eq. S2)
 // and the cumulative-update acceptance (Eq. 6).
 //
 // Sweep design: one workgroup per chain holds the chain's whole field in LDS when it fits

@@ -1147,27 +1147,12 @@ __global__ void fill_i32_k(int* dst, int n, int value) {
   if (i < n) dst[i] = value;
 }
 
-__global__ void gate_delay_k(long long ticks) {
-  const long long t0 = wall_clock64();
-  for (int i = 0; i < 4096; ++i) {
-    if (wall_clock64() - t0 >= ticks) break;
-    __builtin_amdgcn_s_sleep(2);
-  }
-}
+__global__ void order_gate_k() {}
 
 }  // namespace
 
-hipError_t launch_gate_delay(int us, hipStream_t st) {
-  static int khz[64] = {0};
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  if (khz[dev] <= 0) {
-    e = hipDeviceGetAttribute(&khz[dev], hipDeviceAttributeWallClockRate, dev);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(gate_delay_k, dim3(1), dim3(64), 0, st, (long long)us * khz[dev] / 1000);
+hipError_t launch_order_gate(hipStream_t st) {
+  hipLaunchKernelGGL(order_gate_k, dim3(1), dim3(64), 0, st);
   return hipGetLastError();
 }
 

@@ -55,9 +55,13 @@ hipError_t launch_qr(const double* A, int64_t astride, const double* norm2, int6
 
 // dst[0..n) = value (a plain kernel, safe inside captured graphs)
 hipError_t launch_fill_i32(int* dst, int n, int value, hipStream_t st);
-// One wave that waits about `us` microseconds of the constant-rate wall clock (at most
-// 4096 short polls, so it always ends)
-hipError_t launch_gate_delay(int us, hipStream_t st);
+// status[b] = 1 if item b's field (nelem = Ltau N values) holds a non-finite value, else 0
+// (a plain kernel, safe inside captured graphs)
+hipError_t launch_field_status(FieldRef f, int nb, int nelem, int* status, hipStream_t st);
+// One empty wave.  Enqueued on a side stream in front of work released at the same moment
+// as a launch on another stream, its dispatch lets the other launch's workgroups reach the
+// compute units first.
+hipError_t launch_order_gate(hipStream_t st);
 
 // Vn[b] = F[b] Vo[b][perm[b], :] with F = S_r R S_c the V-update factor of launch_qr, from R
 // in the upper triangle of QRW[b] and scales[b] (Vo == nullptr: identity).

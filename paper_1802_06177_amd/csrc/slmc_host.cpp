@@ -380,7 +380,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     if (G && !g_aff) { g_out = G; goff = w.goff; }
   }
 
-  HIPCHK(launch_fill_i32(w.status, nb, 0, st));
+  HIPCHK(launch_field_status(f, nb, m->Ltau * N, w.status, st));
   // a2: segment products (a1 fused: the phonon factors scale the panel rows).  With more
   // than one block they go to the side stream, one launch per block, and step k of the
   // chain below waits only for block k: the chain (one workgroup per item, latency-bound)
@@ -429,14 +429,15 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   // Gated: the side work, segment block k + 2 (blocks 1 and 2 at k = 0) on s and V update
   // k - 1 on s2, is released when wy_apply k is done, so it runs on the CUs that QR k
   // leaves free rather than beside wy_apply; a segment block is ready a whole step before
-  // the chain needs it.  A short gate kernel on s goes first: released at the same moment
+  // the chain needs it.  An empty gate kernel on s goes first: released at the same moment
   // as the QR, the side work's workgroups would take CUs that the QR's (a whole CU each)
-  // are waiting for.  Eager: all segment products are queued on s up front, and V update
-  // k follows QR k on s2.  Events: ev[k] segment k done (s), ev[mseg+1+k] QR k done (st),
+  // are waiting for, and the gate's dispatch lets the QR's go first.  Eager: all segment
+  // products are queued on s up front, and V update k follows QR k on s2.
+  // Events: ev[k] segment k done (s), ev[mseg+1+k] QR k done (st),
   // ev[2 mseg+1+k] V update k done (s2), ev[3 mseg+1+k] wy_apply k done (st),
   // ev[4 mseg+1+k] gate k passed (s).  QR k reuses the buffers that V update k - kQB
   // reads, so step k waits for it (with the wait for segment k, before wy_apply k).
-  constexpr int kGateUs = 2, kSegAhead = 2, kQB = GroupBufs::kQB;
+  constexpr int kSegAhead = 2, kQB = GroupBufs::kQB;
   hipEvent_t* ev_qr = overlap ? &ss->ev[mseg + 1] : nullptr;
   hipEvent_t* ev_vu = overlap ? &ss->ev[2 * mseg + 1] : nullptr;
   hipEvent_t* ev_ph = overlap ? &ss->ev[3 * mseg + 1] : nullptr;
@@ -479,7 +480,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     if (gated) {
       HIPCHK(hipEventRecord(ev_ph[k], st));
       HIPCHK(hipStreamWaitEvent(ss->s, ev_ph[k], 0));
-      HIPCHK(launch_gate_delay(kGateUs, ss->s));
+      HIPCHK(launch_order_gate(ss->s));
       HIPCHK(hipEventRecord(ev_gt[k], ss->s));
       for (int j = (k == 0 ? 1 : k + kSegAhead); j <= k + kSegAhead && j < mseg; ++j) {
         ProfScope ps(0, ss->s);
@@ -683,7 +684,8 @@ size_t slmc_accept_workspace_bytes(const slmc_model* model, int32_t n_chains,
 }
 
 int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_chains,
-                    const double* x, double* logw, void* ws, size_t ws_bytes, void* stream) {
+                    const double* x, double* logw, int32_t* status, void* ws, size_t ws_bytes,
+                    void* stream) {
   g_err.clear();
   int rc = check_model(model);
   if (rc) return rc;
@@ -699,7 +701,8 @@ int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_
   carve(a, n_chains, Np, (model->Ltau + model->n_s - 1) / model->n_s, w);
   double* ld = a.take<double>(n_chains);
   int8_t* sg = (int8_t*)a.take<int>(n_chains);
-  int32_t* stt = a.take<int32_t>(n_chains);
+  int32_t* stt_ws = a.take<int32_t>(n_chains);
+  int32_t* stt = status ? status : stt_ws;
   Group grp{0, {}};
   for (int c = 0; c < n_chains; ++c) grp.items.push_back(c);
   slmc_batch bt{n_chains, nullptr, nullptr, nullptr};
@@ -714,8 +717,8 @@ int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_
 int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff, const slmc_options* opt,
                            int32_t n_chains, double* x_cur, const double* x_prop, double* logw_cur,
                            double* eeff_cur, uint64_t seed, uint64_t proposal_idx,
-                           uint8_t* accepted, double* log_ratio, double* G_prop, void* ws,
-                           size_t ws_bytes, void* stream) {
+                           uint8_t* accepted, double* log_ratio, double* G_prop,
+                           int32_t* status, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
   int rc = check_model(model);
   if (rc) return rc;
@@ -737,7 +740,8 @@ int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff, const s
   a.take<double>(n_chains);
   a.take<double>(n_chains);
   int8_t* sg = (int8_t*)a.take<int>(n_chains);
-  int32_t* stt = a.take<int32_t>(n_chains);
+  int32_t* stt_ws = a.take<int32_t>(n_chains);
+  int32_t* stt = status ? status : stt_ws;
   Group grp{0, {}};
   for (int c = 0; c < n_chains; ++c) grp.items.push_back(c);
   slmc_batch bt{n_chains, nullptr, nullptr, nullptr};

@@ -91,10 +91,14 @@ def test_sweep_and_accept_validation():
     need = L.slmc_accept_workspace_bytes(C.byref(ok), 4, C.byref(opt))
     assert need > 0
     rc = L.slmc_cumulative_accept(C.byref(ok), C.byref(eff), C.byref(opt), 4, vp, vp, vp, vp, 1, 0,
-                                  vp, vp, None, vp, need - 1, None)
+                                  vp, vp, None, None, vp, need - 1, None)
     assert rc == _abi.SLMC_E_WORKSPACE
     rc = L.slmc_cumulative_accept(C.byref(ok), C.byref(eff), C.byref(opt), 0, vp, vp, vp, vp, 1, 0,
-                                  vp, vp, None, vp, need, None)
+                                  vp, vp, None, None, vp, need, None)
+    assert rc == _abi.SLMC_E_ARG
+    rc = L.slmc_log_weight(C.byref(ok), C.byref(opt), 4, vp, vp, None, vp, need - 1, None)
+    assert rc == _abi.SLMC_E_WORKSPACE
+    rc = L.slmc_log_weight(C.byref(ok), C.byref(opt), 4, None, vp, None, vp, need, None)
     assert rc == _abi.SLMC_E_ARG
 
 
@@ -124,3 +128,46 @@ def test_binding_refuses_cpu_tensors():
     x = torch.zeros((2, 40, 16), dtype=torch.float64)
     with pytest.raises(TypeError):
         slmc.logdet(slmc.model(4, 4, 40, 10), x)
+
+
+def test_binding_rejects_mis_shaped_tensors_before_any_call():
+    # the C ABI takes raw pointers; the binding checks every size first (on CPU tensors the
+    # shape check fires before the device check)
+    import torch
+    m = slmc.model(4, 4, 40, 10)
+    f64 = dict(dtype=torch.float64)
+    with pytest.raises(ValueError):
+        slmc.logdet(m, torch.zeros((2, 40, 15), **f64))
+    with pytest.raises(ValueError):
+        slmc.green(m, torch.zeros((2, 40, 16), **f64), G=torch.zeros((2, 16, 15), **f64))
+    with pytest.raises(ValueError):     # packed item past the end of x
+        slmc.logdet(m, torch.zeros(2 * 640 - 1, **f64), x_off=[0, 640], n_items=2)
+    with pytest.raises(ValueError):     # n_items larger than x holds
+        slmc.logdet(m, torch.zeros(640, **f64), n_items=2)
+    m2 = slmc.model(6, 6, 30, 10)
+    with pytest.raises(ValueError):     # model index out of range
+        slmc.green([m, m2], torch.zeros(2000, **f64), model_idx=[0, 2], x_off=[0, 640],
+                   g_off=[0, 256], n_items=2, G=torch.zeros(2000, **f64))
+    with pytest.raises(ValueError):     # G too small for the packed items
+        slmc.green([m, m2], torch.zeros(1720, **f64), model_idx=[0, 1], x_off=[0, 640],
+                   g_off=[0, 256], n_items=2, G=torch.zeros(1551, **f64))
+    with pytest.raises(ValueError):
+        slmc.eff_sweep(m, slmc.eff_model(), torch.zeros((2, 39, 16), **f64), 1, 1, 0)
+    with pytest.raises(ValueError):
+        slmc.eff_energy(m, slmc.eff_model(), torch.zeros((2, 40), **f64))
+    with pytest.raises(ValueError):
+        slmc.log_weight(m, torch.zeros((2, 16, 40), **f64))
+    x = torch.zeros((3, 40, 16), **f64)
+    with pytest.raises(ValueError):
+        slmc.cumulative_accept(m, slmc.eff_model(), x, torch.zeros((2, 40, 16), **f64),
+                               torch.zeros(3, **f64), torch.zeros(3, **f64), 1, 0)
+    with pytest.raises(ValueError):
+        slmc.cumulative_accept(m, slmc.eff_model(), x, x.clone(), torch.zeros(2, **f64),
+                               torch.zeros(3, **f64), 1, 0)
+    with pytest.raises(ValueError):
+        slmc.cumulative_accept(m, slmc.eff_model(), x, x.clone(), torch.zeros(3, **f64),
+                               torch.zeros(3, **f64), 1, 0, G_prop=torch.zeros((3, 16, 17), **f64))
+    # well-shaped CPU tensors get past the shape checks and are refused as CPU tensors
+    with pytest.raises(TypeError):
+        slmc.green([m, m2], torch.zeros(1720, **f64), model_idx=[0, 1], x_off=[0, 640],
+                   g_off=[0, 256], n_items=2, G=torch.zeros(1552, **f64))

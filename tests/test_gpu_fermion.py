@@ -2,9 +2,10 @@
 against the FP64 CPU oracle on the same seeded inputs.
 
 Bars (max over items): FP64 path: relative log-det error <= 1e-11, max|dG| <= 1e-9, sign
-exact.  Mixed paths: relative log-det error <= 1e-8 for the FP32 path with FP64
-promotion every k-step; the other variants are measured against their own looser bars
-(printed with the test output)."""
+exact.  Mixed paths: relative log-det error <= 1e-8 (the target of the mixed-precision
+form), max|dG| <= 1e-7.  The int8-slice path meets it; the FP32 and bf16 split forms are
+asserted against the same 1e-8 bar under a strict xfail (their FP32 matrix-core
+accumulation leaves an error floor above it), with the measured error printed."""
 
 import numpy as np
 import pytest
@@ -294,19 +295,27 @@ def test_logdet_only_equals_green_logdet():
 
 
 # ------------------------------------------------------------------------- mixed paths
-# Bars are set from the measured behaviour of each variant (about 3x the worst error seen
-# on these items).  Only the FP64 path meets the 1e-8 relative log-det target: the FP32
-# matrix cores truncate while accumulating, which leaves a coherent ~3-5e-8 floor even
-# with per-k-step FP64 promotion and the compensation of E's rounding.
+# Every precision form is held to the same 1e-8 relative log-det bar.  The FP32 matrix
+# cores round while they accumulate, which leaves a coherent error of a few 1e-8 (FP32 with
+# FP64 promotion every k-step) up to 1e-5 (bf16x3) even with the compensation of E's
+# rounding; those forms fail the bar and are marked as expected failures (strict: a pass
+# would flag that the floor moved).  The worst error is printed before the assertion.
 
-@pytest.mark.parametrize("prec,chunk,rel_bar,g_bar", [
-    ("fp32", 1, 1.5e-7, 1e-6), ("fp32", 4, 2e-7, 1e-6), ("fp32", 0, 8e-7, 3e-6),
-    ("fp32plain", 1, 3e-7, 1e-6), ("bf16x6", 0, 1.5e-6, 3e-6), ("bf16x3", 0, 1e-4, 2e-4),
-    ("int8x5", 0, 1e-9, 1e-8)])
-def test_mixed_variants_error_bars_8x8(prec, chunk, rel_bar, g_bar):
+_FP32_FLOOR = "FP32 matrix-core accumulation floor: measured error above the 1e-8 target"
+
+
+@pytest.mark.parametrize("prec,chunk", [
+    pytest.param("fp32", 1, marks=pytest.mark.xfail(strict=True, raises=AssertionError, reason=_FP32_FLOOR)),
+    pytest.param("fp32", 4, marks=pytest.mark.xfail(strict=True, raises=AssertionError, reason=_FP32_FLOOR)),
+    pytest.param("fp32", 0, marks=pytest.mark.xfail(strict=True, raises=AssertionError, reason=_FP32_FLOOR)),
+    pytest.param("fp32plain", 1, marks=pytest.mark.xfail(strict=True, raises=AssertionError, reason=_FP32_FLOOR)),
+    pytest.param("bf16x6", 0, marks=pytest.mark.xfail(strict=True, raises=AssertionError, reason=_FP32_FLOOR)),
+    pytest.param("bf16x3", 0, marks=pytest.mark.xfail(strict=True, raises=AssertionError, reason=_FP32_FLOOR)),
+    ("int8x5", 0)])
+def test_mixed_variants_meet_1e8_8x8(prec, chunk):
     md = workload_models("W2")[0]
     xs = [workload_item("W2", b)[1] for b in range(0, 256, 64)]
-    _check(md, xs, _run(md, xs, prec=prec, chunk=chunk), rel_bar, g_bar)
+    _check(md, xs, _run(md, xs, prec=prec, chunk=chunk), 1e-8, 1e-7)
 
 
 def test_fp32_compensation_of_E_reduces_error():
@@ -321,10 +330,13 @@ def test_fp32_compensation_of_E_reduces_error():
     assert ec < 0.6 * ep
 
 
-def test_fp32_full_size_16x16():
+@pytest.mark.parametrize("prec", [
+    pytest.param("fp32", marks=pytest.mark.xfail(strict=True, raises=AssertionError, reason=_FP32_FLOOR)),
+    pytest.param("bf16x3", marks=pytest.mark.xfail(strict=True, raises=AssertionError, reason=_FP32_FLOOR))])
+def test_split_forms_full_size_16x16_meet_1e8(prec):
     md = workload_models("W4", 1)[0]
     xs = [workload_item("W4", b, 1)[1] for b in (3,)]
-    _check(md, xs, _run(md, xs, prec="fp32", chunk=1, resid=1), 2e-7, 1e-6)
+    _check(md, xs, _run(md, xs, prec=prec, chunk=1 if prec == "fp32" else 0, resid=1), 1e-8, 1e-7)
 
 
 # ------------------------------------------------------------------------- int8 slices
@@ -379,6 +391,31 @@ def test_int8x5_lds_base_rows_equal_streamed_bitwise(Lx, Ly, Ltau, n_s):
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
     _check(md, xs[:1], [o[:1] for o in outs[0]], 1e-9, 1e-8)
+
+
+def test_int8x5_negative_determinants_keep_their_sign():
+    md = _md(2, 40, 5, 3.0)
+    g = gen(98, 1)
+    xs = [g.normal(0.0, 3.0, size=(40, 4)) for _ in range(40)]
+    out = _run(md, xs, prec="int8x5", resid=1)
+    refs = [_ref(md, x)[1] for x in xs]
+    assert min(refs) < 0 < max(refs)
+    _check(md, xs, out, 1e-8, 1e-7)
+
+
+def test_int8x5_nonfinite_input_flags_only_that_item():
+    md = _md(8, 24, 6)
+    g = gen(96, 2)
+    xs = [g.normal(size=(24, 64)) for _ in range(3)]
+    xs[1] = xs[1].copy()
+    xs[1][7, 9] = np.inf
+    ld, sg, G, st = _run(md, xs, prec="int8x5", resid=1)
+    assert st[1] == 5 and np.isnan(ld[1])
+    assert st[0] == 0 and st[2] == 0
+    for k in (0, 2):
+        ref = _ref(md, xs[k])
+        assert abs(ld[k] - ref[0]) <= 1e-8 * abs(ref[0])
+        assert np.max(np.abs(G[k] - ref[2])) <= 1e-7
 
 
 def test_int8x5_staggered_closed_form_16x16():

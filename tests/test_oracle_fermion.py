@@ -4,6 +4,8 @@ brute force and exact symmetries.  CPU only."""
 import numpy as np
 import pytest
 
+import scipy.linalg as sla
+
 import oracle as o
 import pins
 
@@ -219,3 +221,34 @@ def test_P9_ratio_catches_transposed_green():
     x = _field(10, 20, 16)
     ld, _, G = o.logdet_green(_E(4, 4), x, 0.1, 1.5, 5)
     assert np.max(np.abs(G - G.T)) > 1e-3     # G is not symmetric for a random field
+
+
+# ------------------------------------------------------------------ A4 factor order
+
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s,lam,seed", [(4, 4, 20, 5, 1.5, 41), (2, 3, 12, 4, 2.5, 42),
+                                                      (6, 4, 16, 8, 1.0, 43)])
+def test_A4_paper_factor_order_same_logdet_similar_green(Lx, Ly, Ltau, n_s, lam, seed):
+    # SM Eq. S2 writes B_l = e^{-dtau g X(l)} e^{-dtau K} (phonon factor first); the oracle
+    # uses B_l = e^{-dtau K} diag(v_l).  Then B_L..B_1 (oracle) = E [paper product] E^{-1},
+    # so I + B_L..B_1 is similar to the paper's M: same determinant (value and sign) and
+    # G_oracle = E G_paper E^{-1}.  The paper-order product is formed here directly from its
+    # definition (no stabilization: these fields keep it well conditioned) with the
+    # exponentials of the Fock-space test's matrix exponential, not the oracle's eigh.
+    dtau = 0.1
+    K = o.hopping_matrix(Lx, Ly, 1.0, 0.2)
+    E = sla.expm(-dtau * K)
+    Einv = sla.expm(dtau * K)
+    x = _field(seed, Ltau, Lx * Ly)
+    N = Lx * Ly
+    P = np.eye(N)
+    for l in range(Ltau):
+        P = (np.exp(-dtau * lam * x[l])[:, None] * E) @ P   # B_l = diag(v_l) e^{-dtau K}
+    Mp = np.eye(N) + P
+    sp, ldp = np.linalg.slogdet(Mp)
+    Gp = np.linalg.inv(Mp)
+    ld, s, G = o.logdet_green(o.expk(K, dtau), x, dtau, lam, n_s)
+    assert abs(ld - ldp) <= T3 * abs(ldp)
+    assert s == int(sp)
+    assert np.max(np.abs(G - E @ Gp @ Einv)) <= T3
+    # and the paper-order G itself is not the oracle's (the two orders differ)
+    assert np.max(np.abs(G - Gp)) > 1e-6
