@@ -371,6 +371,13 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # the oracle's worker pool starts before anything touches the GPU (its processes are
+    # spawned, not forked from a process holding the device), and warms up meanwhile
+    pool = None
+    if args.cpu_sample > 0 and not args.no_workloads and args.copy_calibration <= 0:
+        pool = _start_pool()
+        _progress("oracle pool of %d workers started" % pool[1])
+
     import numpy as np
     import torch
 
@@ -395,6 +402,7 @@ def main():
     xs = np.stack([workload_item("W4", b % 128, lam_idx)[1] for b in range(B)])
 
     main_run = run(slmc, torch, md, eff, xs, B, args.precision, args)
+    _progress("headline run done: %.1f evals/s" % (B * args.steps / (main_run["ms"] / 1e3)))
     ms_per_step = main_run["ms"] / args.steps
     value = B * args.steps / (main_run["ms"] / 1e3)
     roof = roofline(main_run["prof"], args.precision, md, B, args.steps,
@@ -414,6 +422,7 @@ def main():
             r_al = run(slmc, torch, md, eff, xs, B, args.precision, args_alone)
             r_alone = roofline(r_al["prof"], args.precision, md, B, args.steps, False, "seg_chain")
             seg_rate["schedule_serial"] = {k: r_alone[k] for k in keep}
+            _progress("serial-schedule run done")
 
     fp64 = None
     if args.precision != "fp64" and not args.no_fp64:
@@ -423,27 +432,34 @@ def main():
                 "ms_per_step": round(r64["ms"] / args.steps, 4),
                 "mixed_over_fp64": round(r64["ms"] / main_run["ms"], 4),
                 "path_roofline": path_roofline("fp64", md, v64)}
+        _progress("FP64 run done: %.1f evals/s" % v64)
 
     # the effective-model sweep alone on the 12x12 shape: 64 chains (L2-resident) and 2048
     # chains (a working set above the 256 MB last-level cache)
     sweep = {"12x12x120_64": sweep_rates(slmc, torch, np, 64),
              "12x12x120_2048": sweep_rates(slmc, torch, np, 2048, n_sweeps=1, reps=3)}
+    _progress("sweep legs done")
 
     # the other workloads, timed on the GPU; their outputs are checked against the oracle in
     # the cpu_baseline leg below
     legs, checks = {}, {}
     if not args.no_workloads:
         legs["small_4x4"], checks["small_4x4"] = small_rates(slmc, torch, np)
+        _progress("4x4 leg done")
         legs["fields_8x8_ltau80"], checks["fields_8x8_ltau80"] = fields_8x8_rates(slmc, torch, np)
+        _progress("8x8 leg done")
         legs["accept_12x12_ltau120"], checks["accept_12x12_ltau120"] = accept_12x12(slmc, torch, np)
+        _progress("12x12 accept leg done")
         legs["uneven_packed"] = {}
         checks["uneven_packed"] = []
         for prec in (args.precision, "fp64"):
             legs["uneven_packed"][prec], ch = uneven_rates(slmc, torch, np, prec)
             checks["uneven_packed"] += [(prec + ":" + c[0],) + c[1:] for c in ch]
+            _progress("uneven leg (%s) done" % prec)
         checks["errors_16x16_by_lam"] = []
         for li in (0, 2):
             checks["errors_16x16_by_lam"] += errors_16x16(slmc, torch, np, args.precision, li)
+        _progress("16x16 error leg done")
 
     # CPU oracle: timed on one BLAS thread on a bounded sample of the 16x16 fields (the
     # baseline), and run over every output of the GPU legs above in a pool of one-thread
@@ -474,6 +490,7 @@ def main():
         # thread count is timed beside it on a few fields
         with threadpool_limits(limits=1):
             refs, r1 = oracle_rate(range(ns))
+        _progress("oracle baseline (one thread, %d fields) done" % ns)
         _, rall = oracle_rate(range(min(6, ns)))
         cpu = {"value": round(r1, 4), "unit": "evals/s", "cores": 1, "kind": "oracle",
                "sample": "%d %s, one BLAS thread" % (ns, what),
@@ -488,7 +505,7 @@ def main():
                "items": ns, "precision": args.precision, "lam": md["lam"]}
         if checks:
             t1 = time.perf_counter()
-            summary, n_eval, workers = _oracle_checks(checks)
+            summary, n_eval, workers = _oracle_checks(pool, checks)
             cpu["workload_checks"] = {"oracle_evaluations": n_eval, "workers": workers,
                                       "one_thread_each": True,
                                       "wall_s": round(time.perf_counter() - t1, 2)}
@@ -515,7 +532,34 @@ def main():
         "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
     }
     out.update(legs)
+    if pool is not None:
+        pool[0].shutdown(wait=True)
     print(json.dumps(out), flush=True)
+
+
+def _progress(msg):
+    print("[bench %.1f s] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
+def _warm():
+    import oracle  # noqa: F401
+    return os.getpid()
+
+
+def _start_pool():
+    """A pool of one-thread oracle workers (as many as the host CPUs this process may use,
+    at most 16), spawned and warmed up now."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, _host_info()["cpus"]))
+    ex = ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                             initializer=_oracle_init)
+    for f in [ex.submit(_warm) for _ in range(workers)]:
+        f.result(timeout=300)
+    return ex, workers
 
 
 def _host_info():
@@ -586,13 +630,11 @@ def _oracle_accept(task):
             abs(logw - lw0) / abs(lw0), bool(a))
 
 
-def _oracle_checks(checks):
-    """Runs the oracle over every GPU output of the workload legs in a pool of one-thread
-    worker processes (as many as the host CPUs this process may use, at most 16)."""
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
+def _oracle_checks(pool, checks):
+    """Runs the oracle over every GPU output of the workload legs in the pool of one-thread
+    worker processes."""
     import numpy as np
-    workers = max(1, min(16, _host_info()["cpus"]))
+    ex, workers = pool
     ferm = [(name, t) for name, lst in checks.items() if name != "accept_12x12_ltau120" for t in lst]
     acc = checks.get("accept_12x12_ltau120")
     acc_tasks = []
@@ -603,11 +645,14 @@ def _oracle_checks(checks):
                               float(acc["log_ratio"][c])))
     # the slowest evaluations first, so the pool drains evenly
     order = sorted(range(len(ferm)), key=lambda k: -ferm[k][1][2].size * ferm[k][1][1]["Lx"] ** 2)
-    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
-                             initializer=_oracle_init) as ex:
-        fa = ex.map(_oracle_accept, acc_tasks, chunksize=1) if acc_tasks else []
-        ff = list(ex.map(_oracle_fermion, [ferm[k][1] for k in order], chunksize=1))
-        fa = list(fa)
+    fa = [ex.submit(_oracle_accept, t) for t in acc_tasks]
+    ffut = [ex.submit(_oracle_fermion, ferm[k][1]) for k in order]
+    ff = []
+    for j, f in enumerate(ffut):
+        ff.append(f.result(timeout=600))
+        if (j + 1) % 200 == 0:
+            _progress("oracle checks: %d of %d evaluations" % (j + 1, len(ffut)))
+    fa = [f.result(timeout=600) for f in fa]
     summary = {}
     for k, r in zip(order, ff):
         name = ferm[k][0]
