@@ -358,6 +358,9 @@ def main():
                     help="skip the serial-schedule run of the slice-product kernel")
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="oracle items for cpu_baseline, about 10-30 s of CPU work (0: skip)")
+    ap.add_argument("--cpu-all-threads", action="store_true",
+                    help="also time the oracle with the BLAS library's default thread count "
+                         "(slower than one thread at these sizes)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the legs of the other workloads (4x4, 8x8, 12x12 accept, uneven "
                          "packed batch, 16x16 error by coupling), e.g. for profiling runs")
@@ -491,12 +494,15 @@ def main():
         with threadpool_limits(limits=1):
             refs, r1 = oracle_rate(range(ns))
         _progress("oracle baseline (one thread, %d fields) done" % ns)
-        _, rall = oracle_rate(range(min(6, ns)))
         cpu = {"value": round(r1, 4), "unit": "evals/s", "cores": 1, "kind": "oracle",
                "sample": "%d %s, one BLAS thread" % (ns, what),
                "cpu_model": host["cpu_model"], "host_cpus": host["cpus"],
-               "all_threads": {"value": round(rall, 4), "cores": int(threads),
-                               "sample": "%d of the same fields" % min(6, ns)}}
+               "blas_threads_default": int(threads)}
+        if args.cpu_all_threads:
+            _, rall = oracle_rate(range(min(6, ns)))
+            cpu["all_threads"] = {"value": round(rall, 4), "cores": int(threads),
+                                  "sample": "%d of the same fields" % min(6, ns)}
+            _progress("oracle on %d BLAS threads done" % threads)
         err = {"max_rel_logdet": float(max(abs(ld_g[k] - refs[k][0]) / abs(refs[k][0]) for k in range(ns))),
                "max_per_site_logdet": float(max(abs(ld_g[k] - refs[k][0]) for k in range(ns)) / (md["Lx"] * md["Ly"])),
                "max_abs_G": float(max(np.max(np.abs(G_g[k] - refs[k][2])) for k in range(ns))),
@@ -650,9 +656,10 @@ def _oracle_checks(pool, checks):
     ff = []
     for j, f in enumerate(ffut):
         ff.append(f.result(timeout=600))
-        if (j + 1) % 200 == 0:
+        if (j + 1) % 50 == 0:
             _progress("oracle checks: %d of %d evaluations" % (j + 1, len(ffut)))
     fa = [f.result(timeout=600) for f in fa]
+    _progress("oracle checks done: %d + %d evaluations" % (len(ff), len(fa)))
     summary = {}
     for k, r in zip(order, ff):
         name = ferm[k][0]
