@@ -22,8 +22,9 @@ Ltau 80 (256 fields in one call, FP64 against FP32 matrix cores and the int8 spl
 the 12x12 Ltau 120 proposal step of 64 chains (sweep + FP64 cumulative accept), the
 uneven packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
 The cpu_baseline leg times the FP64 CPU oracle on a bounded sample of the 16x16 fields
-(one BLAS thread) and runs it over every GPU output of the other legs in a pool of
-one-thread workers, which gives each leg's error against it.
+(one BLAS thread) and runs it over the GPU outputs of the other legs (every field of the
+4x4, 8x8 and 16x16 legs, 8 items of each size class of the uneven batch, 8 of the 64
+accept chains), which gives each leg's error against it.
 """
 
 import argparse
@@ -374,13 +375,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    # the oracle's worker pool starts before anything touches the GPU (its processes are
-    # spawned, not forked from a process holding the device), and warms up meanwhile
-    pool = None
-    if args.cpu_sample > 0 and not args.no_workloads and args.copy_calibration <= 0:
-        pool = _start_pool()
-        _progress("oracle pool of %d workers started" % pool[1])
-
     import numpy as np
     import torch
 
@@ -457,7 +451,11 @@ def main():
         checks["uneven_packed"] = []
         for prec in (args.precision, "fp64"):
             legs["uneven_packed"][prec], ch = uneven_rates(slmc, torch, np, prec)
-            checks["uneven_packed"] += [(prec + ":" + c[0],) + c[1:] for c in ch]
+            seen = {}
+            for c in ch:     # the first 8 items of each size class
+                seen[c[0]] = seen.get(c[0], 0) + 1
+                if seen[c[0]] <= 8:
+                    checks["uneven_packed"].append((prec + ":" + c[0],) + c[1:])
             _progress("uneven leg (%s) done" % prec)
         checks["errors_16x16_by_lam"] = []
         for li in (0, 2):
@@ -465,8 +463,8 @@ def main():
         _progress("16x16 error leg done")
 
     # CPU oracle: timed on one BLAS thread on a bounded sample of the 16x16 fields (the
-    # baseline), and run over every output of the GPU legs above in a pool of one-thread
-    # workers, which gives the error of each leg against it
+    # baseline), and run over the outputs of the GPU legs above (uneven batch and accept
+    # step sampled), which gives the error of each leg against it
     cpu = None
     err = None
     if args.cpu_sample > 0:
@@ -511,9 +509,9 @@ def main():
                "items": ns, "precision": args.precision, "lam": md["lam"]}
         if checks:
             t1 = time.perf_counter()
-            summary, n_eval, workers = _oracle_checks(pool, checks)
-            cpu["workload_checks"] = {"oracle_evaluations": n_eval, "workers": workers,
-                                      "one_thread_each": True,
+            with threadpool_limits(limits=1):
+                summary, n_eval = _oracle_checks(checks)
+            cpu["workload_checks"] = {"oracle_evaluations": n_eval, "blas_threads": 1,
                                       "wall_s": round(time.perf_counter() - t1, 2)}
             for name, tab in summary.items():
                 legs.setdefault(name, {})["error_vs_oracle"] = tab
@@ -538,8 +536,6 @@ def main():
         "accept_rate": round(main_run["accept"], 4), "wall_s": round(main_run["wall"], 3),
     }
     out.update(legs)
-    if pool is not None:
-        pool[0].shutdown(wait=True)
     print(json.dumps(out), flush=True)
 
 
@@ -548,24 +544,6 @@ def _progress(msg):
 
 
 _T0 = time.perf_counter()
-
-
-def _warm():
-    import oracle  # noqa: F401
-    return os.getpid()
-
-
-def _start_pool():
-    """A pool of one-thread oracle workers (as many as the host CPUs this process may use,
-    at most 16), spawned and warmed up now."""
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
-    workers = max(1, min(16, _host_info()["cpus"]))
-    ex = ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
-                             initializer=_oracle_init)
-    for f in [ex.submit(_warm) for _ in range(workers)]:
-        f.result(timeout=300)
-    return ex, workers
 
 
 def _host_info():
@@ -586,12 +564,6 @@ def _host_info():
 
 
 _E_CACHE = {}
-
-
-def _oracle_init():
-    from threadpoolctl import threadpool_limits
-    global _LIMIT
-    _LIMIT = threadpool_limits(limits=1)
 
 
 def _oracle_fermion(task):
@@ -636,29 +608,26 @@ def _oracle_accept(task):
             abs(logw - lw0) / abs(lw0), bool(a))
 
 
-def _oracle_checks(pool, checks):
-    """Runs the oracle over every GPU output of the workload legs in the pool of one-thread
-    worker processes."""
+def _oracle_checks(checks):
+    """Runs the oracle over the GPU outputs of the workload legs, one evaluation after
+    another in this process (progress on stderr every 50)."""
     import numpy as np
-    ex, workers = pool
     ferm = [(name, t) for name, lst in checks.items() if name != "accept_12x12_ltau120" for t in lst]
     acc = checks.get("accept_12x12_ltau120")
     acc_tasks = []
     if acc:
-        for c in range(len(acc["accepted"])):
+        for c in range(min(8, len(acc["accepted"]))):
             acc_tasks.append((acc["md"], acc["eff"], acc["seed"], c, acc["x_cur"][c], acc["x_prop"][c],
                               float(acc["logw"][c]), float(acc["eeff"][c]), int(acc["accepted"][c]),
                               float(acc["log_ratio"][c])))
-    # the slowest evaluations first, so the pool drains evenly
-    order = sorted(range(len(ferm)), key=lambda k: -ferm[k][1][2].size * ferm[k][1][1]["Lx"] ** 2)
-    fa = [ex.submit(_oracle_accept, t) for t in acc_tasks]
-    ffut = [ex.submit(_oracle_fermion, ferm[k][1]) for k in order]
-    ff = []
-    for j, f in enumerate(ffut):
-        ff.append(f.result(timeout=600))
+    order = list(range(len(ferm)))
+    ff, fa = [], []
+    for j, k in enumerate(order):
+        ff.append(_oracle_fermion(ferm[k][1]))
         if (j + 1) % 50 == 0:
-            _progress("oracle checks: %d of %d evaluations" % (j + 1, len(ffut)))
-    fa = [f.result(timeout=600) for f in fa]
+            _progress("oracle checks: %d of %d evaluations" % (j + 1, len(order)))
+    for t in acc_tasks:
+        fa.append(_oracle_accept(t))
     _progress("oracle checks done: %d + %d evaluations" % (len(ff), len(fa)))
     summary = {}
     for k, r in zip(order, ff):
@@ -682,7 +651,7 @@ def _oracle_checks(pool, checks):
             "decisions_equal": int(a[:, 1].sum()), "accepted_by_oracle": int(a[:, 6].sum()),
             "max_abs_dlog_r": float(a[:, 2].max()), "accept_near_ties": int(a[:, 3].sum()),
             "sweep_near_ties": int(a[:, 4].sum()), "max_rel_logw_current": float(a[:, 5].max())}
-    return summary, len(ferm) + len(acc_tasks), workers
+    return summary, len(ferm) + len(acc_tasks)
 
 
 if __name__ == "__main__":
