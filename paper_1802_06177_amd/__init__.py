@@ -335,3 +335,4 @@ def cumulative_accept(m, eff, x_cur, x_prop, logw_cur, eeff_cur, seed, proposal_
         None if G_prop is None else _dev_f64(G_prop, "G_prop"), vp(st.data_ptr()), wsp, wsn,
         _stream(stream)))
     return acc, lr, st
+

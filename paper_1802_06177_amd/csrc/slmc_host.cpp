@@ -196,8 +196,79 @@ void split_e_int8(const std::vector<double>& Ep, int Np, std::vector<int8_t>& q,
   }
 }
 
+// The padded exponential in every format the segment kernels read, built on the host.
+struct HostConsts {
+  int Np = 0;
+  std::vector<double> E64;
+  std::vector<float> E32;
+  std::vector<uint16_t> b2, b3, lo;
+  std::vector<int8_t> eq;
+  std::vector<double> esc;
+};
+
+void build_consts(const slmc_model* m, HostConsts& h) {
+  const int N = m->Lx * m->Ly, Np = roundup16(N);
+  std::vector<double> E;
+  host_expk(m, E);
+  h.Np = Np;
+  h.E64.assign((size_t)Np * Np, 0.0);
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j)
+      h.E64[(size_t)i * Np + j] = (i < N && j < N) ? E[(size_t)i * N + j] : (i == j ? 1.0 : 0.0);
+  const std::vector<double>& Ep = h.E64;
+  h.E32.resize(Ep.size());
+  for (size_t k = 0; k < Ep.size(); ++k) h.E32[k] = (float)Ep[k];
+  h.b2.resize(2 * Ep.size());
+  h.b3.resize(3 * Ep.size());
+  h.lo.resize(Ep.size());
+  for (size_t k = 0; k < Ep.size(); ++k) h.lo[k] = bf16_rne_host((float)(Ep[k] - (double)h.E32[k]));
+  for (size_t k = 0; k < Ep.size(); ++k) {
+    double r = Ep[k];
+    for (int p = 0; p < 3; ++p) {
+      uint16_t hb = bf16_rne_host((float)r);
+      h.b3[p * Ep.size() + k] = hb;
+      if (p < 2) h.b2[p * Ep.size() + k] = hb;
+      r -= bf16_to_double(hb);
+    }
+  }
+  split_e_int8(Ep, Np, h.eq, h.esc);
+}
+
+// Bytes of the device copy of a model's constants (each piece 256-byte aligned).
+size_t consts_bytes(const HostConsts& h) {
+  return align256(h.E64.size() * 8) + align256(h.E32.size() * 4) + align256(h.b2.size() * 2) +
+         align256(h.b3.size() * 2) + align256(h.lo.size() * 2) + align256(h.eq.size()) +
+         align256(h.esc.size() * 8);
+}
+
+// Points mc's pieces into dev (consts_bytes(h) bytes) and copies them there on st; the
+// host vectors must outlive the copies.
+int upload_consts(const HostConsts& h, char* dev, ModelConsts& mc, hipStream_t st) {
+  size_t off = 0;
+  auto put = [&](const void* src, size_t bytes) -> char* {
+    char* d = dev + off;
+    off += align256(bytes);
+    return (hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess) ? d : nullptr;
+  };
+  mc.Np = h.Np;
+  mc.E64 = (double*)put(h.E64.data(), h.E64.size() * 8);
+  mc.E32 = (float*)put(h.E32.data(), h.E32.size() * 4);
+  mc.Ebf2 = (uint16_t*)put(h.b2.data(), h.b2.size() * 2);
+  mc.Ebf3 = (uint16_t*)put(h.b3.data(), h.b3.size() * 2);
+  mc.Elo = (uint16_t*)put(h.lo.data(), h.lo.size() * 2);
+  mc.Eq = (int8_t*)put(h.eq.data(), h.eq.size());
+  mc.Esc = (double*)put(h.esc.data(), h.esc.size() * 8);
+  if (!mc.E64 || !mc.E32 || !mc.Ebf2 || !mc.Ebf3 || !mc.Elo || !mc.Eq || !mc.Esc)
+    return fail(SLMC_E_DEVICE, "copy of the model constants failed");
+  return SLMC_OK;
+}
+
 std::mutex g_cache_mu;
-std::map<std::tuple<int, int, int, double, double, double>, ModelConsts> g_cache;
+struct CacheEntry {
+  ModelConsts mc;
+  char* base = nullptr;
+};
+std::map<std::tuple<int, int, int, double, double, double>, CacheEntry> g_cache;
 
 int get_consts(const slmc_model* m, ModelConsts** out) {
   int dev = 0;
@@ -205,48 +276,17 @@ int get_consts(const slmc_model* m, ModelConsts** out) {
   auto key = std::make_tuple(dev, m->Lx, m->Ly, m->t, m->mu, m->dtau);
   std::lock_guard<std::mutex> lk(g_cache_mu);
   auto it = g_cache.find(key);
-  if (it != g_cache.end()) { *out = &it->second; return SLMC_OK; }
-  const int N = m->Lx * m->Ly, Np = roundup16(N);
-  std::vector<double> E;
-  host_expk(m, E);
-  std::vector<double> Ep((size_t)Np * Np, 0.0);
-  for (int i = 0; i < Np; ++i)
-    for (int j = 0; j < Np; ++j)
-      Ep[(size_t)i * Np + j] = (i < N && j < N) ? E[(size_t)i * N + j] : (i == j ? 1.0 : 0.0);
-  std::vector<float> E32(Ep.size());
-  for (size_t k = 0; k < Ep.size(); ++k) E32[k] = (float)Ep[k];
-  std::vector<uint16_t> b2(2 * Ep.size()), b3(3 * Ep.size()), lo(Ep.size());
-  for (size_t k = 0; k < Ep.size(); ++k) lo[k] = bf16_rne_host((float)(Ep[k] - (double)E32[k]));
-  for (size_t k = 0; k < Ep.size(); ++k) {
-    double r = Ep[k];
-    for (int p = 0; p < 3; ++p) {
-      uint16_t h = bf16_rne_host((float)r);
-      b3[p * Ep.size() + k] = h;
-      if (p < 2) b2[p * Ep.size() + k] = h;
-      r -= bf16_to_double(h);
-    }
-  }
-  ModelConsts mc;
-  mc.Np = Np;
-  HIPCHK(hipMalloc(&mc.E64, Ep.size() * sizeof(double)));
-  HIPCHK(hipMalloc(&mc.E32, E32.size() * sizeof(float)));
-  HIPCHK(hipMalloc(&mc.Ebf2, b2.size() * sizeof(uint16_t)));
-  HIPCHK(hipMalloc(&mc.Ebf3, b3.size() * sizeof(uint16_t)));
-  HIPCHK(hipMalloc(&mc.Elo, lo.size() * sizeof(uint16_t)));
-  HIPCHK(hipMemcpy(mc.Elo, lo.data(), lo.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(mc.E64, Ep.data(), Ep.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(mc.E32, E32.data(), E32.size() * sizeof(float), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(mc.Ebf2, b2.data(), b2.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(mc.Ebf3, b3.data(), b3.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-  std::vector<int8_t> eq;
-  std::vector<double> esc;
-  split_e_int8(Ep, Np, eq, esc);
-  HIPCHK(hipMalloc(&mc.Eq, eq.size()));
-  HIPCHK(hipMalloc(&mc.Esc, esc.size() * sizeof(double)));
-  HIPCHK(hipMemcpy(mc.Eq, eq.data(), eq.size(), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(mc.Esc, esc.data(), esc.size() * sizeof(double), hipMemcpyHostToDevice));
-  auto res = g_cache.emplace(key, mc);
-  *out = &res.first->second;
+  if (it != g_cache.end()) { *out = &it->second.mc; return SLMC_OK; }
+  HostConsts h;
+  build_consts(m, h);
+  CacheEntry ce;
+  HIPCHK(hipMalloc(&ce.base, consts_bytes(h)));
+  int rc = upload_consts(h, ce.base, ce.mc, nullptr);
+  if (rc) { (void)hipFree(ce.base); return rc; }
+  // the host vectors go out of scope here: wait for the copies
+  HIPCHK(hipStreamSynchronize(nullptr));
+  auto res = g_cache.emplace(key, ce);
+  *out = &res.first->second.mc;
   return SLMC_OK;
 }
 
@@ -337,10 +377,12 @@ size_t group_bytes(const slmc_model* m, int nb) {
 // The hot path for one group of items sharing a model.
 int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, const slmc_batch* batch,
               const double* x, double* logdet, int8_t* sign, double* G, int32_t* status,
-              GroupBufs& w, hipStream_t st) {
-  ModelConsts* mc = nullptr;
-  int rc = get_consts(m, &mc);
-  if (rc) return rc;
+              GroupBufs& w, hipStream_t st, ModelConsts* mc = nullptr) {
+  int rc = SLMC_OK;
+  if (!mc) {
+    rc = get_consts(m, &mc);
+    if (rc) return rc;
+  }
   const int N = m->Lx * m->Ly, Np = mc->Np, nb = (int)grp.items.size();
   const int mseg = (m->Ltau + m->n_s - 1) / m->n_s;
   const size_t n2 = (size_t)Np * Np;
@@ -799,13 +841,7 @@ void slmc_cache_clear(void) {
     int dev = std::get<0>(kv.first), cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(dev);
-    (void)hipFree(kv.second.E64);
-    (void)hipFree(kv.second.E32);
-    (void)hipFree(kv.second.Ebf2);
-    (void)hipFree(kv.second.Ebf3);
-    (void)hipFree(kv.second.Elo);
-    (void)hipFree(kv.second.Eq);
-    (void)hipFree(kv.second.Esc);
+    (void)hipFree(kv.second.base);
     (void)hipSetDevice(cur);
   }
   g_cache.clear();
