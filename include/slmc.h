@@ -236,6 +236,26 @@ int slmc_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches)
 void slmc_profile_reset(void);
 const char* slmc_profile_name(int32_t kernel_class);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): slmc_green (or slmc_logdet when G is
+ * NULL) of n_items fields of ONE model laid out [n_items][Ltau][N] (G [n_items][N][N]),
+ * that allocates nothing.  Its workspace and the model's constants (e^{-dtau K} in every
+ * format) live in a static device array of 256 MiB that the library holds on each GPU it
+ * runs on until the process ends; the workspace part is SLMC_NOALLOC_WORKSPACE_BYTES, and
+ * a batch whose slmc_workspace_bytes() exceeds it is refused with SLMC_E_WORKSPACE (e.g.
+ * at most 18 items of the 16x16, Ltau 160, n_s 8 model; 508 of the 8x8, Ltau 80 one).
+ * It calls no hipMalloc, hipFree or allocating routine and creates no stream or event:
+ * every kernel runs on `stream` in order (the serial schedule, bitwise the results of
+ * slmc_green).  A call whose model differs from the previous call's on this GPU waits for
+ * `stream` (host synchronization) and copies the new constants into the array first.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads without ordering) race and must not be issued.  Arguments,
+ * outputs and per-item status as slmc_green. */
+#define SLMC_NOALLOC_WORKSPACE_BYTES ((size_t)248 << 20)
+int slmc_green_noalloc(const slmc_model* model, const slmc_options* opt, int32_t n_items,
+                       const double* x, double* logdet, int8_t* sign, double* G,
+                       int32_t* status, void* stream);
+
 /* Frees the library's device constant cache (e^{-dtau K} copies per model and device)
  * and its side streams (after waiting for them).  Must not be called while work that
  * uses them is still queued on other streams. */

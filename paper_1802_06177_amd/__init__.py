@@ -336,3 +336,25 @@ def cumulative_accept(m, eff, x_cur, x_prop, logw_cur, eeff_cur, seed, proposal_
         _stream(stream)))
     return acc, lr, st
 
+
+def green_noalloc(m, x, opt=None, want_g=True, G=None, stream=None):
+    """slmc_green_noalloc: log-det, sign, (G) and status of the fields x [items, Ltau, N] of
+    one model, with the library's static scratch as workspace (no device allocation in the
+    library; the outputs are allocated here unless G is passed)."""
+    torch = _torch()
+    n = _chains(m, x)
+    N = m.Lx * m.Ly
+    if G is not None:
+        _shape(G, (n, N, N), "G")
+    xp = _dev_f64(x, "x")
+    opt = opt or options()
+    logdet = torch.empty(n, dtype=torch.float64, device=x.device)
+    sign = torch.empty(n, dtype=torch.int8, device=x.device)
+    status = torch.empty(n, dtype=torch.int32, device=x.device)
+    if want_g and G is None:
+        G = torch.empty((n, N, N), dtype=torch.float64, device=x.device)
+    vp = C.c_void_p
+    _abi.check(_abi.lib().slmc_green_noalloc(
+        C.byref(m), C.byref(opt), n, xp, vp(logdet.data_ptr()), vp(sign.data_ptr()),
+        _dev_f64(G, "G") if want_g else None, vp(status.data_ptr()), _stream(stream)))
+    return (logdet, sign, G, status) if want_g else (logdet, sign, status)

@@ -641,9 +641,89 @@ size_t accept_bytes(const slmc_model* m, int nch) {
   return b;
 }
 
+// ---- the entry point that allocates nothing --------------------------------------------
+// Its workspace and the model's constants live in one static device array per GPU
+// (`scratch`, kScratchBytes, held until the process ends).  Host code never uses the
+// array's name as an address: at the first call on a device the address of that device's
+// copy is taken with hipGetSymbolAddress and kept per device; kernels get that pointer.
+constexpr size_t kScratchBytes = 256ull << 20;   // whole array
+constexpr size_t kScratchConst = 8ull << 20;     // first part: the model's constants
+static_assert(kScratchBytes - kScratchConst == SLMC_NOALLOC_WORKSPACE_BYTES,
+              "header limit and scratch layout disagree");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchDev {
+  char* ptr = nullptr;            // device address of this device's `scratch`
+  bool have_consts = false;
+  std::tuple<int, int, double, double, double> key;
+  HostConsts host;                // source of the resident constants (kept for the copies)
+  ModelConsts mc;
+};
+std::mutex g_scr_mu;
+std::map<int, ScratchDev> g_scr;
+
+int green_noalloc(const slmc_model* m, const slmc_options* opt, int32_t n_items, const double* x,
+                  double* logdet, int8_t* sign, double* G, int32_t* status, hipStream_t st) {
+  int rc = check_model(m);
+  if (rc) return rc;
+  rc = check_opt(opt);
+  if (rc) return rc;
+  if (n_items < 0) return fail(SLMC_E_ARG, "n_items < 0");
+  if (n_items == 0) return SLMC_OK;
+  if (!x || !logdet || !sign || !status) return fail(SLMC_E_ARG, "NULL output or input pointer");
+  const size_t need = group_bytes(m, n_items);
+  if (need > kScratchBytes - kScratchConst)
+    return fail(SLMC_E_WORKSPACE, "%d items of this model need %zu bytes of workspace; the static "
+                "scratch holds %zu", n_items, need, kScratchBytes - kScratchConst);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scr_mu);
+  ScratchDev& sd = g_scr[dev];
+  if (!sd.ptr) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SLMC_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    sd.ptr = (char*)p;
+  }
+  // the constants of this model, copied into the scratch on the caller's stream when the
+  // resident ones belong to another model (the host copy stays alive in sd.host)
+  auto key = std::make_tuple(m->Lx, m->Ly, m->t, m->mu, m->dtau);
+  if (!sd.have_consts || sd.key != key) {
+    // earlier calls on this stream may still read the resident constants, and their
+    // copies may still read the host source: let them finish first
+    if (sd.have_consts) HIPCHK(hipStreamSynchronize(st));
+    sd.have_consts = false;
+    sd.host = HostConsts();
+    build_consts(m, sd.host);
+    if (consts_bytes(sd.host) > kScratchConst)
+      return fail(SLMC_E_SHAPE, "model constants exceed the static scratch's constant part");
+    rc = upload_consts(sd.host, sd.ptr, sd.mc, st);
+    if (rc) return rc;
+    sd.key = key;
+    sd.have_consts = true;
+  }
+  Arena a(sd.ptr + kScratchConst);
+  GroupBufs w;
+  carve(a, n_items, roundup16(m->Lx * m->Ly), (m->Ltau + m->n_s - 1) / m->n_s, w);
+  Group grp{0, {}};
+  for (int b = 0; b < n_items; ++b) grp.items.push_back(b);
+  slmc_batch bt{n_items, nullptr, nullptr, nullptr};
+  slmc_options o = *opt;
+  o.flags |= SLMC_FLAG_SERIAL;    // no library streams or events: everything on st
+  return run_group(m, &o, grp, &bt, x, logdet, sign, G, status, w, st, &sd.mc);
+}
+
 }  // namespace
 
 extern "C" {
+
+int slmc_green_noalloc(const slmc_model* model, const slmc_options* opt, int32_t n_items,
+                       const double* x, double* logdet, int8_t* sign, double* G,
+                       int32_t* status, void* stream) {
+  g_err.clear();
+  return green_noalloc(model, opt, n_items, x, logdet, sign, G, status, (hipStream_t)stream);
+}
+
 
 int slmc_version(void) { return 10000; }
 
