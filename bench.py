@@ -20,7 +20,7 @@ the slice-product kernel in the overlapped run and with every kernel run alone, 
 effective-model sweeps alone, and the other workloads: 4x4 Ltau 40 (64 fields), 8x8
 Ltau 80 (256 fields in one call, FP64 against FP32 matrix cores and the int8 split),
 the 12x12 Ltau 120 proposal step of 64 chains (sweep + FP64 cumulative accept), the
-uneven packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
+modified Wolff cluster moves on the same shape, the uneven packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
 The cpu_baseline leg times the FP64 CPU oracle on a bounded sample of the 16x16 fields
 (one BLAS thread) and runs it over the GPU outputs of the other legs (every field of the
 4x4, 8x8 and 16x16 legs, 8 items of each size class of the uneven batch, 8 of the 64
@@ -242,6 +242,45 @@ def errors_16x16(slmc, torch, np, prec, lam_idx):
             for b in range(128)]
 
 
+def wolff_12x12(slmc, torch, np, chains=64, n_clusters=4, reps=5):
+    """Modified Wolff cluster moves (SM Sec. IV) alone on the 12x12, Ltau = 120 shape with
+    the seeded effective model: cluster moves per second, mean cluster size, and the
+    whole cumulative proposal (one sweep + the cluster moves in the coin's order); the
+    first launch's inputs and outputs for the oracle check."""
+    from synth import gen, eff_coefficients, workload_models
+    md = workload_models("W3")[0]
+    m = slmc.model_from_dict(md)
+    effd = eff_coefficients(3, 0, md["lam"], delta=0.5)
+    eff = slmc.eff_model(**effd)
+    x0 = gen(3, 501).normal(size=(chains, md["Ltau"], md["Lx"] * md["Ly"]))
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda:0")
+    seed = 1802061771
+    sizes0 = slmc.eff_wolff(m, eff, x, n_clusters, seed, 0)
+    torch.cuda.synchronize()
+    first = dict(md=md, eff=effd, seed=seed, n_clusters=n_clusters, x_in=x0, x_out=x.cpu().numpy(),
+                 sizes=sizes0.cpu().numpy())
+    k = [0]
+
+    def clusters():
+        k[0] += 1
+        slmc.eff_wolff(m, eff, x, n_clusters, seed, k[0])
+
+    def proposal():
+        k[0] += 1
+        slmc.eff_propose(m, eff, x, 1, n_clusters, seed, k[0])
+
+    t_w = _timed(torch, clusters, reps)
+    t_p = _timed(torch, proposal, reps)
+    sz = slmc.eff_wolff(m, eff, x, n_clusters, seed, 10 ** 6).float().mean().item()
+    out = {"chains": chains, "clusters_per_launch": n_clusters,
+           "cluster_moves_per_s": round(chains * n_clusters / t_w, 1),
+           "ms_per_launch": round(t_w * 1e3, 4), "mean_cluster_size": round(sz, 2),
+           "sites": md["Lx"] * md["Ly"],
+           "proposal_ms": round(t_p * 1e3, 4),
+           "proposals_per_s": round(chains / t_p, 1)}
+    return out, first
+
+
 def accept_12x12(slmc, torch, np, steps=10):
     """64 chains of the 12x12, Ltau = 120 shape (n_s = 10, lam = 1.5) with the seeded
     effective model (couplings out to the third neighbour): one proposal = copy, one
@@ -447,6 +486,8 @@ def main():
         _progress("8x8 leg done")
         legs["accept_12x12_ltau120"], checks["accept_12x12_ltau120"] = accept_12x12(slmc, torch, np)
         _progress("12x12 accept leg done")
+        legs["wolff_12x12_ltau120"], checks["wolff_12x12_ltau120"] = wolff_12x12(slmc, torch, np)
+        _progress("12x12 Wolff leg done")
         legs["uneven_packed"] = {}
         checks["uneven_packed"] = []
         for prec in (args.precision, "fp64"):
@@ -612,7 +653,8 @@ def _oracle_checks(checks):
     """Runs the oracle over the GPU outputs of the workload legs, one evaluation after
     another in this process (progress on stderr every 50)."""
     import numpy as np
-    ferm = [(name, t) for name, lst in checks.items() if name != "accept_12x12_ltau120" for t in lst]
+    ferm = [(name, t) for name, lst in checks.items()
+            if name not in ("accept_12x12_ltau120", "wolff_12x12_ltau120") for t in lst]
     acc = checks.get("accept_12x12_ltau120")
     acc_tasks = []
     if acc:
@@ -628,6 +670,21 @@ def _oracle_checks(checks):
             _progress("oracle checks: %d of %d evaluations" % (j + 1, len(order)))
     for t in acc_tasks:
         fa.append(_oracle_accept(t))
+    wf = checks.get("wolff_12x12_ltau120")
+    wres = None
+    if wf:
+        from oracle.effective import EffModel
+        from oracle.wolff import wolff as o_wolff
+        d = wf["md"]
+        om = EffModel(**{**wf["eff"], "Js": tuple(wf["eff"]["Js"])})
+        same, ties, n = 0, 0, min(4, len(wf["sizes"]))
+        for c in range(n):
+            xo = wf["x_in"][c].copy()
+            margins = []
+            so = o_wolff(xo, d["Lx"], d["Ly"], om, wf["n_clusters"], wf["seed"], 0, c, margins=margins)
+            ties += int(np.sum(np.abs(np.asarray(margins)) <= 1e-12))
+            same += int(list(wf["sizes"][c]) == so and np.array_equal(wf["x_out"][c], xo))
+        wres = {"chains": n, "fields_and_clusters_equal": same, "bond_near_ties": ties}
     _progress("oracle checks done: %d + %d evaluations" % (len(ff), len(fa)))
     summary = {}
     for k, r in zip(order, ff):
@@ -651,7 +708,9 @@ def _oracle_checks(checks):
             "decisions_equal": int(a[:, 1].sum()), "accepted_by_oracle": int(a[:, 6].sum()),
             "max_abs_dlog_r": float(a[:, 2].max()), "accept_near_ties": int(a[:, 3].sum()),
             "sweep_near_ties": int(a[:, 4].sum()), "max_rel_logw_current": float(a[:, 5].max())}
-    return summary, len(ferm) + len(acc_tasks)
+    if wres:
+        summary["wolff_12x12_ltau120"] = wres
+    return summary, len(ferm) + len(acc_tasks) + (wres["chains"] if wres else 0)
 
 
 if __name__ == "__main__":

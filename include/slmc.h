@@ -190,6 +190,34 @@ int slmc_eff_sweep(const slmc_model* model, const slmc_eff* eff, int32_t n_chain
                    double* x, int32_t n_sweeps, uint64_t seed, uint64_t proposal_idx,
                    int64_t* n_accepted, void* stream);
 
+/* n_clusters modified Wolff cluster moves of every chain, in place (SM Sec. IV, Eq. S8):
+ * a cluster grows in the spatial plane, each site carrying its whole time column; bond
+ * (i, t) joins site i to its neighbour at offset t (t = 0..5: (1,0), (0,1) with Js[0];
+ * (1,1), (1,-1) with Js[1]; (2,0), (0,2) with Js[2]; terms with J = 0 or whose ends
+ * coincide are no bonds) and is open with probability 1 - exp(min(0, 2 e)),
+ * e = J sum_l x[l][i] x[l][j]; the cluster (the seed's component of the open bonds) is
+ * reflected, x -> -x on its columns, which the Z2-even effective model always accepts.
+ *   Random numbers: Philox4x32-10, key (seed lo, seed hi); bond 6 i + t of cluster w:
+ *   counter (6 i + t, 0x80000000 + w, proposal_idx mod 2^32, chain), word 0 -> u, open iff
+ *   e < 0 and u < -expm1(2 e); seed site of cluster w: counter (0xFFFFFFFD, 0x80000000 + w,
+ *   proposal, chain), word 0 -> r, site floor(r N / 2^32); u = (r + 1/2) 2^-32.
+ *   x device [n_chains][Ltau][N] in/out; cluster_sizes device [n_chains][n_clusters] int32
+ *   or NULL. */
+int slmc_eff_wolff(const slmc_model* model, const slmc_eff* eff, int32_t n_chains, double* x,
+                   int32_t n_clusters, uint64_t seed, uint64_t proposal_idx, int32_t* cluster_sizes,
+                   void* stream);
+
+/* The whole cumulative proposal of every chain, in place (SM Sec. IV, last paragraph:
+ * local sweeps and cluster moves together): the proposal's coin (as in slmc_eff_sweep)
+ * picks, per chain, either n_sweeps sweeps in forward phase order followed by n_clusters
+ * cluster moves, or the cluster moves followed by the sweeps in reverse phase order; the
+ * equal mixture of the two orders is reversible, so the acceptance of Eq. 6 stays exact.
+ * Random numbers as slmc_eff_sweep and slmc_eff_wolff.  n_accepted device [n_chains]
+ * int64 (local moves), cluster_sizes as slmc_eff_wolff.  Needs what slmc_eff_sweep needs. */
+int slmc_eff_propose(const slmc_model* model, const slmc_eff* eff, int32_t n_chains, double* x,
+                     int32_t n_sweeps, int32_t n_clusters, uint64_t seed, uint64_t proposal_idx,
+                     int64_t* n_accepted, int32_t* cluster_sizes, void* stream);
+
 /* Device workspace, in bytes, of slmc_cumulative_accept for n_chains chains. */
 size_t slmc_accept_workspace_bytes(const slmc_model* model, int32_t n_chains,
                                    const slmc_options* opt);

@@ -19,8 +19,8 @@ from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLA
                    Model, Options, Batch, Eff)
 
 __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
-           "eff_energy", "eff_sweep", "log_weight", "cumulative_accept", "cache_clear",
-           "SlmcError", "version"]
+           "eff_energy", "eff_sweep", "eff_wolff", "eff_propose", "log_weight", "cumulative_accept",
+           "green_noalloc", "cache_clear", "SlmcError", "version"]
 
 PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6,
               "fp32plain": SLMC_FP32_PLAIN, "int8x5": SLMC_INT8X5}
@@ -287,6 +287,33 @@ def eff_sweep(m, eff, x, n_sweeps, seed, proposal_idx, stream=None):
                                          int(n_sweeps), C.c_uint64(seed), C.c_uint64(proposal_idx),
                                          C.c_void_p(nacc.data_ptr()), _stream(stream)))
     return nacc
+
+
+def eff_wolff(m, eff, x, n_clusters, seed, proposal_idx, stream=None):
+    """n_clusters modified Wolff cluster moves of every chain of x [chains, Ltau, N], in
+    place (SM Sec. IV); returns the cluster sizes [chains, n_clusters]."""
+    torch = _torch()
+    n = _chains(m, x)
+    sizes = torch.empty((n, max(int(n_clusters), 0)), dtype=torch.int32, device=x.device)
+    _abi.check(_abi.lib().slmc_eff_wolff(C.byref(m), C.byref(eff), n, _dev_f64(x, "x"),
+                                         int(n_clusters), C.c_uint64(seed), C.c_uint64(proposal_idx),
+                                         C.c_void_p(sizes.data_ptr()), _stream(stream)))
+    return sizes
+
+
+def eff_propose(m, eff, x, n_sweeps, n_clusters, seed, proposal_idx, stream=None):
+    """The cumulative proposal of every chain of x [chains, Ltau, N], in place: sweeps and
+    cluster moves in the order of the proposal's coin.  Returns (accepted local moves
+    [chains] int64, cluster sizes [chains, n_clusters] int32)."""
+    torch = _torch()
+    n = _chains(m, x)
+    nacc = torch.empty(n, dtype=torch.int64, device=x.device)
+    sizes = torch.empty((n, max(int(n_clusters), 0)), dtype=torch.int32, device=x.device)
+    _abi.check(_abi.lib().slmc_eff_propose(C.byref(m), C.byref(eff), n, _dev_f64(x, "x"),
+                                           int(n_sweeps), int(n_clusters), C.c_uint64(seed),
+                                           C.c_uint64(proposal_idx), C.c_void_p(nacc.data_ptr()),
+                                           C.c_void_p(sizes.data_ptr()), _stream(stream)))
+    return nacc, sizes
 
 
 def log_weight(m, x, opt=None, stream=None, ws=None):

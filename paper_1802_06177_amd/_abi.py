@@ -15,7 +15,8 @@ SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLAIN, SLMC_INT8X5 = r
 EXPORTS = ("slmc_version", "slmc_last_error", "slmc_expk", "slmc_workspace_bytes", "slmc_logdet",
            "slmc_green", "slmc_eff_energy", "slmc_eff_sweep", "slmc_accept_workspace_bytes",
            "slmc_cumulative_accept", "slmc_log_weight", "slmc_profile", "slmc_profile_read",
-           "slmc_profile_reset", "slmc_profile_name", "slmc_cache_clear", "slmc_green_noalloc")
+           "slmc_profile_reset", "slmc_profile_name", "slmc_cache_clear", "slmc_green_noalloc",
+           "slmc_eff_wolff", "slmc_eff_propose")
 SLMC_NOALLOC_WORKSPACE_BYTES = 248 << 20
 
 
@@ -74,6 +75,8 @@ def lib():
     L.slmc_profile_name.argtypes = [i32]
     L.slmc_log_weight.argtypes = [P(Model), P(Options), i32, vp, vp, vp, vp, sz, vp]
     L.slmc_cache_clear.restype = None
+    L.slmc_eff_wolff.argtypes = [P(Model), P(Eff), i32, vp, i32, u64, u64, vp, vp]
+    L.slmc_eff_propose.argtypes = [P(Model), P(Eff), i32, vp, i32, i32, u64, u64, vp, vp, vp]
     L.slmc_green_noalloc.argtypes = [P(Model), P(Options), i32, vp, vp, vp, vp, vp, vp]
     _lib = L
     return L

@@ -6,38 +6,15 @@
 // Sweep design: one workgroup per chain holds the chain's whole field in LDS when it fits
 // (N Ltau doubles <= 144 KB; e.g. 12x12x120), otherwise works on it in place in global
 // memory (L2-resident); every colour phase updates its sites in parallel (no two sites of
-// a phase share a coupling) and a barrier separates phases.  Random numbers come from a
-// Philox4x32-10 written here from its published definition (Salmon et al., SC'11).
+// a phase share a coupling) and a barrier separates phases.  Random numbers come from the
+// Philox4x32-10 of philox.h.
 #include "common.h"
 #include "launch.h"
+#include "philox.h"
 
 namespace slmc {
 
 namespace {
-
-struct U4 { uint32_t x, y, z, w; };
-
-__device__ __forceinline__ U4 philox(U4 c, uint32_t k0, uint32_t k1) {
-  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
-    const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
-    U4 n;
-    n.x = hi1 ^ c.y ^ k0;
-    n.y = lo1;
-    n.z = hi0 ^ c.w ^ k1;
-    n.w = lo0;
-    c = n;
-    k0 += W0;
-    k1 += W1;
-  }
-  return c;
-}
-
-__device__ __forceinline__ double u01(uint32_t r) {
-  return ((double)r + 0.5) * 2.3283064365386962890625e-10;   // 2^-32
-}
 
 __device__ __forceinline__ int wrap(int a, int L) { a %= L; return a < 0 ? a + L : a; }
 // periodic wrap of -L <= a < 2 L without a division
@@ -166,8 +143,7 @@ __global__ __launch_bounds__(1024) void eff_sweep_k(double* __restrict__ x, int 
   }
   const int m2 = mod * mod, P = 2 * m2;
   const int nx = Lx / mod, ny = Ly / mod, per_l = nx * ny, cnt = (Ltau / 2) * per_l;
-  const U4 cc = philox(U4{0xFFFFFFFFu, 0xFFFFFFFEu, prop, (uint32_t)ch}, k0, k1);
-  const bool forward = cc.x < 0x80000000u;
+  const bool forward = proposal_forward(prop, (uint32_t)ch, k0, k1);
   // Work item t = lq per_l + ry nx + rx of a phase is the site (sx + mod rx, sy + mod ry) of
   // slice tc + 2 lq.  A thread's items are t0, t0 + blockDim, ..., the same in every phase:
   // their (lq, ry, rx) start from t0 and advance by blockDim's (dq, dry, drx) with carries,

@@ -101,6 +101,13 @@ hipError_t launch_eff_sweep(double* x, int nch, int Lx, int Ly, int Ltau, EffPar
                             int mod, int n_sweeps, uint64_t seed, uint64_t proposal,
                             int64_t* nacc, hipStream_t st);
 
+// n_clusters modified Wolff cluster moves of every chain (in place), bonds from the spatial
+// couplings Js[3]; coin_mode 0: every chain, 1: only chains whose proposal coin picks the
+// forward order, 2: only the reverse ones.  sizes (or nullptr): [nch][n_clusters].
+hipError_t launch_wolff(double* x, int nch, int Lx, int Ly, int Ltau, const double* Js,
+                        int n_clusters, uint64_t seed, uint64_t proposal, int coin_mode,
+                        int* sizes, hipStream_t st);
+
 // log w = -dtau S_Bose + 2 logdet for every chain.
 hipError_t launch_log_weight(const double* x, const double* logdet, int nch, int N, int Ltau,
                              double lam, double omega0, double dtau, double c_kin,

@@ -798,6 +798,51 @@ int slmc_eff_sweep(const slmc_model* model, const slmc_eff* eff, int32_t n_chain
   return SLMC_OK;
 }
 
+int slmc_eff_wolff(const slmc_model* model, const slmc_eff* eff, int32_t n_chains, double* x,
+                   int32_t n_clusters, uint64_t seed, uint64_t proposal_idx, int32_t* cluster_sizes,
+                   void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (!eff || !x) return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_chains < 0 || n_clusters < 0) return fail(SLMC_E_ARG, "negative count");
+  if (n_chains == 0 || n_clusters == 0) return SLMC_OK;
+  HIPCHK(launch_wolff(x, n_chains, model->Lx, model->Ly, model->Ltau, eff->Js, n_clusters, seed,
+                      proposal_idx, 0, cluster_sizes, (hipStream_t)stream));
+  return SLMC_OK;
+}
+
+int slmc_eff_propose(const slmc_model* model, const slmc_eff* eff, int32_t n_chains, double* x,
+                     int32_t n_sweeps, int32_t n_clusters, uint64_t seed, uint64_t proposal_idx,
+                     int64_t* n_accepted, int32_t* cluster_sizes, void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (!eff || !x || !n_accepted) return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_chains < 0 || n_sweeps < 0 || n_clusters < 0) return fail(SLMC_E_ARG, "negative count");
+  if (model->Ltau < 2 || model->Ltau % 2) return fail(SLMC_E_SHAPE, "Ltau must be even and >= 2");
+  if (!std::isfinite(eff->delta)) return fail(SLMC_E_ARG, "delta must be finite");
+  int mod = 1;
+  rc = colour_mod(model, eff, &mod);
+  if (rc) return rc;
+  if (n_chains == 0) return SLMC_OK;
+  hipStream_t st = (hipStream_t)stream;
+  // reverse-coin chains: clusters first; then every chain's sweeps (each in its coin's
+  // phase order); then the forward-coin chains' clusters
+  if (n_clusters > 0)
+    HIPCHK(launch_wolff(x, n_chains, model->Lx, model->Ly, model->Ltau, eff->Js, n_clusters, seed,
+                        proposal_idx, 2, cluster_sizes, st));
+  {
+    ProfScope ps(7, st);
+    HIPCHK(launch_eff_sweep(x, n_chains, model->Lx, model->Ly, model->Ltau, eff_params(eff), mod,
+                            n_sweeps, seed, proposal_idx, n_accepted, st));
+  }
+  if (n_clusters > 0)
+    HIPCHK(launch_wolff(x, n_chains, model->Lx, model->Ly, model->Ltau, eff->Js, n_clusters, seed,
+                        proposal_idx, 1, cluster_sizes, st));
+  return SLMC_OK;
+}
+
 size_t slmc_accept_workspace_bytes(const slmc_model* model, int32_t n_chains,
                                    const slmc_options* opt) {
   (void)opt;
