@@ -21,6 +21,7 @@ effective  symmetric effective model E_eff, local dE, checkerboard
 philox     Philox4x32-10 counter-based generator (Salmon et al., SC'11)
 accept     SLMC cumulative-update acceptance                        (Eq. 6)
 wolff      modified Wolff cluster moves and the cumulative proposal (SM Sec. IV, Eq. S8)
+measure    G at every time slice and the CDW structure factor's estimators (SM Eq. S3)
 """
 
 from .lattice import hopping_matrix, expk
@@ -30,10 +31,11 @@ from .effective import EffModel, eff_energy, eff_local_delta, colouring, sweep
 from .philox import philox4x32_10, uniform01
 from .accept import cumulative_accept
 from .wolff import cluster as wolff_cluster, wolff, propose
+from .measure import green_slices, cdw_estimators, stagger
 
 __all__ = [
     "hopping_matrix", "expk", "slice_scales", "udv_chain", "recombine", "logdet_green",
     "logdet_green_direct", "bosonic_action", "log_weight", "EffModel", "eff_energy",
     "eff_local_delta", "colouring", "sweep", "philox4x32_10", "uniform01", "cumulative_accept",
-    "wolff_cluster", "wolff", "propose",
+    "wolff_cluster", "wolff", "propose", "green_slices", "cdw_estimators", "stagger",
 ]
