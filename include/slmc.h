@@ -190,6 +190,30 @@ int slmc_eff_sweep(const slmc_model* model, const slmc_eff* eff, int32_t n_chain
                    double* x, int32_t n_sweeps, uint64_t seed, uint64_t proposal_idx,
                    int64_t* n_accepted, void* stream);
 
+/* Device workspace, in bytes, of slmc_green_slices for n_items fields of one model. */
+size_t slmc_slices_workspace_bytes(const slmc_model* model, int32_t n_items,
+                                   const slmc_options* opt);
+
+/* The equal-time Green's function after every time slice, G(l) = [I + B_l ... B_0
+ * B_{Ltau-1} ... B_{l+1}]^{-1} for l = 0 .. Ltau-1 (SM Eq. S3; slice l = Ltau-1 is the G of
+ * slmc_green), and per slice the CDW structure factor's estimators (main text, "Results";
+ * two identical spin species, Wick's theorem):
+ *   s_nn = N^-1 sum_ij p_i p_j <n_i n_j>,  <n_i n_j> = <n_i><n_j> + 2 (delta_ij - G_ji) G_ij,
+ *   m_st = N^-1 sum_i p_i <n_i>,           <n_i> = 2 (1 - G_ii),   p_i = (-1)^(ix+iy);
+ * over a Markov chain S_CDW = mean(s_nn) - N mean(m_st)^2.
+ * Every n_wrap-th slice (l = n_wrap - 1, 2 n_wrap - 1, ..., and Ltau - 1) is evaluated by
+ * the stabilized chain (precision opt->precision) of the field rotated to start after it;
+ * the slices between are propagated from the last evaluated one, G(l+1) = B_{l+1} G(l)
+ * B_{l+1}^{-1}, with FP64 matrix-core products (n_wrap = 1: every slice evaluated; the
+ * propagation error grows at most by the condition number of B per slice).
+ *   x device [n_items][Ltau][N]; G_all device [n_items][Ltau][N][N] or NULL (only the
+ *   estimators); s_nn, m_st device [n_items][Ltau] double; status device [n_items] int32
+ *   (the first non-OK status of the evaluations); ws device workspace of
+ *   slmc_slices_workspace_bytes(). */
+int slmc_green_slices(const slmc_model* model, const slmc_options* opt, int32_t n_items,
+                      const double* x, int32_t n_wrap, double* G_all, double* s_nn, double* m_st,
+                      int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* n_clusters modified Wolff cluster moves of every chain, in place (SM Sec. IV, Eq. S8):
  * a cluster grows in the spatial plane, each site carrying its whole time column; bond
  * (i, t) joins site i to its neighbour at offset t (t = 0..5: (1,0), (0,1) with Js[0];

@@ -27,12 +27,12 @@ import numpy as np
 from .fermion import logdet_green
 
 
-def green_slices(E, x, dtau, lam, n_s):
+def green_slices(E, x, dtau, lam, n_s, slices=None):
     """[G after slice l for l = 0 .. Ltau-1] (SM Eq. S3), each by the stabilized chain of
-    the rotated field (reading A34)."""
+    the rotated field (reading A34); only the listed slices if `slices` is given."""
     Ltau = x.shape[0]
     out = []
-    for l in range(Ltau):
+    for l in (range(Ltau) if slices is None else slices):
         xr = np.roll(x, -(l + 1), axis=0)      # xr[k] = x[(k + l + 1) mod Ltau]
         out.append(logdet_green(E, xr, dtau, lam, n_s)[2])
     return np.array(out)

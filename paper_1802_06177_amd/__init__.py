@@ -20,7 +20,7 @@ from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLA
 
 __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
            "eff_energy", "eff_sweep", "eff_wolff", "eff_propose", "log_weight", "cumulative_accept",
-           "green_noalloc", "cache_clear", "SlmcError", "version"]
+           "green_noalloc", "green_slices", "cache_clear", "SlmcError", "version"]
 
 PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6,
               "fp32plain": SLMC_FP32_PLAIN, "int8x5": SLMC_INT8X5}
@@ -287,6 +287,28 @@ def eff_sweep(m, eff, x, n_sweeps, seed, proposal_idx, stream=None):
                                          int(n_sweeps), C.c_uint64(seed), C.c_uint64(proposal_idx),
                                          C.c_void_p(nacc.data_ptr()), _stream(stream)))
     return nacc
+
+
+def green_slices(m, x, n_wrap, opt=None, want_g=False, stream=None, ws=None):
+    """G after every time slice (SM Eq. S3) and the CDW estimators per slice for the
+    fields x [items, Ltau, N]: returns (s_nn [items, Ltau], m_st [items, Ltau], status
+    [items], G_all [items, Ltau, N, N] or None)."""
+    torch = _torch()
+    n = _chains(m, x)
+    opt = opt or options()
+    L = _abi.lib()
+    N, Lt = m.Lx * m.Ly, m.Ltau
+    need = L.slmc_slices_workspace_bytes(C.byref(m), n, C.byref(opt))
+    wsp, wsn = _ws_args(ws if ws is not None else _workspace(need, x.device, stream))
+    s_nn = torch.empty((n, Lt), dtype=torch.float64, device=x.device)
+    m_st = torch.empty((n, Lt), dtype=torch.float64, device=x.device)
+    st = torch.empty(n, dtype=torch.int32, device=x.device)
+    G = torch.empty((n, Lt, N, N), dtype=torch.float64, device=x.device) if want_g else None
+    vp = C.c_void_p
+    _abi.check(L.slmc_green_slices(C.byref(m), C.byref(opt), n, _dev_f64(x, "x"), int(n_wrap),
+                                   None if G is None else vp(G.data_ptr()), vp(s_nn.data_ptr()),
+                                   vp(m_st.data_ptr()), vp(st.data_ptr()), wsp, wsn, _stream(stream)))
+    return s_nn, m_st, st, G
 
 
 def eff_wolff(m, eff, x, n_clusters, seed, proposal_idx, stream=None):

@@ -16,7 +16,8 @@ EXPORTS = ("slmc_version", "slmc_last_error", "slmc_expk", "slmc_workspace_bytes
            "slmc_green", "slmc_eff_energy", "slmc_eff_sweep", "slmc_accept_workspace_bytes",
            "slmc_cumulative_accept", "slmc_log_weight", "slmc_profile", "slmc_profile_read",
            "slmc_profile_reset", "slmc_profile_name", "slmc_cache_clear", "slmc_green_noalloc",
-           "slmc_eff_wolff", "slmc_eff_propose")
+           "slmc_eff_wolff", "slmc_eff_propose", "slmc_slices_workspace_bytes",
+           "slmc_green_slices")
 SLMC_NOALLOC_WORKSPACE_BYTES = 248 << 20
 
 
@@ -75,6 +76,9 @@ def lib():
     L.slmc_profile_name.argtypes = [i32]
     L.slmc_log_weight.argtypes = [P(Model), P(Options), i32, vp, vp, vp, vp, sz, vp]
     L.slmc_cache_clear.restype = None
+    L.slmc_slices_workspace_bytes.restype = sz
+    L.slmc_slices_workspace_bytes.argtypes = [P(Model), i32, P(Options)]
+    L.slmc_green_slices.argtypes = [P(Model), P(Options), i32, vp, i32, vp, vp, vp, vp, vp, sz, vp]
     L.slmc_eff_wolff.argtypes = [P(Model), P(Eff), i32, vp, i32, u64, u64, vp, vp]
     L.slmc_eff_propose.argtypes = [P(Model), P(Eff), i32, vp, i32, i32, u64, u64, vp, vp, vp]
     L.slmc_green_noalloc.argtypes = [P(Model), P(Options), i32, vp, vp, vp, vp, vp, vp]

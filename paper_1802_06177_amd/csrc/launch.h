@@ -108,6 +108,25 @@ hipError_t launch_wolff(double* x, int nch, int Lx, int Ly, int Ltau, const doub
                         int n_clusters, uint64_t seed, uint64_t proposal, int coin_mode,
                         int* sizes, hipStream_t st);
 
+// ---- G at every slice, CDW estimators ----
+// xr[b][k] = x[b][(k + r) mod Ltau] (fields [nb][Ltau][N])
+hipError_t launch_rotate_fields(const double* x, double* xr, int nb, int N, int Ltau, int r,
+                                hipStream_t st);
+// Gout[b] = B_s Gin[b] B_s^{-1}, B_s = E diag(exp(-ldl x[b][s])), via T[b] (scratch
+// [nb][N][N]); E and Einv = e^{+dtau K} with leading dimension ldE; G strides sgin/sgout.
+hipError_t launch_propagate(const double* Gin, int64_t sgin, double* Gout, int64_t sgout,
+                            double* T, const double* E, const double* Einv, int ldE,
+                            const double* x, int s, double ldl, int nb, int N, int Ltau,
+                            hipStream_t st);
+// s_nn[b so], m_st[b so] of G + b sg (N x N, row-major)
+hipError_t launch_cdw(const double* G, int64_t sg, int nb, int Lx, int N, double* s_nn, double* m_st,
+                      int64_t so, hipStream_t st);
+// dst[b sd + e] = src[b ss + e] for e < n, b < nb
+hipError_t launch_copy_items(const double* src, int64_t ss, double* dst, int64_t sd, int64_t n, int nb,
+                             hipStream_t st);
+// out[i] = a[i] (first) or the first nonzero of out[i], a[i]
+hipError_t launch_status_or(const int* a, int* out, int n, int first, hipStream_t st);
+
 // log w = -dtau S_Bose + 2 logdet for every chain.
 hipError_t launch_log_weight(const double* x, const double* logdet, int nch, int N, int Ltau,
                              double lam, double omega0, double dtau, double c_kin,

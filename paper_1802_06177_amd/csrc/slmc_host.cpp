@@ -168,6 +168,7 @@ struct ModelConsts {
   uint16_t* Elo = nullptr;    // [Np][Np] bf16 of E64 - fp32(E64)
   int8_t* Eq = nullptr;       // [Np][Npk/64][5][64] int8 slices of the row-scaled E
   double* Esc = nullptr;      // [Np] row scales 2^{ea_i}
+  double* Einv = nullptr;     // [Np][Np] e^{+dtau K} (G propagation between slices)
 };
 
 // E = diag(Esc) sum_p A_p 2^{-7(p+1)}: per row a power of two above twice the row maximum,
@@ -204,6 +205,7 @@ struct HostConsts {
   std::vector<uint16_t> b2, b3, lo;
   std::vector<int8_t> eq;
   std::vector<double> esc;
+  std::vector<double> Einv;
 };
 
 void build_consts(const slmc_model* m, HostConsts& h) {
@@ -232,13 +234,20 @@ void build_consts(const slmc_model* m, HostConsts& h) {
     }
   }
   split_e_int8(Ep, Np, h.eq, h.esc);
+  slmc_model mi = *m;
+  mi.dtau = -m->dtau;
+  host_expk(&mi, E);
+  h.Einv.assign((size_t)Np * Np, 0.0);
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j)
+      h.Einv[(size_t)i * Np + j] = (i < N && j < N) ? E[(size_t)i * N + j] : (i == j ? 1.0 : 0.0);
 }
 
 // Bytes of the device copy of a model's constants (each piece 256-byte aligned).
 size_t consts_bytes(const HostConsts& h) {
   return align256(h.E64.size() * 8) + align256(h.E32.size() * 4) + align256(h.b2.size() * 2) +
          align256(h.b3.size() * 2) + align256(h.lo.size() * 2) + align256(h.eq.size()) +
-         align256(h.esc.size() * 8);
+         align256(h.esc.size() * 8) + align256(h.Einv.size() * 8);
 }
 
 // Points mc's pieces into dev (consts_bytes(h) bytes) and copies them there on st; the
@@ -258,7 +267,8 @@ int upload_consts(const HostConsts& h, char* dev, ModelConsts& mc, hipStream_t s
   mc.Elo = (uint16_t*)put(h.lo.data(), h.lo.size() * 2);
   mc.Eq = (int8_t*)put(h.eq.data(), h.eq.size());
   mc.Esc = (double*)put(h.esc.data(), h.esc.size() * 8);
-  if (!mc.E64 || !mc.E32 || !mc.Ebf2 || !mc.Ebf3 || !mc.Elo || !mc.Eq || !mc.Esc)
+  mc.Einv = (double*)put(h.Einv.data(), h.Einv.size() * 8);
+  if (!mc.E64 || !mc.E32 || !mc.Ebf2 || !mc.Ebf3 || !mc.Elo || !mc.Eq || !mc.Esc || !mc.Einv)
     return fail(SLMC_E_DEVICE, "copy of the model constants failed");
   return SLMC_OK;
 }
@@ -635,6 +645,15 @@ EffParams eff_params(const slmc_eff* e) {
   return EffParams{e->Jk, e->J2, e->Jp, e->Jp6, e->a, e->Js[0], e->Js[1], e->Js[2], e->Jt, e->delta};
 }
 
+size_t slices_bytes(const slmc_model* m, int nb) {
+  const int N = m->Lx * m->Ly;
+  const size_t nn = (size_t)N * N;
+  size_t b = group_bytes(m, nb);
+  b += align256((size_t)nb * N * m->Ltau * 8) + 3 * align256((size_t)nb * nn * 8);
+  b += 3 * align256((size_t)nb * 8);
+  return b;
+}
+
 size_t accept_bytes(const slmc_model* m, int nch) {
   size_t b = group_bytes(m, nch);
   b += 5 * align256((size_t)nch * sizeof(double)) + 2 * align256((size_t)nch * sizeof(int));
@@ -840,6 +859,85 @@ int slmc_eff_propose(const slmc_model* model, const slmc_eff* eff, int32_t n_cha
   if (n_clusters > 0)
     HIPCHK(launch_wolff(x, n_chains, model->Lx, model->Ly, model->Ltau, eff->Js, n_clusters, seed,
                         proposal_idx, 1, cluster_sizes, st));
+  return SLMC_OK;
+}
+
+size_t slmc_slices_workspace_bytes(const slmc_model* model, int32_t n_items,
+                                   const slmc_options* opt) {
+  (void)opt;
+  if (!model || n_items < 1 || check_model(model)) return 0;
+  return slices_bytes(model, n_items);
+}
+
+int slmc_green_slices(const slmc_model* model, const slmc_options* opt, int32_t n_items,
+                      const double* x, int32_t n_wrap, double* G_all, double* s_nn, double* m_st,
+                      int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  rc = check_opt(opt);
+  if (rc) return rc;
+  if (!x || !s_nn || !m_st || !status) return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_items < 1) return fail(SLMC_E_ARG, "n_items must be >= 1");
+  if (n_wrap < 1 || n_wrap > model->Ltau) return fail(SLMC_E_ARG, "n_wrap must be in [1, Ltau]");
+  const size_t need = slices_bytes(model, n_items);
+  if (!ws || ws_bytes < need) return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  ModelConsts* mc = nullptr;
+  rc = get_consts(model, &mc);
+  if (rc) return rc;
+  const int N = model->Lx * model->Ly, Lt = model->Ltau;
+  const int64_t nn = (int64_t)N * N, xn = (int64_t)N * Lt;
+  Arena a(ws);
+  GroupBufs w;
+  carve(a, n_items, roundup16(N), (Lt + model->n_s - 1) / model->n_s, w);
+  double* xr = a.take<double>((size_t)n_items * xn);
+  double* Gp[2] = {a.take<double>((size_t)n_items * nn), a.take<double>((size_t)n_items * nn)};
+  double* T = a.take<double>((size_t)n_items * nn);
+  double* ld = a.take<double>(n_items);
+  int8_t* sg = (int8_t*)a.take<int>(n_items);
+  int32_t* sta = a.take<int32_t>(n_items);
+  hipStream_t st = (hipStream_t)stream;
+  Group grp{0, {}};
+  for (int b = 0; b < n_items; ++b) grp.items.push_back(b);
+  // G after slice l: stored in G_all[b][l] when given, else in two ping-pong buffers
+  auto gslot = [&](int l, int pp) -> std::pair<double*, int64_t> {
+    if (G_all) return {G_all + (int64_t)l * nn, (int64_t)Lt * nn};
+    return {Gp[pp], nn};
+  };
+  const double ldl = model->dtau * model->lambda;
+  const int nA = (Lt + n_wrap - 1) / n_wrap;
+  int pp = 0;
+  for (int j = 0; j < nA; ++j) {
+    // anchor: the slice before block j, evaluated on the field rotated to start after it
+    const int r = j * n_wrap, anchor = (r + Lt - 1) % Lt;
+    const double* xe = x;
+    if (r != 0) {
+      HIPCHK(launch_rotate_fields(x, xr, n_items, N, Lt, r, st));
+      xe = xr;
+    }
+    // the evaluation writes G contiguously ([b][N][N]); a strided copy files it in G_all
+    std::pair<double*, int64_t> ga{Gp[pp], nn};
+    slmc_batch bt{n_items, nullptr, nullptr, nullptr};
+    rc = run_group(model, opt, grp, &bt, xe, ld, sg, ga.first, sta, w, st, mc);
+    if (rc) return rc;
+    HIPCHK(launch_status_or(sta, status, n_items, j == 0, st));
+    if (G_all) {
+      HIPCHK(launch_copy_items(ga.first, nn, G_all + (int64_t)anchor * nn, (int64_t)Lt * nn, nn,
+                               n_items, st));
+    }
+    HIPCHK(launch_cdw(ga.first, ga.second, n_items, model->Lx, N, s_nn + anchor, m_st + anchor, Lt, st));
+    // propagate through the block: slices r .. min(r + n_wrap, Lt) - 2
+    auto prev = ga;
+    for (int l = r; l <= std::min(r + n_wrap, Lt) - 2; ++l) {
+      pp ^= 1;
+      auto gn = gslot(l, pp);
+      HIPCHK(launch_propagate(prev.first, prev.second, gn.first, gn.second, T, mc->E64, mc->Einv,
+                              mc->Np, x, l, ldl, n_items, N, Lt, st));
+      HIPCHK(launch_cdw(gn.first, gn.second, n_items, model->Lx, N, s_nn + l, m_st + l, Lt, st));
+      prev = gn;
+    }
+    pp ^= 1;
+  }
   return SLMC_OK;
 }
 

@@ -1,0 +1,122 @@
+"""GPU parity of G after every time slice (SM Eq. S3) and of the CDW estimators (main
+text, "Results"), through the C ABI, against the oracle (each slice by definition: the
+stabilized chain of the rotated field).
+
+Bars.  Evaluated slices: the path's bar (FP64 1e-9, int8x5 1e-6 on max|dG|).  A slice
+reached by k propagation steps G -> B G B^{-1} from an evaluated one: an error d in G
+becomes at most ||B||_inf ||B^{-1}||_1 d in max-abs norm, so the bar grows as
+bar_k = kappa_k (bar_{k-1} + 1e-12) with kappa_k computed from the field (1e-12 covers the
+rounding of the two products).  Estimators: s_nn = N m^2 + (2/N)(tr G - q) moves by at most
+dG (4 N |m| + 2 + 4 N max|G|) and m_st by 2 dG for a max-abs error dG in G."""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import gen, workload_item, workload_models
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1802_06177_amd as slmc  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _md(Lx, Ly, Ltau, n_s, lam=1.5, mu=0.0):
+    return dict(Lx=Lx, Ly=Ly, Ltau=Ltau, n_s=n_s, t=1.0, mu=mu, dtau=0.1, lam=lam, omega0=1.0, c_kin=0.5)
+
+
+def _bars(md, x, n_wrap, g_bar):
+    """Per-slice max|dG| bar (evaluated slices g_bar, propagated ones grown by kappa)."""
+    K = oracle.hopping_matrix(md["Lx"], md["Ly"], md["t"], md["mu"])
+    E, Einv = oracle.expk(K, md["dtau"]), oracle.expk(K, -md["dtau"])
+    Lt = md["Ltau"]
+    bars = np.empty(Lt)
+    for l in range(Lt):
+        j = l // n_wrap
+        k = l - j * n_wrap + 1          # propagation steps from the anchor j n_wrap - 1
+        if l == Lt - 1 or k == n_wrap:
+            bars[l] = g_bar
+            continue
+        b = g_bar
+        for s in range(j * n_wrap, l + 1):
+            v = np.exp(-md["dtau"] * md["lam"] * x[s])
+            kap = np.max(np.sum(np.abs(E * v[None, :]), axis=1)) * \
+                np.max(np.sum(np.abs(Einv / v[:, None]), axis=0))
+            b = kap * (b + 1e-12)
+        bars[l] = b
+    return bars
+
+
+def _check(md, xs, n_wrap, prec, g_bar, slices=None, resid=0):
+    print("case: slices %dx%d Ltau=%d n_s=%d n_wrap=%d prec=%s items=%d" %
+          (md["Lx"], md["Ly"], md["Ltau"], md["n_s"], n_wrap, prec, len(xs)), flush=True)
+    m = slmc.model_from_dict(md)
+    x = torch.tensor(np.stack(xs), dtype=torch.float64, device=DEV)
+    opt = slmc.options(prec, resid)
+    s_nn, m_st, st, G = slmc.green_slices(m, x, n_wrap, opt, want_g=True)
+    s2, m2, _, _ = slmc.green_slices(m, x, n_wrap, opt, want_g=False)
+    torch.cuda.synchronize()
+    s_nn, m_st, st, G = s_nn.cpu().numpy(), m_st.cpu().numpy(), st.cpu().numpy(), G.cpu().numpy()
+    assert np.array_equal(s_nn, s2.cpu().numpy()) and np.array_equal(m_st, m2.cpu().numpy())
+    assert np.all(st == 0)
+    E = oracle.expk(oracle.hopping_matrix(md["Lx"], md["Ly"], md["t"], md["mu"]), md["dtau"])
+    N = md["Lx"] * md["Ly"]
+    worst = 0.0
+    for b, xb in enumerate(xs):
+        sl = list(range(md["Ltau"])) if slices is None else slices
+        ref = oracle.green_slices(E, xb, md["dtau"], md["lam"], md["n_s"], slices=sl)
+        bars = _bars(md, xb, n_wrap, g_bar)
+        for k, l in enumerate(sl):
+            dg = float(np.max(np.abs(G[b, l] - ref[k])))
+            worst = max(worst, dg / bars[l])
+            assert dg <= bars[l], (b, l, dg, bars[l])
+            so, mo = oracle.cdw_estimators(ref[k], md["Lx"], md["Ly"])
+            es = bars[l] * (4 * N * abs(mo) + 2 + 4 * N * np.max(np.abs(ref[k])))
+            assert abs(s_nn[b, l] - so) <= es, (b, l, s_nn[b, l], so, es)
+            assert abs(m_st[b, l] - mo) <= 2 * bars[l] + 1e-15
+    print("  worst max|dG| / bar = %.3e" % worst, flush=True)
+    return G, s_nn, m_st
+
+
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s", [(4, 4, 20, 5), (6, 4, 12, 4), (2, 3, 10, 3)])
+def test_every_slice_evaluated_matches_oracle(Lx, Ly, Ltau, n_s):
+    md = _md(Lx, Ly, Ltau, n_s, mu=0.1)
+    xs = [gen(401, Lx * 100 + Ltau + k).normal(0.0, 1.0, size=(Ltau, Lx * Ly)) for k in range(3)]
+    _check(md, xs, 1, "fp64", 1e-9)
+
+
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s,n_wrap", [(4, 4, 20, 5, 5), (8, 8, 40, 10, 10),
+                                                    (6, 6, 18, 6, 4), (4, 4, 16, 4, 16)])
+def test_propagated_slices_match_oracle(Lx, Ly, Ltau, n_s, n_wrap):
+    md = _md(Lx, Ly, Ltau, n_s)
+    xs = [gen(402, Lx * 100 + Ltau + k).normal(0.0, 1.0, size=(Ltau, Lx * Ly)) for k in range(2)]
+    _check(md, xs, n_wrap, "fp64", 1e-9)
+
+
+def test_int8x5_slices_match_oracle():
+    md = _md(8, 8, 40, 10)
+    xs = [gen(403, k).normal(0.0, 1.0, size=(40, 64)) for k in range(2)]
+    _check(md, xs, 5, "int8x5", 1e-6, resid=1)
+
+
+def test_full_size_16x16_sampled_slices():
+    md = workload_models("W4", 1)[0]
+    xs = [workload_item("W4", b, 1)[1] for b in (0, 1)]
+    # anchors (7, 15, 159) and slices 1, 4 and 6 propagations after an anchor
+    _check(md, xs, 8, "fp64", 1e-9, slices=[0, 3, 7, 13, 15, 100, 159])
+
+
+def test_estimators_at_half_filling_without_field():
+    # free fermions: every slice is the closed-form G; m_st = 0 and s_nn is the momentum sum
+    import pins
+    md = _md(4, 4, 20, 5)
+    x = torch.zeros((1, 20, 16), dtype=torch.float64, device=DEV)
+    s_nn, m_st, st, G = slmc.green_slices(slmc.model_from_dict(md), x, 5, want_g=True)
+    torch.cuda.synchronize()
+    G0 = pins.free_green(4, 4, 1.0, 0.0, 2.0)
+    assert np.max(np.abs(G.cpu().numpy()[0] - G0[None])) < 1e-9
+    assert np.max(np.abs(m_st.cpu().numpy())) < 1e-12
+    so, _ = oracle.cdw_estimators(G0, 4, 4)
+    assert np.max(np.abs(s_nn.cpu().numpy() - so)) < 1e-9
