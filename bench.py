@@ -20,7 +20,8 @@ the slice-product kernel in the overlapped run and with every kernel run alone, 
 effective-model sweeps alone, and the other workloads: 4x4 Ltau 40 (64 fields), 8x8
 Ltau 80 (256 fields in one call, FP64 against FP32 matrix cores and the int8 split),
 the 12x12 Ltau 120 proposal step of 64 chains (sweep + FP64 cumulative accept), the
-modified Wolff cluster moves on the same shape, the uneven packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
+modified Wolff cluster moves on the same shape, G after every time slice with the CDW
+estimators on the 16x16 workload, the uneven packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
 The cpu_baseline leg times the FP64 CPU oracle on a bounded sample of the 16x16 fields
 (one BLAS thread) and runs it over the GPU outputs of the other legs (every field of the
 4x4, 8x8 and 16x16 legs, 8 items of each size class of the uneven batch, 8 of the 64
@@ -281,6 +282,31 @@ def wolff_12x12(slmc, torch, np, chains=64, n_clusters=4, reps=5):
     return out, first
 
 
+def slices_16x16(slmc, torch, np, items=32, reps=2):
+    """G after every time slice (SM Eq. S3) and the CDW estimators on the 16x16, Ltau = 160
+    workload (FP64 evaluations every n_wrap slices, FP64 propagation between): slices per
+    second at n_wrap = 8 and 40, and the n_wrap = 8 outputs of two fields on sampled slices
+    for the oracle check."""
+    from synth import workload_item, workload_models
+    md = workload_models("W4", 1)[0]
+    m = slmc.model_from_dict(md)
+    xs = [workload_item("W4", b, 1)[1] for b in range(items)]
+    x = torch.tensor(np.stack(xs), dtype=torch.float64, device="cuda:0")
+    opt = slmc.options("fp64")
+    out = {"items": items, "Ltau": md["Ltau"]}
+    for nw in (8, 40):
+        t = _timed(torch, lambda: slmc.green_slices(m, x, nw, opt), reps)
+        out["n_wrap_%d" % nw] = {"ms_per_call": round(t * 1e3, 3),
+                                 "slices_per_s": round(items * md["Ltau"] / t, 1),
+                                 "evaluations_per_call": items * ((md["Ltau"] + nw - 1) // nw)}
+    s_nn, m_st, st, G = slmc.green_slices(m, x[:2].contiguous(), 8, opt, want_g=True)
+    sl = [0, 3, 6, 7, 100, 159]
+    first = dict(md=md, x=[xs[0], xs[1]], slices=sl, G=G.cpu().numpy()[:, sl], s_nn=s_nn.cpu().numpy()[:, sl],
+                 m_st=m_st.cpu().numpy()[:, sl], status=st.cpu().numpy())
+    out["cdw_s_nn_mean"] = round(float(s_nn.mean().item()), 6)
+    return out, first
+
+
 def accept_12x12(slmc, torch, np, steps=10):
     """64 chains of the 12x12, Ltau = 120 shape (n_s = 10, lam = 1.5) with the seeded
     effective model (couplings out to the third neighbour): one proposal = copy, one
@@ -488,6 +514,8 @@ def main():
         _progress("12x12 accept leg done")
         legs["wolff_12x12_ltau120"], checks["wolff_12x12_ltau120"] = wolff_12x12(slmc, torch, np)
         _progress("12x12 Wolff leg done")
+        legs["slices_16x16_ltau160"], checks["slices_16x16_ltau160"] = slices_16x16(slmc, torch, np)
+        _progress("16x16 G-slices leg done")
         legs["uneven_packed"] = {}
         checks["uneven_packed"] = []
         for prec in (args.precision, "fp64"):
@@ -607,6 +635,14 @@ def _host_info():
 _E_CACHE = {}
 
 
+def oracle_E(d):
+    import oracle
+    key = (d["Lx"], d["Ly"], d["t"], d["mu"], d["dtau"])
+    if key not in _E_CACHE:
+        _E_CACHE[key] = oracle.expk(oracle.hopping_matrix(d["Lx"], d["Ly"], d["t"], d["mu"]), d["dtau"])
+    return _E_CACHE[key]
+
+
 def _oracle_fermion(task):
     """One oracle evaluation against one GPU result: (label, rel log-det error, per-site
     error, max |dG|, sign equal, status ok)."""
@@ -654,7 +690,8 @@ def _oracle_checks(checks):
     another in this process (progress on stderr every 50)."""
     import numpy as np
     ferm = [(name, t) for name, lst in checks.items()
-            if name not in ("accept_12x12_ltau120", "wolff_12x12_ltau120") for t in lst]
+            if name not in ("accept_12x12_ltau120", "wolff_12x12_ltau120", "slices_16x16_ltau160")
+            for t in lst]
     acc = checks.get("accept_12x12_ltau120")
     acc_tasks = []
     if acc:
@@ -710,7 +747,22 @@ def _oracle_checks(checks):
             "sweep_near_ties": int(a[:, 4].sum()), "max_rel_logw_current": float(a[:, 5].max())}
     if wres:
         summary["wolff_12x12_ltau120"] = wres
-    return summary, len(ferm) + len(acc_tasks) + (wres["chains"] if wres else 0)
+    sc = checks.get("slices_16x16_ltau160")
+    if sc:
+        d = sc["md"]
+        E = oracle_E(d)
+        from oracle.measure import green_slices, cdw_estimators
+        dg, ds = 0.0, 0.0
+        for b, xb in enumerate(sc["x"]):
+            ref = green_slices(E, xb, d["dtau"], d["lam"], d["n_s"], slices=sc["slices"])
+            for k in range(len(sc["slices"])):
+                dg = max(dg, float(np.max(np.abs(sc["G"][b, k] - ref[k]))))
+                ds = max(ds, abs(sc["s_nn"][b, k] - cdw_estimators(ref[k], d["Lx"], d["Ly"])[0]))
+        summary["slices_16x16_ltau160"] = {"fields": len(sc["x"]), "slices": sc["slices"], "n_wrap": 8,
+                                           "max_abs_G": dg, "max_abs_s_nn": ds,
+                                           "status_ok": bool(np.all(sc["status"] == 0))}
+    return summary, len(ferm) + len(acc_tasks) + (wres["chains"] if wres else 0) + \
+        (2 * len(sc["slices"]) if sc else 0)
 
 
 if __name__ == "__main__":
