@@ -21,7 +21,9 @@ effective-model sweeps alone, and the other workloads: 4x4 Ltau 40 (64 fields), 
 Ltau 80 (256 fields in one call, FP64 against FP32 matrix cores and the int8 split),
 the 12x12 Ltau 120 proposal step of 64 chains (sweep + FP64 cumulative accept), the
 modified Wolff cluster moves on the same shape, G after every time slice with the CDW
-estimators on the 16x16 workload, the uneven packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
+estimators on the 16x16 workload, the paper's DQMC comparison updates (local sweep with
+Sherman-Morrison updates, block updates) on the 8x8 and 16x16 workloads, the uneven
+packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
 The cpu_baseline leg times the FP64 CPU oracle on a bounded sample of the 16x16 fields
 (one BLAS thread) and runs it over the GPU outputs of the other legs (every field of the
 4x4, 8x8 and 16x16 legs, 8 items of each size class of the uneven batch, 8 of the 64
@@ -307,6 +309,40 @@ def slices_16x16(slmc, torch, np, items=32, reps=2):
     return out, first
 
 
+def dqmc_rates(slmc, torch, np, wl, chains, n_rec, reps=1):
+    """The paper's comparison method on the GPU (SM Sec. I): one DQMC local sweep of every
+    chain (N Ltau sequential local updates per chain, each with its O(N^2) Sherman-Morrison
+    update; G re-evaluated every n_rec slices) and 4 column block updates, FP64.  Sweep time,
+    site updates per second and acceptance, from HIP events."""
+    from synth import workload_item, workload_models
+    md = workload_models(wl, 1 if wl == "W4" else 0)[0]
+    m = slmc.model_from_dict(md)
+    N, Lt = md["Lx"] * md["Ly"], md["Ltau"]
+    xs = [workload_item(wl, b % 128, 1 if wl == "W4" else 0)[1] for b in range(chains)]
+    x = torch.tensor(np.stack(xs), dtype=torch.float64, device="cuda:0")
+    opt = slmc.options("fp64")
+    k = [0]
+    accs = []
+
+    def sweep():
+        k[0] += 1
+        a, _, _ = slmc.dqmc_sweep(m, x, 0.8, n_rec, 2018, k[0], opt)
+        accs.append(a)
+
+    t = _timed(torch, sweep, reps)
+    acc = float(torch.stack(accs[-reps:]).double().mean().item()) / (N * Lt)
+    logw, _ = slmc.log_weight(m, x, opt)
+
+    def block():
+        k[0] += 1
+        slmc.dqmc_block(m, x, logw, 4, 2018, k[0], opt)
+
+    tb = _timed(torch, block, reps)
+    return {"chains": chains, "N": N, "Ltau": Lt, "n_rec": n_rec, "sweep_ms": round(t * 1e3, 3),
+            "site_updates_per_s": round(chains * N * Lt / t, 1), "local_accept_rate": round(acc, 4),
+            "block_updates": 4, "block_ms": round(tb * 1e3, 3)}
+
+
 def accept_12x12(slmc, torch, np, steps=10):
     """64 chains of the 12x12, Ltau = 120 shape (n_s = 10, lam = 1.5) with the seeded
     effective model (couplings out to the third neighbour): one proposal = copy, one
@@ -516,6 +552,9 @@ def main():
         _progress("12x12 Wolff leg done")
         legs["slices_16x16_ltau160"], checks["slices_16x16_ltau160"] = slices_16x16(slmc, torch, np)
         _progress("16x16 G-slices leg done")
+        legs["dqmc"] = {"8x8_ltau80": dqmc_rates(slmc, torch, np, "W2", 64, 10),
+                        "16x16_ltau160": dqmc_rates(slmc, torch, np, "W4", B, 8)}
+        _progress("DQMC comparison leg done")
         legs["uneven_packed"] = {}
         checks["uneven_packed"] = []
         for prec in (args.precision, "fp64"):

@@ -214,6 +214,44 @@ int slmc_green_slices(const slmc_model* model, const slmc_options* opt, int32_t 
                       const double* x, int32_t n_wrap, double* G_all, double* s_nn, double* m_st,
                       int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
+/* Device workspace, in bytes, of slmc_dqmc_sweep and slmc_dqmc_block. */
+size_t slmc_dqmc_workspace_bytes(const slmc_model* model, int32_t n_chains,
+                                 const slmc_options* opt);
+
+/* One DQMC local sweep of every chain, in place: the comparison method of the paper
+ * (SM Sec. I, Eqs. S4-S6).  Slices l = 0 .. Ltau-1 in order, in each the sites i = 0 .. N-1
+ * in order: move x[l][i] -> x + delta (2 u1 - 1), Delta = expm1(-dtau lambda dx), spin
+ * ratio R = 1 + (1 - G_ii) Delta with G the Green's function after slice l-1 (the factor
+ * order B_l = e^{-dtau K} diag(v_l) puts the change on the right of B_l), accept iff
+ * log u2 < 2 log|R| - dtau dS_Bose; on accept G <- G - (I - G) e_i (Delta / R) e_i^T G
+ * (Sherman-Morrison).  G after slice l-1 is evaluated by the stabilized chain
+ * (opt->precision) of the rotated field at every slice l with l % n_rec == 0 and
+ * propagated from the previous slice (FP64 products) otherwise.
+ *   Random numbers: Philox4x32-10, key (seed lo, seed hi), counter (i + N l, 0xC0000000,
+ *   sweep_idx mod 2^32, chain), words 0 (u1) and 1 (u2).
+ *   x device [n_chains][Ltau][N] in/out; n_accepted device [n_chains] int64 (set);
+ *   G_out device [n_chains][N][N] or NULL: the equal-time G of the final fields, evaluated;
+ *   status device [n_chains] int32 (first non-OK status of the evaluations); ws of
+ *   slmc_dqmc_workspace_bytes().  Each site update reads and writes all of G: O(N^2) per
+ *   site, N^3 Ltau per sweep. */
+int slmc_dqmc_sweep(const slmc_model* model, const slmc_options* opt, int32_t n_chains, double* x,
+                    double delta, int32_t n_rec, uint64_t seed, uint64_t sweep_idx,
+                    int64_t* n_accepted, double* G_out, int32_t* status, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* n_updates DQMC block updates of every chain (SM Sec. I, last paragraph; main text): the
+ * column of one site is reflected, x[.][s] -> -x[.][s] (the reflection about the mean
+ * displacement in the shifted frame), and accepted iff log u < log w(x') - log w(x), the
+ * full weight ratio (log w = -dtau S_Bose + 2 logdet, logdet evaluated with
+ * opt->precision).  Update u: site floor(r N / 2^32), r = Philox word 0 at counter
+ * (0xFFFFFFFB, 0xFFFFFFFC, c, chain), u = word 0 at (0xFFFFFFFF, 0xFFFFFFFC, c, chain),
+ * c = (sweep_idx n_updates + u) mod 2^32.  x in/out; logw device [n_chains] in/out (the
+ * cached log weight of x, replaced on accept); n_accepted device [n_chains] int64 (set);
+ * status as slmc_dqmc_sweep; ws of slmc_dqmc_workspace_bytes(). */
+int slmc_dqmc_block(const slmc_model* model, const slmc_options* opt, int32_t n_chains, double* x,
+                    double* logw, int32_t n_updates, uint64_t seed, uint64_t sweep_idx,
+                    int64_t* n_accepted, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* n_clusters modified Wolff cluster moves of every chain, in place (SM Sec. IV, Eq. S8):
  * a cluster grows in the spatial plane, each site carrying its whole time column; bond
  * (i, t) joins site i to its neighbour at offset t (t = 0..5: (1,0), (0,1) with Js[0];

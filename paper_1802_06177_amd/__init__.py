@@ -20,7 +20,8 @@ from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLA
 
 __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
            "eff_energy", "eff_sweep", "eff_wolff", "eff_propose", "log_weight", "cumulative_accept",
-           "green_noalloc", "green_slices", "cache_clear", "SlmcError", "version"]
+           "green_noalloc", "green_slices", "dqmc_sweep", "dqmc_block", "cache_clear", "SlmcError",
+           "version"]
 
 PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6,
               "fp32plain": SLMC_FP32_PLAIN, "int8x5": SLMC_INT8X5}
@@ -309,6 +310,48 @@ def green_slices(m, x, n_wrap, opt=None, want_g=False, stream=None, ws=None):
                                    None if G is None else vp(G.data_ptr()), vp(s_nn.data_ptr()),
                                    vp(m_st.data_ptr()), vp(st.data_ptr()), wsp, wsn, _stream(stream)))
     return s_nn, m_st, st, G
+
+
+def dqmc_sweep(m, x, delta, n_rec, seed, sweep_idx, opt=None, want_g=False, stream=None, ws=None):
+    """One DQMC local sweep of every chain of x [chains, Ltau, N], in place (SM Sec. I).
+    Returns (accepted moves [chains] int64, status [chains] int32, G of the final fields
+    [chains, N, N] or None)."""
+    torch = _torch()
+    n = _chains(m, x)
+    opt = opt or options()
+    L = _abi.lib()
+    N = m.Lx * m.Ly
+    need = L.slmc_dqmc_workspace_bytes(C.byref(m), n, C.byref(opt))
+    wsp, wsn = _ws_args(ws if ws is not None else _workspace(need, x.device, stream))
+    nacc = torch.empty(n, dtype=torch.int64, device=x.device)
+    st = torch.empty(n, dtype=torch.int32, device=x.device)
+    G = torch.empty((n, N, N), dtype=torch.float64, device=x.device) if want_g else None
+    vp = C.c_void_p
+    _abi.check(L.slmc_dqmc_sweep(C.byref(m), C.byref(opt), n, _dev_f64(x, "x"), float(delta), int(n_rec),
+                                 C.c_uint64(seed), C.c_uint64(sweep_idx), vp(nacc.data_ptr()),
+                                 None if G is None else vp(G.data_ptr()), vp(st.data_ptr()), wsp, wsn,
+                                 _stream(stream)))
+    return nacc, st, G
+
+
+def dqmc_block(m, x, logw, n_updates, seed, sweep_idx, opt=None, stream=None, ws=None):
+    """n_updates column-reflection block updates of every chain (SM Sec. I), in place;
+    logw [chains] (cached log weight) is updated on accept.  Returns (accepted [chains]
+    int64, status [chains] int32)."""
+    torch = _torch()
+    n = _chains(m, x)
+    _shape(logw, (n,), "logw")
+    opt = opt or options()
+    L = _abi.lib()
+    need = L.slmc_dqmc_workspace_bytes(C.byref(m), n, C.byref(opt))
+    wsp, wsn = _ws_args(ws if ws is not None else _workspace(need, x.device, stream))
+    nacc = torch.empty(n, dtype=torch.int64, device=x.device)
+    st = torch.empty(n, dtype=torch.int32, device=x.device)
+    vp = C.c_void_p
+    _abi.check(L.slmc_dqmc_block(C.byref(m), C.byref(opt), n, _dev_f64(x, "x"), _dev_f64(logw, "logw"),
+                                 int(n_updates), C.c_uint64(seed), C.c_uint64(sweep_idx),
+                                 vp(nacc.data_ptr()), vp(st.data_ptr()), wsp, wsn, _stream(stream)))
+    return nacc, st
 
 
 def eff_wolff(m, eff, x, n_clusters, seed, proposal_idx, stream=None):

@@ -224,13 +224,14 @@ __global__ __launch_bounds__(256) void accept_k(double* __restrict__ x_cur,
                                                 const double* __restrict__ logw_prop,
                                                 const double* __restrict__ eeff_prop,
                                                 int64_t nelem, uint32_t k0, uint32_t k1,
-                                                uint32_t prop, uint8_t* __restrict__ accepted,
+                                                uint32_t tag, uint32_t prop,
+                                                uint8_t* __restrict__ accepted,
                                                 double* __restrict__ log_ratio) {
   __shared__ int dec;
   const int ch = blockIdx.x;
   if (threadIdx.x == 0) {
     const double lr = (logw_prop[ch] - logw_cur[ch]) + (eeff_prop[ch] - eeff_cur[ch]);
-    const U4 r = philox(U4{0xFFFFFFFFu, 0xFFFFFFFFu, prop, (uint32_t)ch}, k0, k1);
+    const U4 r = philox(U4{0xFFFFFFFFu, tag, prop, (uint32_t)ch}, k0, k1);
     const int a = log(u01(r.x)) < lr;
     log_ratio[ch] = lr;
     accepted[ch] = (uint8_t)a;
@@ -281,10 +282,10 @@ hipError_t launch_log_weight(const double* x, const double* logdet, int nch, int
 hipError_t launch_accept(double* x_cur, const double* x_prop, double* logw_cur, double* eeff_cur,
                          const double* logw_prop, const double* eeff_prop, int nch,
                          int64_t nelem, uint64_t seed, uint64_t proposal, uint8_t* accepted,
-                         double* log_ratio, hipStream_t st) {
+                         double* log_ratio, hipStream_t st, uint32_t tag) {
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu), k1 = (uint32_t)(seed >> 32);
   hipLaunchKernelGGL(accept_k, dim3(nch), dim3(256), 0, st, x_cur, x_prop, logw_cur, eeff_cur,
-                     logw_prop, eeff_prop, nelem, k0, k1, (uint32_t)(proposal & 0xFFFFFFFFu),
+                     logw_prop, eeff_prop, nelem, k0, k1, tag, (uint32_t)(proposal & 0xFFFFFFFFu),
                      accepted, log_ratio);
   return hipGetLastError();
 }

@@ -132,10 +132,26 @@ hipError_t launch_log_weight(const double* x, const double* logdet, int nch, int
                              double lam, double omega0, double dtau, double c_kin,
                              double* logw, hipStream_t st);
 
-// Cumulative accept: log r = (logw' - logw) + (E' - E); accept iff log u < log r.
+// Cumulative accept: log r = (logw' - logw) + (E' - E); accept iff log u < log r, u from
+// Philox word 0 at counter (0xFFFFFFFF, tag, proposal mod 2^32, chain).
 hipError_t launch_accept(double* x_cur, const double* x_prop, double* logw_cur,
                          double* eeff_cur, const double* logw_prop, const double* eeff_prop,
                          int nch, int64_t nelem, uint64_t seed, uint64_t proposal,
-                         uint8_t* accepted, double* log_ratio, hipStream_t st);
+                         uint8_t* accepted, double* log_ratio, hipStream_t st,
+                         uint32_t tag = 0xFFFFFFFFu);
+
+// ---- DQMC comparison updates ----
+// The N local updates of slice l of every chain, in order, with Sherman-Morrison updates
+// of G (G after slice l-1 on entry, [nch] at stride sg); nacc[ch] += accepted moves.
+hipError_t launch_dqmc_slice(double* G, int64_t sg, double* x, int nch, int N, int Ltau, int l,
+                             double dtau, double lam, double omega0, double c_kin, double delta,
+                             uint64_t seed, uint64_t sweep, int64_t* nacc, hipStream_t st);
+// x_prop = x_cur with one column negated per chain (site from Philox at counter
+// (0xFFFFFFFB, 0xFFFFFFFC, ctr, chain))
+hipError_t launch_reflect_column(const double* x_cur, double* x_prop, int nch, int N, int Ltau,
+                                 uint64_t seed, uint32_t ctr, hipStream_t st);
+hipError_t launch_fill_i64(int64_t* dst, int n, int64_t v, hipStream_t st);
+// nacc[i] += a[i]
+hipError_t launch_add_accepted(const uint8_t* a, int64_t* nacc, int n, hipStream_t st);
 
 }  // namespace slmc
