@@ -5,7 +5,8 @@ and Philox streams.
 
 Bars (T6): a decision can differ only where |log u - log r_oracle| <= 1e-8; such near-ties
 are counted and the fixed seeds here have none, so accept counts are equal and the fields
-agree bit for bit (a move is the same sum on both sides).  The final G (evaluated by the
+agree within 1e-13 (a move x + delta (2u - 1) may be one fused multiply-add on the GPU;
+a block update is an exact negation, bit for bit).  The final G (evaluated by the
 stabilized chain) meets the FP64 bar 1e-9; cached log weights 1e-11 relative."""
 
 import numpy as np
@@ -57,7 +58,7 @@ def test_local_sweep_matches_oracle(Lx, Ly, Ltau, n_s, n_rec, delta, chains):
               (c, nacc[c], acc, len(margins), ties, min(margins)), flush=True)
         assert ties == 0
         assert int(nacc[c]) == acc and 0 < acc < Ltau * Lx * Ly
-        assert np.array_equal(xg[c], xo)
+        assert np.max(np.abs(xg[c] - xo)) <= 1e-13
         assert np.max(np.abs(G[c] - Go)) <= 1e-9
 
 
@@ -101,5 +102,5 @@ def test_dqmc_sweep_int8x5_evaluations():
         margins = []
         acc, Go = oracle.local_sweep(E, xo, 0.1, 1.5, 1.0, 0.5, 4, 1.0, 11, 2, c, margins=margins)
         assert int(np.sum(np.asarray(margins) <= 1e-6)) == 0
-        assert int(nacc[c]) == acc and np.array_equal(xg[c], xo)
+        assert int(nacc[c]) == acc and np.max(np.abs(xg[c] - xo)) <= 1e-13
         assert np.max(np.abs(G[c] - Go)) <= 1e-6
