@@ -23,6 +23,7 @@ accept     SLMC cumulative-update acceptance                        (Eq. 6)
 wolff      modified Wolff cluster moves and the cumulative proposal (SM Sec. IV, Eq. S8)
 measure    G at every time slice and the CDW structure factor's estimators (SM Eq. S3)
 dqmc       DQMC comparison updates: local ratio, Sherman-Morrison, block update (SM Sec. I)
+train      effective-model features and their regression onto ln w (Eq. 5, SM Sec. III)
 """
 
 from .lattice import hopping_matrix, expk
@@ -34,11 +35,13 @@ from .accept import cumulative_accept
 from .wolff import cluster as wolff_cluster, wolff, propose
 from .measure import green_slices, cdw_estimators, stagger
 from .dqmc import local_ratio, sherman_morrison, local_sweep, block_updates
+from .train import features as eff_features, fit as eff_fit, TERMS
 
 __all__ = [
     "hopping_matrix", "expk", "slice_scales", "udv_chain", "recombine", "logdet_green",
     "logdet_green_direct", "bosonic_action", "log_weight", "EffModel", "eff_energy",
     "eff_local_delta", "colouring", "sweep", "philox4x32_10", "uniform01", "cumulative_accept",
     "wolff_cluster", "wolff", "propose", "green_slices", "cdw_estimators", "stagger",
-    "local_ratio", "sherman_morrison", "local_sweep", "block_updates",
+    "local_ratio", "sherman_morrison", "local_sweep", "block_updates", "eff_features", "eff_fit",
+    "TERMS",
 ]
