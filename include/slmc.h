@@ -252,6 +252,27 @@ int slmc_dqmc_block(const slmc_model* model, const slmc_options* opt, int32_t n_
                     double* logw, int32_t n_updates, uint64_t seed, uint64_t sweep_idx,
                     int64_t* n_accepted, int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
+/* Device workspace, in bytes, of slmc_eff_fit for n_configs configurations. */
+size_t slmc_fit_workspace_bytes(int32_t n_configs);
+
+/* Training of the effective model (main text Eq. 5, SM Sec. III): the multi-linear
+ * regression of ln w onto the terms of the effective model over configurations (e.g. from
+ * slmc_dqmc_sweep / slmc_log_weight).  E_eff is linear in its coefficients,
+ * E_eff(x) = sum_t J_t F_t(x), with the features in the order of slmc_eff
+ *   F = (sum (x_{l+1}-x_l)^2, sum x^2, sum f4(x; a), sum f6(x; a), sum over the bonds of
+ *        Js[0], Js[1], Js[2] of x_i x_j, sum x_{i,l} x_{i,l+1})   (t = 0..7),
+ * and the fit minimises sum_c (logw_c - E0 + sum_{t in mask} J_t F_ct)^2 by a Householder QR
+ * of the design matrix [1, -F_mask] (columns scaled to unit maximum; FP64, one workgroup,
+ * fixed reduction order).  mask: bit t selects term t; at most two of Jk, J2, Jt (bits 0,
+ * 1, 7: they are linearly dependent) and the selected columns must have full rank.
+ *   x device [n_configs][Ltau][N]; logw device [n_configs] (ln w of each configuration);
+ *   features device [n_configs][8] or NULL; coef device [9] = (E0, Jk, J2, Jp, Jp6, Js0,
+ *   Js1, Js2, Jt) (0 for terms outside the mask); a: the well position of f4, f6;
+ *   ws of slmc_fit_workspace_bytes(). */
+int slmc_eff_fit(const slmc_model* model, double a, int32_t n_configs, const double* x,
+                 const double* logw, int32_t mask, double* features, double* coef, void* ws,
+                 size_t ws_bytes, void* stream);
+
 /* n_clusters modified Wolff cluster moves of every chain, in place (SM Sec. IV, Eq. S8):
  * a cluster grows in the spatial plane, each site carrying its whole time column; bond
  * (i, t) joins site i to its neighbour at offset t (t = 0..5: (1,0), (0,1) with Js[0];

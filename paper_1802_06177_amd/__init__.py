@@ -20,8 +20,8 @@ from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLA
 
 __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
            "eff_energy", "eff_sweep", "eff_wolff", "eff_propose", "log_weight", "cumulative_accept",
-           "green_noalloc", "green_slices", "dqmc_sweep", "dqmc_block", "cache_clear", "SlmcError",
-           "version"]
+           "green_noalloc", "green_slices", "dqmc_sweep", "dqmc_block", "eff_fit", "cache_clear",
+           "SlmcError", "version"]
 
 PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6,
               "fp32plain": SLMC_FP32_PLAIN, "int8x5": SLMC_INT8X5}
@@ -352,6 +352,31 @@ def dqmc_block(m, x, logw, n_updates, seed, sweep_idx, opt=None, stream=None, ws
                                  int(n_updates), C.c_uint64(seed), C.c_uint64(sweep_idx),
                                  vp(nacc.data_ptr()), vp(st.data_ptr()), wsp, wsn, _stream(stream)))
     return nacc, st
+
+
+TERMS = ("Jk", "J2", "Jp", "Jp6", "Js0", "Js1", "Js2", "Jt")
+
+
+def eff_fit(m, x, logw, terms=("Jk", "Jp", "Jp6", "Js0", "Jt"), a=None, stream=None):
+    """Least-squares fit of ln w ~ E0 - E_eff over the configurations x [n, Ltau, N]
+    (Eq. 5): returns (coef [9] = (E0, J in TERMS order), features [n, 8]).  a defaults to
+    the well position lambda / omega0^2."""
+    torch = _torch()
+    n = _chains(m, x)
+    _shape(logw, (n,), "logw")
+    mask = 0
+    for t in terms:
+        mask |= 1 << TERMS.index(t)
+    a = m.lam / m.omega0 ** 2 if a is None else float(a)
+    L = _abi.lib()
+    ws = _workspace(L.slmc_fit_workspace_bytes(n), x.device, stream)
+    wsp, wsn = _ws_args(ws)
+    coef = torch.empty(9, dtype=torch.float64, device=x.device)
+    F = torch.empty((n, 8), dtype=torch.float64, device=x.device)
+    vp = C.c_void_p
+    _abi.check(L.slmc_eff_fit(C.byref(m), a, n, _dev_f64(x, "x"), _dev_f64(logw, "logw"), mask,
+                              vp(F.data_ptr()), vp(coef.data_ptr()), wsp, wsn, _stream(stream)))
+    return coef, F
 
 
 def eff_wolff(m, eff, x, n_clusters, seed, proposal_idx, stream=None):

@@ -17,7 +17,8 @@ EXPORTS = ("slmc_version", "slmc_last_error", "slmc_expk", "slmc_workspace_bytes
            "slmc_cumulative_accept", "slmc_log_weight", "slmc_profile", "slmc_profile_read",
            "slmc_profile_reset", "slmc_profile_name", "slmc_cache_clear", "slmc_green_noalloc",
            "slmc_eff_wolff", "slmc_eff_propose", "slmc_slices_workspace_bytes",
-           "slmc_green_slices", "slmc_dqmc_workspace_bytes", "slmc_dqmc_sweep", "slmc_dqmc_block")
+           "slmc_green_slices", "slmc_dqmc_workspace_bytes", "slmc_dqmc_sweep", "slmc_dqmc_block",
+           "slmc_fit_workspace_bytes", "slmc_eff_fit")
 SLMC_NOALLOC_WORKSPACE_BYTES = 248 << 20
 
 
@@ -84,6 +85,9 @@ def lib():
     L.slmc_dqmc_sweep.argtypes = [P(Model), P(Options), i32, vp, C.c_double, i32, u64, u64, vp, vp, vp,
                                   vp, sz, vp]
     L.slmc_dqmc_block.argtypes = [P(Model), P(Options), i32, vp, vp, i32, u64, u64, vp, vp, vp, sz, vp]
+    L.slmc_fit_workspace_bytes.restype = sz
+    L.slmc_fit_workspace_bytes.argtypes = [i32]
+    L.slmc_eff_fit.argtypes = [P(Model), C.c_double, i32, vp, vp, i32, vp, vp, vp, sz, vp]
     L.slmc_eff_wolff.argtypes = [P(Model), P(Eff), i32, vp, i32, u64, u64, vp, vp]
     L.slmc_eff_propose.argtypes = [P(Model), P(Eff), i32, vp, i32, i32, u64, u64, vp, vp, vp]
     L.slmc_green_noalloc.argtypes = [P(Model), P(Options), i32, vp, vp, vp, vp, vp, vp]

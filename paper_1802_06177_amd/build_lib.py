@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslmc.so")
 
-SOURCES = ["k_chain.hip", "k_chain_f32.hip", "k_chain_bf16.hip", "k_chain_i8.hip", "k_stab.hip", "k_final.hip", "k_eff.hip", "k_wolff.hip", "k_measure.hip", "k_dqmc.hip",
+SOURCES = ["k_chain.hip", "k_chain_f32.hip", "k_chain_bf16.hip", "k_chain_i8.hip", "k_stab.hip", "k_final.hip", "k_eff.hip", "k_wolff.hip", "k_measure.hip", "k_dqmc.hip", "k_train.hip",
            "slmc_host.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

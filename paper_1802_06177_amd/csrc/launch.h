@@ -127,6 +127,15 @@ hipError_t launch_copy_items(const double* src, int64_t ss, double* dst, int64_t
 // out[i] = a[i] (first) or the first nonzero of out[i], a[i]
 hipError_t launch_status_or(const int* a, int* out, int n, int first, hipStream_t st);
 
+// ---- effective-model regression ----
+// F[c][8]: the effective model's terms with unit coefficients for every configuration
+hipError_t launch_features(const double* x, int n, int Lx, int Ly, int Ltau, double a, double* F,
+                           hipStream_t st);
+// out[9] = (E0, J[8]): least squares of logw ~ E0 - sum_{t in mask} J_t F_t (Householder QR in
+// one workgroup; Aw [9][n] and yw [n] scratch)
+hipError_t launch_fit(const double* F, const double* logw, int n, int mask, double* Aw, double* yw,
+                      double* out, hipStream_t st);
+
 // log w = -dtau S_Bose + 2 logdet for every chain.
 hipError_t launch_log_weight(const double* x, const double* logdet, int nch, int N, int Ltau,
                              double lam, double omega0, double dtau, double c_kin,

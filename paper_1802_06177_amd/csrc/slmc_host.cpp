@@ -1091,6 +1091,38 @@ int slmc_dqmc_block(const slmc_model* model, const slmc_options* opt, int32_t n_
   return SLMC_OK;
 }
 
+size_t slmc_fit_workspace_bytes(int32_t n_configs) {
+  if (n_configs < 1) return 0;
+  return 3 * align256((size_t)n_configs * 9 * sizeof(double));
+}
+
+int slmc_eff_fit(const slmc_model* model, double a, int32_t n_configs, const double* x,
+                 const double* logw, int32_t mask, double* features, double* coef, void* ws,
+                 size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (!x || !logw || !coef) return fail(SLMC_E_ARG, "NULL pointer");
+  if (mask <= 0 || mask > 255) return fail(SLMC_E_ARG, "mask must select 1 to 8 terms (bits 0..7)");
+  int p = 1;
+  for (int t = 0; t < 8; ++t) p += (mask >> t) & 1;
+  if ((mask & 1) && (mask & 2) && (mask & 128))
+    return fail(SLMC_E_ARG, "Jk, J2 and Jt together are linearly dependent");
+  if (n_configs < p) return fail(SLMC_E_ARG, "need at least %d configurations for %d unknowns", p, p);
+  if (!std::isfinite(a)) return fail(SLMC_E_ARG, "a must be finite");
+  const size_t need = slmc_fit_workspace_bytes(n_configs);
+  if (!ws || ws_bytes < need) return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  Arena ar(ws);
+  double* F = ar.take<double>((size_t)n_configs * 9);
+  double* Aw = ar.take<double>((size_t)n_configs * 9);
+  double* yw = ar.take<double>((size_t)n_configs * 9);
+  hipStream_t st = (hipStream_t)stream;
+  double* Fo = features ? features : F;
+  HIPCHK(launch_features(x, n_configs, model->Lx, model->Ly, model->Ltau, a, Fo, st));
+  HIPCHK(launch_fit(Fo, logw, n_configs, mask, Aw, yw, coef, st));
+  return SLMC_OK;
+}
+
 size_t slmc_accept_workspace_bytes(const slmc_model* model, int32_t n_chains,
                                    const slmc_options* opt) {
   (void)opt;
