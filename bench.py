@@ -22,8 +22,8 @@ Ltau 80 (256 fields in one call, FP64 against FP32 matrix cores and the int8 spl
 the 12x12 Ltau 120 proposal step of 64 chains (sweep + FP64 cumulative accept), the
 modified Wolff cluster moves on the same shape, G after every time slice with the CDW
 estimators on the 16x16 workload, the paper's DQMC comparison updates (local sweep with
-Sherman-Morrison updates, block updates) on the 8x8 and 16x16 workloads, the uneven
-packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
+Sherman-Morrison updates, block updates) on the 8x8 and 16x16 workloads, the training of
+the effective model on DQMC configurations of the paper's L = 6, the uneven packed batch (L = 8..20) and the headline path's error at couplings 1.0 and 2.0.
 The cpu_baseline leg times the FP64 CPU oracle on a bounded sample of the 16x16 fields
 (one BLAS thread) and runs it over the GPU outputs of the other legs (every field of the
 4x4, 8x8 and 16x16 legs, 8 items of each size class of the uneven batch, 8 of the 64
@@ -343,6 +343,45 @@ def dqmc_rates(slmc, torch, np, wl, chains, n_rec, reps=1):
             "block_updates": 4, "block_ms": round(tb * 1e3, 3)}
 
 
+def train_6x6(slmc, torch, np, chains=64, burn=8, keep=16):
+    """Training the effective model on the paper's L = 6 (Eq. 5, SM Sec. III; beta = 4,
+    Ltau = 40, g = 1, Omega = 0.5, i.e. the paper's lambda = 0.5): DQMC local sweeps of 64
+    chains generate the configurations (burn-in, then one per chain per sweep), their log
+    weights, and the least-squares fit of the paper's five terms; wall time of each part
+    from HIP events, and the data for the oracle check."""
+    from synth import gen
+    md = dict(Lx=6, Ly=6, Ltau=40, n_s=10, t=1.0, mu=0.0, dtau=0.1, lam=1.0, omega0=0.5, c_kin=0.5)
+    m = slmc.model_from_dict(md)
+    x = torch.tensor(gen(6, 0).normal(size=(chains, 40, 36)), dtype=torch.float64, device="cuda:0")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    confs = []
+    ev[0].record()
+    for sw in range(burn + keep):
+        slmc.dqmc_sweep(m, x, 1.0, 10, 1802, sw)
+        if sw >= burn:
+            confs.append(x.clone())
+    ev[1].record()
+    X = torch.cat(confs)
+    lw, st = slmc.log_weight(m, X)
+    ev[2].record()
+    terms = ("Jk", "Jp", "Jp6", "Js0", "Jt")
+    coef, F = slmc.eff_fit(m, X, lw, terms=terms)
+    ev[3].record()
+    torch.cuda.synchronize()
+    c = coef.cpu().numpy()
+    Fh, lwh = F.cpu().numpy(), lw.cpu().numpy()
+    mask = np.array([t in terms for t in slmc.TERMS], dtype=float)
+    pred = c[0] - Fh @ (c[1:] * mask)
+    r2 = 1.0 - float(np.sum((lwh - pred) ** 2) / np.sum((lwh - lwh.mean()) ** 2))
+    out = {"configurations": int(X.shape[0]), "sweeps": burn + keep, "chains": chains,
+           "dqmc_ms": round(ev[0].elapsed_time(ev[1]), 2), "log_weight_ms": round(ev[1].elapsed_time(ev[2]), 3),
+           "fit_ms": round(ev[2].elapsed_time(ev[3]), 3), "status_ok": bool(torch.all(st == 0).item()),
+           "E0": float(c[0]), "J": {t: float(c[1 + k]) for k, t in enumerate(slmc.TERMS) if t in terms},
+           "r2": round(r2, 6)}
+    first = dict(md=md, X=X.cpu().numpy(), logw=lwh, F=Fh, coef=c, terms=terms)
+    return out, first
+
+
 def accept_12x12(slmc, torch, np, steps=10):
     """64 chains of the 12x12, Ltau = 120 shape (n_s = 10, lam = 1.5) with the seeded
     effective model (couplings out to the third neighbour): one proposal = copy, one
@@ -555,6 +594,8 @@ def main():
         legs["dqmc"] = {"8x8_ltau80": dqmc_rates(slmc, torch, np, "W2", 64, 10),
                         "16x16_ltau160": dqmc_rates(slmc, torch, np, "W4", B, 8)}
         _progress("DQMC comparison leg done")
+        legs["train_6x6_ltau40"], checks["train_6x6_ltau40"] = train_6x6(slmc, torch, np)
+        _progress("training leg done")
         legs["uneven_packed"] = {}
         checks["uneven_packed"] = []
         for prec in (args.precision, "fp64"):
@@ -729,7 +770,8 @@ def _oracle_checks(checks):
     another in this process (progress on stderr every 50)."""
     import numpy as np
     ferm = [(name, t) for name, lst in checks.items()
-            if name not in ("accept_12x12_ltau120", "wolff_12x12_ltau120", "slices_16x16_ltau160")
+            if name not in ("accept_12x12_ltau120", "wolff_12x12_ltau120", "slices_16x16_ltau160",
+                            "train_6x6_ltau40")
             for t in lst]
     acc = checks.get("accept_12x12_ltau120")
     acc_tasks = []
@@ -800,6 +842,19 @@ def _oracle_checks(checks):
         summary["slices_16x16_ltau160"] = {"fields": len(sc["x"]), "slices": sc["slices"], "n_wrap": 8,
                                            "max_abs_G": dg, "max_abs_s_nn": ds,
                                            "status_ok": bool(np.all(sc["status"] == 0))}
+    tc = checks.get("train_6x6_ltau40")
+    if tc:
+        from oracle.train import features as o_features, fit as o_fit, TERMS
+        d = tc["md"]
+        a = d["lam"] / d["omega0"] ** 2
+        Fo = np.array([o_features(xc, d["Lx"], d["Ly"], a) for xc in tc["X"]])
+        mask = [int(t in tc["terms"]) for t in TERMS]
+        E0, J = o_fit(Fo, tc["logw"], mask)
+        ref = np.concatenate([[E0], J])
+        summary["train_6x6_ltau40"] = {
+            "configurations": int(len(Fo)),
+            "max_rel_features": float(np.max(np.abs(tc["F"] - Fo) / np.maximum(1.0, np.abs(Fo)))),
+            "max_rel_coef": float(np.max(np.abs(tc["coef"] - ref)) / np.max(np.abs(ref)))}
     return summary, len(ferm) + len(acc_tasks) + (wres["chains"] if wres else 0) + \
         (2 * len(sc["slices"]) if sc else 0)
 
