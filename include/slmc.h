@@ -337,6 +337,26 @@ int slmc_log_weight(const slmc_model* model, const slmc_options* opt, int32_t n_
                     const double* x, double* logw, int32_t* status, void* ws, size_t ws_bytes,
                     void* stream);
 
+/* One whole SLMC step of every chain, as one call that a HIP graph can capture and replay
+ * step after step: the proposal index is read from device memory (*proposal_counter) by
+ * every kernel that draws random numbers and incremented by one at the end, so each replay
+ * of a captured step makes the next proposal.  The step is
+ *   x_prop = x_cur; the cumulative proposal of slmc_eff_propose (n_sweeps sweeps and
+ *   n_clusters Wolff cluster moves in the order of the proposal's coin); the acceptance of
+ *   slmc_cumulative_accept (Eq. 6) with its outputs accepted, log_ratio, G_prop (or NULL)
+ *   and status (or NULL).
+ * Random numbers as those calls with proposal_idx = *proposal_counter (mod 2^32).
+ *   x_cur, x_prop device [n_chains][Ltau][N]; logw_cur, eeff_cur as slmc_cumulative_accept;
+ *   proposal_counter device uint64 (read, then incremented on the stream);
+ *   n_local_accepted device [n_chains] int64 (local moves of this proposal, set);
+ *   ws of slmc_accept_workspace_bytes().  Capturable as slmc_green is (the model's
+ *   constants must have been built by an earlier call outside the capture). */
+int slmc_step(const slmc_model* model, const slmc_eff* eff, const slmc_options* opt,
+              int32_t n_chains, double* x_cur, double* x_prop, double* logw_cur, double* eeff_cur,
+              int32_t n_sweeps, int32_t n_clusters, uint64_t seed, uint64_t* proposal_counter,
+              uint8_t* accepted, double* log_ratio, double* G_prop, int32_t* status,
+              int64_t* n_local_accepted, void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel timing with HIP events recorded around each launch on its stream (off by
  * default; costs two events per launch while on).  Classes: 0 seg_chain, 1 wy_apply,
  * 2 qr, 3 vupd, 4 lu, 5 lu_solve, 6 residual, 7 eff_sweep.  slmc_profile_read waits for

@@ -20,8 +20,8 @@ from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLA
 
 __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
            "eff_energy", "eff_sweep", "eff_wolff", "eff_propose", "log_weight", "cumulative_accept",
-           "green_noalloc", "green_slices", "dqmc_sweep", "dqmc_block", "eff_fit", "cache_clear",
-           "SlmcError", "version"]
+           "green_noalloc", "green_slices", "dqmc_sweep", "dqmc_block", "eff_fit", "step",
+           "cache_clear", "SlmcError", "version"]
 
 PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6,
               "fp32plain": SLMC_FP32_PLAIN, "int8x5": SLMC_INT8X5}
@@ -377,6 +377,44 @@ def eff_fit(m, x, logw, terms=("Jk", "Jp", "Jp6", "Js0", "Jt"), a=None, stream=N
     _abi.check(L.slmc_eff_fit(C.byref(m), a, n, _dev_f64(x, "x"), _dev_f64(logw, "logw"), mask,
                               vp(F.data_ptr()), vp(coef.data_ptr()), wsp, wsn, _stream(stream)))
     return coef, F
+
+
+def step(m, eff, x_cur, x_prop, logw_cur, eeff_cur, n_sweeps, n_clusters, seed, counter, opt=None,
+         G_prop=None, out=None, stream=None, ws=None):
+    """One whole SLMC step (slmc_step): proposal from x_cur into x_prop, accept into x_cur,
+    logw_cur, eeff_cur; the proposal index is read from the device tensor counter (uint64
+    stored as int64, shape [1]) and incremented.  out: optional dict of preallocated output
+    tensors (accepted, log_ratio, status, n_local) -- pass it when capturing into a graph.
+    Returns that dict."""
+    torch = _torch()
+    n = _chains(m, x_cur, "x_cur")
+    _shape(x_prop, tuple(x_cur.shape), "x_prop")
+    _shape(logw_cur, (n,), "logw_cur")
+    _shape(eeff_cur, (n,), "eeff_cur")
+    if counter.dtype != torch.int64 or counter.numel() != 1 or not counter.is_cuda:
+        raise ValueError("counter must be a one-element int64 GPU tensor")
+    if G_prop is not None:
+        N = m.Lx * m.Ly
+        _shape(G_prop, (n, N, N), "G_prop")
+    opt = opt or options()
+    L = _abi.lib()
+    need = L.slmc_accept_workspace_bytes(C.byref(m), n, C.byref(opt))
+    wsp, wsn = _ws_args(ws if ws is not None else _workspace(need, x_cur.device, stream))
+    if out is None:
+        out = {"accepted": torch.empty(n, dtype=torch.uint8, device=x_cur.device),
+               "log_ratio": torch.empty(n, dtype=torch.float64, device=x_cur.device),
+               "status": torch.empty(n, dtype=torch.int32, device=x_cur.device),
+               "n_local": torch.empty(n, dtype=torch.int64, device=x_cur.device)}
+    vp = C.c_void_p
+    _abi.check(L.slmc_step(C.byref(m), C.byref(eff), C.byref(opt), n, _dev_f64(x_cur, "x_cur"),
+                           _dev_f64(x_prop, "x_prop"), _dev_f64(logw_cur, "logw_cur"),
+                           _dev_f64(eeff_cur, "eeff_cur"), int(n_sweeps), int(n_clusters),
+                           C.c_uint64(seed), vp(counter.data_ptr()), vp(out["accepted"].data_ptr()),
+                           vp(out["log_ratio"].data_ptr()),
+                           None if G_prop is None else _dev_f64(G_prop, "G_prop"),
+                           vp(out["status"].data_ptr()), vp(out["n_local"].data_ptr()), wsp, wsn,
+                           _stream(stream)))
+    return out
 
 
 def eff_wolff(m, eff, x, n_clusters, seed, proposal_idx, stream=None):

@@ -18,7 +18,7 @@ EXPORTS = ("slmc_version", "slmc_last_error", "slmc_expk", "slmc_workspace_bytes
            "slmc_profile_reset", "slmc_profile_name", "slmc_cache_clear", "slmc_green_noalloc",
            "slmc_eff_wolff", "slmc_eff_propose", "slmc_slices_workspace_bytes",
            "slmc_green_slices", "slmc_dqmc_workspace_bytes", "slmc_dqmc_sweep", "slmc_dqmc_block",
-           "slmc_fit_workspace_bytes", "slmc_eff_fit")
+           "slmc_fit_workspace_bytes", "slmc_eff_fit", "slmc_step")
 SLMC_NOALLOC_WORKSPACE_BYTES = 248 << 20
 
 
@@ -88,6 +88,8 @@ def lib():
     L.slmc_fit_workspace_bytes.restype = sz
     L.slmc_fit_workspace_bytes.argtypes = [i32]
     L.slmc_eff_fit.argtypes = [P(Model), C.c_double, i32, vp, vp, i32, vp, vp, vp, sz, vp]
+    L.slmc_step.argtypes = [P(Model), P(Eff), P(Options), i32, vp, vp, vp, vp, i32, i32, u64, vp, vp, vp,
+                            vp, vp, vp, vp, sz, vp]
     L.slmc_eff_wolff.argtypes = [P(Model), P(Eff), i32, vp, i32, u64, u64, vp, vp]
     L.slmc_eff_propose.argtypes = [P(Model), P(Eff), i32, vp, i32, i32, u64, u64, vp, vp, vp]
     L.slmc_green_noalloc.argtypes = [P(Model), P(Options), i32, vp, vp, vp, vp, vp, vp]

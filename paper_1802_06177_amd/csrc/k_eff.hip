@@ -129,8 +129,11 @@ __global__ __launch_bounds__(EN_THREADS) void eff_energy_k(const double* __restr
 template <bool IN_LDS>
 __global__ __launch_bounds__(1024) void eff_sweep_k(double* __restrict__ x, int N, int Lx, int Ly,
                                                     int Ltau, EffParams p, int mod, int n_sweeps,
-                                                    uint32_t k0, uint32_t k1, uint32_t prop,
+                                                    uint32_t k0, uint32_t k1, uint32_t prop_arg,
+                                                    const uint64_t* __restrict__ prop_dev,
                                                     int64_t* __restrict__ nacc) {
+  // the proposal index comes from the argument, or from device memory (replayable graphs)
+  const uint32_t prop = prop_dev ? (uint32_t)(*prop_dev & 0xFFFFFFFFu) : prop_arg;
   extern __shared__ double lds[];
   __shared__ int64_t redi[16];
   const int ch = blockIdx.x;
@@ -224,9 +227,11 @@ __global__ __launch_bounds__(256) void accept_k(double* __restrict__ x_cur,
                                                 const double* __restrict__ logw_prop,
                                                 const double* __restrict__ eeff_prop,
                                                 int64_t nelem, uint32_t k0, uint32_t k1,
-                                                uint32_t tag, uint32_t prop,
+                                                uint32_t tag, uint32_t prop_arg,
+                                                const uint64_t* __restrict__ prop_dev,
                                                 uint8_t* __restrict__ accepted,
                                                 double* __restrict__ log_ratio) {
+  const uint32_t prop = prop_dev ? (uint32_t)(*prop_dev & 0xFFFFFFFFu) : prop_arg;
   __shared__ int dec;
   const int ch = blockIdx.x;
   if (threadIdx.x == 0) {
@@ -246,7 +251,16 @@ __global__ __launch_bounds__(256) void accept_k(double* __restrict__ x_cur,
   }
 }
 
+__global__ void incr_u64_k(uint64_t* c) {
+  if (threadIdx.x == 0) *c += 1;
+}
+
 }  // namespace
+
+hipError_t launch_incr_u64(uint64_t* c, hipStream_t st) {
+  hipLaunchKernelGGL(incr_u64_k, dim3(1), dim3(64), 0, st, c);
+  return hipGetLastError();
+}
 
 hipError_t launch_eff_energy(const double* x, int nch, int Lx, int Ly, int Ltau, EffParams p,
                              double* e, hipStream_t st) {
@@ -256,17 +270,17 @@ hipError_t launch_eff_energy(const double* x, int nch, int Lx, int Ly, int Ltau,
 
 hipError_t launch_eff_sweep(double* x, int nch, int Lx, int Ly, int Ltau, EffParams p, int mod,
                             int n_sweeps, uint64_t seed, uint64_t proposal, int64_t* nacc,
-                            hipStream_t st) {
+                            hipStream_t st, const uint64_t* prop_dev) {
   const int N = Lx * Ly;
   const size_t bytes = (size_t)N * Ltau * sizeof(double);
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu), k1 = (uint32_t)(seed >> 32);
   const uint32_t pr = (uint32_t)(proposal & 0xFFFFFFFFu);
   if (bytes <= 144 * 1024) {
     hipLaunchKernelGGL(eff_sweep_k<true>, dim3(nch), dim3(1024), bytes, st, x, N, Lx, Ly, Ltau, p,
-                       mod, n_sweeps, k0, k1, pr, nacc);
+                       mod, n_sweeps, k0, k1, pr, prop_dev, nacc);
   } else {
     hipLaunchKernelGGL(eff_sweep_k<false>, dim3(nch), dim3(1024), 0, st, x, N, Lx, Ly, Ltau, p,
-                       mod, n_sweeps, k0, k1, pr, nacc);
+                       mod, n_sweeps, k0, k1, pr, prop_dev, nacc);
   }
   return hipGetLastError();
 }
@@ -282,11 +296,12 @@ hipError_t launch_log_weight(const double* x, const double* logdet, int nch, int
 hipError_t launch_accept(double* x_cur, const double* x_prop, double* logw_cur, double* eeff_cur,
                          const double* logw_prop, const double* eeff_prop, int nch,
                          int64_t nelem, uint64_t seed, uint64_t proposal, uint8_t* accepted,
-                         double* log_ratio, hipStream_t st, uint32_t tag) {
+                         double* log_ratio, hipStream_t st, uint32_t tag,
+                         const uint64_t* prop_dev) {
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu), k1 = (uint32_t)(seed >> 32);
   hipLaunchKernelGGL(accept_k, dim3(nch), dim3(256), 0, st, x_cur, x_prop, logw_cur, eeff_cur,
                      logw_prop, eeff_prop, nelem, k0, k1, tag, (uint32_t)(proposal & 0xFFFFFFFFu),
-                     accepted, log_ratio);
+                     prop_dev, accepted, log_ratio);
   return hipGetLastError();
 }
 

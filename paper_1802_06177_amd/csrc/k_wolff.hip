@@ -29,8 +29,10 @@ constexpr int WF_MAXN = 448;
 __global__ __launch_bounds__(WF_THREADS) void wolff_k(double* __restrict__ x, int N, int Lx, int Ly,
                                                       int Ltau, double J0, double J1, double J2,
                                                       int n_clusters, uint32_t k0, uint32_t k1,
-                                                      uint32_t prop, int coin_mode,
-                                                      int* __restrict__ sizes) {
+                                                      uint32_t prop_arg,
+                                                      const uint64_t* __restrict__ prop_dev,
+                                                      int coin_mode, int* __restrict__ sizes) {
+  const uint32_t prop = prop_dev ? (uint32_t)(*prop_dev & 0xFFFFFFFFu) : prop_arg;
   __shared__ int nbr[6 * WF_MAXN];             // neighbour of bond 6 i + t, -1: no bond
   __shared__ unsigned char open_b[6 * WF_MAXN];
   __shared__ unsigned char in_c[WF_MAXN];
@@ -116,13 +118,13 @@ __global__ __launch_bounds__(WF_THREADS) void wolff_k(double* __restrict__ x, in
 
 hipError_t launch_wolff(double* x, int nch, int Lx, int Ly, int Ltau, const double* Js,
                         int n_clusters, uint64_t seed, uint64_t proposal, int coin_mode,
-                        int* sizes, hipStream_t st) {
+                        int* sizes, hipStream_t st, const uint64_t* prop_dev) {
   if (nch <= 0 || n_clusters <= 0) return hipSuccess;
   if (Lx * Ly > WF_MAXN) return hipErrorInvalidValue;
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu), k1 = (uint32_t)(seed >> 32);
   hipLaunchKernelGGL(wolff_k, dim3(nch), dim3(WF_THREADS), 0, st, x, Lx * Ly, Lx, Ly, Ltau, Js[0],
-                     Js[1], Js[2], n_clusters, k0, k1, (uint32_t)(proposal & 0xFFFFFFFFu), coin_mode,
-                     sizes);
+                     Js[1], Js[2], n_clusters, k0, k1, (uint32_t)(proposal & 0xFFFFFFFFu), prop_dev,
+                     coin_mode, sizes);
   return hipGetLastError();
 }
 

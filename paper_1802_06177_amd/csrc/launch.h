@@ -97,16 +97,19 @@ struct EffParams {
 hipError_t launch_eff_energy(const double* x, int nch, int Lx, int Ly, int Ltau, EffParams p,
                              double* e, hipStream_t st);
 
+// prop_dev (or nullptr): the proposal index is read from device memory instead of `proposal`
 hipError_t launch_eff_sweep(double* x, int nch, int Lx, int Ly, int Ltau, EffParams p,
                             int mod, int n_sweeps, uint64_t seed, uint64_t proposal,
-                            int64_t* nacc, hipStream_t st);
+                            int64_t* nacc, hipStream_t st, const uint64_t* prop_dev = nullptr);
+// *c += 1 (one thread)
+hipError_t launch_incr_u64(uint64_t* c, hipStream_t st);
 
 // n_clusters modified Wolff cluster moves of every chain (in place), bonds from the spatial
 // couplings Js[3]; coin_mode 0: every chain, 1: only chains whose proposal coin picks the
 // forward order, 2: only the reverse ones.  sizes (or nullptr): [nch][n_clusters].
 hipError_t launch_wolff(double* x, int nch, int Lx, int Ly, int Ltau, const double* Js,
                         int n_clusters, uint64_t seed, uint64_t proposal, int coin_mode,
-                        int* sizes, hipStream_t st);
+                        int* sizes, hipStream_t st, const uint64_t* prop_dev = nullptr);
 
 // ---- G at every slice, CDW estimators ----
 // xr[b][k] = x[b][(k + r) mod Ltau] (fields [nb][Ltau][N])
@@ -147,7 +150,7 @@ hipError_t launch_accept(double* x_cur, const double* x_prop, double* logw_cur,
                          double* eeff_cur, const double* logw_prop, const double* eeff_prop,
                          int nch, int64_t nelem, uint64_t seed, uint64_t proposal,
                          uint8_t* accepted, double* log_ratio, hipStream_t st,
-                         uint32_t tag = 0xFFFFFFFFu);
+                         uint32_t tag = 0xFFFFFFFFu, const uint64_t* prop_dev = nullptr);
 
 // ---- DQMC comparison updates ----
 // The N local updates of slice l of every chain, in order, with Sherman-Morrison updates

@@ -1203,6 +1203,74 @@ int slmc_cumulative_accept(const slmc_model* model, const slmc_eff* eff, const s
   return SLMC_OK;
 }
 
+int slmc_step(const slmc_model* model, const slmc_eff* eff, const slmc_options* opt,
+              int32_t n_chains, double* x_cur, double* x_prop, double* logw_cur, double* eeff_cur,
+              int32_t n_sweeps, int32_t n_clusters, uint64_t seed, uint64_t* proposal_counter,
+              uint8_t* accepted, double* log_ratio, double* G_prop, int32_t* status,
+              int64_t* n_local_accepted, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  rc = check_opt(opt);
+  if (rc) return rc;
+  if (!eff || !x_cur || !x_prop || !logw_cur || !eeff_cur || !proposal_counter || !accepted ||
+      !log_ratio || !n_local_accepted)
+    return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_chains < 1) return fail(SLMC_E_ARG, "n_chains must be >= 1");
+  if (n_sweeps < 0 || n_clusters < 0) return fail(SLMC_E_ARG, "negative count");
+  if (model->Ltau < 2 || model->Ltau % 2) return fail(SLMC_E_SHAPE, "Ltau must be even and >= 2");
+  if (!std::isfinite(eff->delta)) return fail(SLMC_E_ARG, "delta must be finite");
+  int mod = 1;
+  rc = colour_mod(model, eff, &mod);
+  if (rc) return rc;
+  const size_t need = accept_bytes(model, n_chains);
+  if (!ws || ws_bytes < need) return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  ModelConsts* mc = nullptr;
+  rc = get_consts(model, &mc);
+  if (rc) return rc;
+  const int N = model->Lx * model->Ly, Lt = model->Ltau;
+  const int64_t xn = (int64_t)N * Lt;
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t* pc = proposal_counter;
+  // the proposal: x' = x, then clusters (reverse coin), sweeps, clusters (forward coin)
+  HIPCHK(launch_copy_items(x_cur, xn, x_prop, xn, xn, n_chains, st));
+  if (n_clusters > 0)
+    HIPCHK(launch_wolff(x_prop, n_chains, model->Lx, model->Ly, Lt, eff->Js, n_clusters, seed, 0, 2,
+                        nullptr, st, pc));
+  {
+    ProfScope ps(7, st);
+    HIPCHK(launch_eff_sweep(x_prop, n_chains, model->Lx, model->Ly, Lt, eff_params(eff), mod, n_sweeps,
+                            seed, 0, n_local_accepted, st, pc));
+  }
+  if (n_clusters > 0)
+    HIPCHK(launch_wolff(x_prop, n_chains, model->Lx, model->Ly, Lt, eff->Js, n_clusters, seed, 0, 1,
+                        nullptr, st, pc));
+  // its weight and the acceptance (as slmc_cumulative_accept)
+  Arena a(ws);
+  GroupBufs w;
+  carve(a, n_chains, roundup16(N), (Lt + model->n_s - 1) / model->n_s, w);
+  double* ld = a.take<double>(n_chains);
+  double* eep = a.take<double>(n_chains);
+  double* lwp = a.take<double>(n_chains);
+  a.take<double>(n_chains);
+  a.take<double>(n_chains);
+  int8_t* sg = (int8_t*)a.take<int>(n_chains);
+  int32_t* stt_ws = a.take<int32_t>(n_chains);
+  int32_t* stt = status ? status : stt_ws;
+  Group grp{0, {}};
+  for (int c = 0; c < n_chains; ++c) grp.items.push_back(c);
+  slmc_batch bt{n_chains, nullptr, nullptr, nullptr};
+  rc = run_group(model, opt, grp, &bt, x_prop, ld, sg, G_prop, stt, w, st, mc);
+  if (rc) return rc;
+  HIPCHK(launch_eff_energy(x_prop, n_chains, model->Lx, model->Ly, Lt, eff_params(eff), eep, st));
+  HIPCHK(launch_log_weight(x_prop, ld, n_chains, N, Lt, model->lambda, model->omega0, model->dtau,
+                           model->c_kin, lwp, st));
+  HIPCHK(launch_accept(x_cur, x_prop, logw_cur, eeff_cur, lwp, eep, n_chains, xn, seed, 0, accepted,
+                       log_ratio, st, 0xFFFFFFFFu, pc));
+  HIPCHK(launch_incr_u64(proposal_counter, st));
+  return SLMC_OK;
+}
+
 int slmc_profile(int enable) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = enable != 0;
