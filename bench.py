@@ -153,6 +153,12 @@ def uneven_rates(slmc, torch, np, prec, reps=3):
         return lambda: slmc.green(models, x, opt, model_idx=msel, x_off=x_off, g_off=g_off,
                                   n_items=len(sel), G=G, ws=ws), g_off
 
+    tuned = {}
+    for mi, d in enumerate(mds):
+        sel = [j for j in range(128) if midx[j] == mi]
+        xc = torch.tensor(np.stack([xs[j] for j in sel]), dtype=torch.float64, device=dev)
+        ch, _, rej = slmc.autotune(models[mi], xc, opt)
+        tuned["L%d" % d["Lx"]] = dict(ch, rejected=rej)
     fn, g_off = packed(list(range(128)))
     t_all = _timed(torch, fn, reps)
     out = {"packed_128": {"evals_per_s": round(128 / t_all, 1), "ms_per_call": round(t_all * 1e3, 3)}}
@@ -163,6 +169,7 @@ def uneven_rates(slmc, torch, np, prec, reps=3):
         out["L%d_Ltau%d" % (d["Lx"], d["Ltau"])] = {"items": len(sel), "evals_per_s": round(len(sel) / tc, 1),
                                                      "ms_per_call": round(tc * 1e3, 3)}
     out["sum_of_classes_ms"] = round(sum(v["ms_per_call"] for k, v in out.items() if k.startswith("L")), 3)
+    out["autotune"] = tuned
     ld, sg, Gp, st = fn()
     torch.cuda.synchronize()
     ld, sg, Gh, st = ld.cpu().numpy(), sg.cpu().numpy(), Gp.cpu().numpy(), st.cpu().numpy()
@@ -502,6 +509,8 @@ def main():
     ap.add_argument("--cpu-all-threads", action="store_true",
                     help="also time the oracle with the BLAS library's default thread count "
                          "(slower than one thread at these sizes)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default schedule and tile choices (no autotuning)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the legs of the other workloads (4x4, 8x8, 12x12 accept, uneven "
                          "packed batch, 16x16 error by coupling), e.g. for profiling runs")
@@ -538,6 +547,16 @@ def main():
     eff = slmc.eff_model(**eff_coefficients(4, 0, args.lam, delta=0.6))
     xs = np.stack([workload_item("W4", b % 128, lam_idx)[1] for b in range(B)])
 
+    # the autotuner picks the schedule and tile choices of both paths on these fields first
+    tune = None
+    if not args.no_tune and not args.serial:
+        tune = {}
+        for p in ([args.precision] + ([] if args.precision == "fp64" or args.no_fp64 else ["fp64"])):
+            o = slmc.options(p, args.residual if p != "fp64" else 0, args.acc_chunk)
+            ch, tried, rej = slmc.autotune(slmc.model_from_dict(md),
+                                           torch.tensor(xs, dtype=torch.float64, device="cuda:0"), o)
+            tune[p] = dict(ch, candidates=tried, rejected=rej)
+        _progress("autotune done: %s" % tune)
     main_run = run(slmc, torch, md, eff, xs, B, args.precision, args)
     _progress("headline run done: %.1f evals/s" % (B * args.steps / (main_run["ms"] / 1e3)))
     ms_per_step = main_run["ms"] / args.steps
@@ -678,6 +697,7 @@ def main():
                    "precision": args.precision, "acc_chunk": args.acc_chunk,
                    "residual_steps": args.residual, "global_batch": B, "parallelism": "none",
                    "schedule": "serial" if args.serial else "overlapped"},
+        "autotune": tune,
         "roofline": roof, "slice_products": seg_rate, "path_roofline": path_roofline(args.precision, md, value),
         "cpu_baseline": cpu, "error_vs_oracle": err,
         "fp64_path": fp64,

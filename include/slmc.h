@@ -357,6 +357,44 @@ int slmc_step(const slmc_model* model, const slmc_eff* eff, const slmc_options* 
               uint8_t* accepted, double* log_ratio, double* G_prop, int32_t* status,
               int64_t* n_local_accepted, void* ws, size_t ws_bytes, void* stream);
 
+/* The schedule and tile choices of one model, precision and batch size (the batch size
+ * rounded up to a power of two): schedule 0 the default per precision (step-by-step
+ * release of the side work, "gated", for SLMC_INT8X5 and SLMC_BF16X3; everything queued
+ * up front, "eager", otherwise), 1 eager, 2 gated, 3 serial (as SLMC_FLAG_SERIAL); seg_ahead
+ * 1-3 segment blocks released ahead of the chain (gated); gate 0/1 an empty kernel in front
+ * of the gated side work; seg_mode (SLMC_INT8X5) 0 A operands in registers where E's
+ * translation symmetry allows, 1 E's base rows in LDS only, 2 E streamed from memory;
+ * seg_cb 0 the default panel width, 1 16 columns, 2 32 columns (FP64, and int8 panels of
+ * at most two row blocks per wave); ms_per_call the tuned time of one logdet call.  Every
+ * choice gives bitwise the same results. */
+typedef struct {
+  int32_t schedule, seg_ahead, gate, seg_mode, seg_cb;
+  double ms_per_call;
+} slmc_tuning;
+
+/* The project's autotuner: times the candidate choices for logdet calls on the n_items
+ * fields x (device [n_items][Ltau][N], one model) and keeps the fastest for this model,
+ * precision and batch size; later slmc_logdet / slmc_green / accept calls that match use
+ * it (calls on other batch sizes keep the defaults).  Candidates are tried coordinate by
+ * coordinate: the segment kernel's variant under the default schedule (int8x5: seg_mode
+ * x seg_cb; FP64: seg_cb), then the schedule (serial, eager, gated with seg_ahead 1-3 and
+ * gate 0/1).  Each candidate's log-dets, signs and statuses are compared bitwise with the
+ * default's before it is timed (one warm call, then 2 timed calls, HIP events on
+ * `stream`); a candidate that differs is rejected.  Synchronous (it waits for `stream`).
+ * With the environment variable SLMC_TUNE_CACHE naming a file, the choices are read from
+ * it at first use and written back after each tuning.  ws: device workspace of at least
+ * slmc_workspace_bytes(model, 1, {n_items}, opt) + 6 * roundup256(8 n_items) bytes.
+ * chosen (host): the choice; n_tried, n_rejected (host, or NULL): candidates run and
+ * rejected.  Not with SLMC_FLAG_SERIAL. */
+int slmc_autotune(const slmc_model* model, const slmc_options* opt, int32_t n_items, const double* x,
+                  void* ws, size_t ws_bytes, void* stream, slmc_tuning* chosen, int32_t* n_tried,
+                  int32_t* n_rejected);
+
+/* The choice in effect for this model, precision and batch size, into out (host);
+ * *tuned (host) = 1 if the autotuner (or the cache file) provided it, 0 for the defaults. */
+int slmc_tuning_lookup(const slmc_model* model, const slmc_options* opt, int32_t n_items,
+                       slmc_tuning* out, int32_t* tuned);
+
 /* Kernel timing with HIP events recorded around each launch on its stream (off by
  * default; costs two events per launch while on).  Classes: 0 seg_chain, 1 wy_apply,
  * 2 qr, 3 vupd, 4 lu, 5 lu_solve, 6 residual, 7 eff_sweep.  slmc_profile_read waits for
@@ -388,7 +426,8 @@ int slmc_green_noalloc(const slmc_model* model, const slmc_options* opt, int32_t
                        int32_t* status, void* stream);
 
 /* Frees the library's device constant cache (e^{-dtau K} copies per model and device)
- * and its side streams (after waiting for them).  Must not be called while work that
+ * and its side streams (after waiting for them), and forgets the autotuner's choices (the
+ * cache file, if any, stays and is read again at the next lookup).  Must not be called while work that
  * uses them is still queued on other streams. */
 void slmc_cache_clear(void);
 

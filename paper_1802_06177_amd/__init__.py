@@ -21,7 +21,7 @@ from ._abi import (SLMC_FP64, SLMC_FP32, SLMC_BF16X3, SLMC_BF16X6, SLMC_FP32_PLA
 __all__ = ["model", "options", "eff_model", "expk", "workspace_bytes", "logdet", "green",
            "eff_energy", "eff_sweep", "eff_wolff", "eff_propose", "log_weight", "cumulative_accept",
            "green_noalloc", "green_slices", "dqmc_sweep", "dqmc_block", "eff_fit", "step",
-           "cache_clear", "SlmcError", "version"]
+           "autotune", "tuning", "cache_clear", "SlmcError", "version"]
 
 PRECISIONS = {"fp64": SLMC_FP64, "fp32": SLMC_FP32, "bf16x3": SLMC_BF16X3, "bf16x6": SLMC_BF16X6,
               "fp32plain": SLMC_FP32_PLAIN, "int8x5": SLMC_INT8X5}
@@ -415,6 +415,42 @@ def step(m, eff, x_cur, x_prop, logw_cur, eeff_cur, n_sweeps, n_clusters, seed, 
                            vp(out["status"].data_ptr()), vp(out["n_local"].data_ptr()), wsp, wsn,
                            _stream(stream)))
     return out
+
+
+SCHEDULES = {0: "default", 1: "eager", 2: "gated", 3: "serial"}
+
+
+def _tuning_dict(t):
+    return {"schedule": SCHEDULES.get(t.schedule, t.schedule), "seg_ahead": t.seg_ahead, "gate": t.gate,
+            "seg_mode": t.seg_mode, "seg_cb": t.seg_cb, "ms_per_call": round(t.ms_per_call, 4)}
+
+
+def autotune(m, x, opt=None, stream=None):
+    """Runs the library's autotuner on the fields x [items, Ltau, N] (slmc_autotune): the
+    fastest bitwise-equal schedule and tile choice for this model, precision and batch size
+    is kept for later calls.  Returns (choice dict, candidates tried, rejected)."""
+    torch = _torch()
+    n = _chains(m, x)
+    opt = opt or options()
+    L = _abi.lib()
+    need = L.slmc_workspace_bytes(C.byref(m), 1, C.byref(_BatchArgs(n).batch), C.byref(opt)) + \
+        6 * ((8 * n + 255) // 256 * 256)
+    wsp, wsn = _ws_args(_workspace(need, x.device, stream))
+    t = _abi.Tuning()
+    tried, rej = C.c_int32(), C.c_int32()
+    _abi.check(L.slmc_autotune(C.byref(m), C.byref(opt), n, _dev_f64(x, "x"), wsp, wsn, _stream(stream),
+                               C.byref(t), C.byref(tried), C.byref(rej)))
+    return _tuning_dict(t), tried.value, rej.value
+
+
+def tuning(m, n_items, opt=None):
+    """(choice dict, tuned?) in effect for this model, precision and batch size."""
+    opt = opt or options()
+    t = _abi.Tuning()
+    tuned = C.c_int32()
+    _abi.check(_abi.lib().slmc_tuning_lookup(C.byref(m), C.byref(opt), int(n_items), C.byref(t),
+                                             C.byref(tuned)))
+    return _tuning_dict(t), bool(tuned.value)
 
 
 def eff_wolff(m, eff, x, n_clusters, seed, proposal_idx, stream=None):

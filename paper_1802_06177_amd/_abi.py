@@ -18,7 +18,8 @@ EXPORTS = ("slmc_version", "slmc_last_error", "slmc_expk", "slmc_workspace_bytes
            "slmc_profile_reset", "slmc_profile_name", "slmc_cache_clear", "slmc_green_noalloc",
            "slmc_eff_wolff", "slmc_eff_propose", "slmc_slices_workspace_bytes",
            "slmc_green_slices", "slmc_dqmc_workspace_bytes", "slmc_dqmc_sweep", "slmc_dqmc_block",
-           "slmc_fit_workspace_bytes", "slmc_eff_fit", "slmc_step")
+           "slmc_fit_workspace_bytes", "slmc_eff_fit", "slmc_step", "slmc_autotune",
+           "slmc_tuning_lookup")
 SLMC_NOALLOC_WORKSPACE_BYTES = 248 << 20
 
 
@@ -42,6 +43,11 @@ class Eff(C.Structure):
     _fields_ = [("Jk", C.c_double), ("J2", C.c_double), ("Jp", C.c_double), ("Jp6", C.c_double),
                 ("a", C.c_double), ("Js", C.c_double * 3), ("Jt", C.c_double),
                 ("delta", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("seg_ahead", C.c_int32), ("gate", C.c_int32),
+                ("seg_mode", C.c_int32), ("seg_cb", C.c_int32), ("ms_per_call", C.c_double)]
 
 
 _lib = None
@@ -90,6 +96,8 @@ def lib():
     L.slmc_eff_fit.argtypes = [P(Model), C.c_double, i32, vp, vp, i32, vp, vp, vp, sz, vp]
     L.slmc_step.argtypes = [P(Model), P(Eff), P(Options), i32, vp, vp, vp, vp, i32, i32, u64, vp, vp, vp,
                             vp, vp, vp, vp, sz, vp]
+    L.slmc_autotune.argtypes = [P(Model), P(Options), i32, vp, vp, sz, vp, P(Tuning), P(i32), P(i32)]
+    L.slmc_tuning_lookup.argtypes = [P(Model), P(Options), i32, P(Tuning), P(i32)]
     L.slmc_eff_wolff.argtypes = [P(Model), P(Eff), i32, vp, i32, u64, u64, vp, vp]
     L.slmc_eff_propose.argtypes = [P(Model), P(Eff), i32, vp, i32, i32, u64, u64, vp, vp, vp]
     L.slmc_green_noalloc.argtypes = [P(Model), P(Options), i32, vp, vp, vp, vp, vp, vp]

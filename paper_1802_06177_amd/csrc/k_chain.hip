@@ -241,19 +241,23 @@ hipError_t launch_seg_f32(int ecorr, int ch, const float* E32, const uint16_t* E
 
 hipError_t launch_seg_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f,
                          int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc,
-                         double ldl, double* S, double* snorm, int trow, hipStream_t st);
+                         double ldl, double* S, double* snorm, int trow, int seg_mode, int seg_cb,
+                         hipStream_t st);
 
 hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const float* E32,
                             const uint16_t* Elo, const uint16_t* Ebf, const int8_t* Eq,
                             const double* Esc, FieldRef f, int nb, int N, int Np, int Ltau,
                             int n_s, int m, int k0, int kc, double ldl, double* S, double* snorm,
-                            int trow, hipStream_t st) {
+                            int trow, hipStream_t st, int seg_mode, int seg_cb) {
   const int NRB = Np / 16;
   const int RB = (NRB + 3) / 4;
   if (RB < 1 || RB > 8) return hipErrorInvalidValue;
   if (prec == 0) {
-    // panel width: 32 columns when it divides Np and the LDS panel stays small
-    const int CB = (Np % 32 == 0 && Np <= 256) ? 2 : 1;
+    // panel width: 32 columns when it divides Np and the LDS panel stays small (seg_cb 1 or 2
+    // forces 16 or 32 where 32 divides Np)
+    int CB = (Np % 32 == 0 && Np <= 256) ? 2 : 1;
+    if (seg_cb == 1) CB = 1;
+    if (seg_cb == 2 && Np % 32 == 0) CB = 2;
     switch (RB) {
       case 1: return pick_f64<1>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
       case 2: return pick_f64<2>(CB, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
@@ -269,7 +273,8 @@ hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const fl
     return launch_seg_f32(prec == 1, acc_chunk, E32, Elo, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S,
                           snorm, st);
   if (prec == 5)
-    return launch_seg_i8(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, st);
+    return launch_seg_i8(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, seg_mode,
+                         seg_cb, st);
   if (prec == 2 || prec == 3)
     return launch_seg_bf16(prec == 2 ? 2 : 3, E64, Ebf, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, st);
   return hipErrorInvalidValue;

@@ -423,10 +423,10 @@ hipError_t run_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldR
 template <int NW, int RB, int CB>
 hipError_t pick_tab(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f, int nb,
                     int N, int Np, int Ltau, int n_s, int m, int k0, int kc, double ldl, double* S,
-                    double* sn, int trow, int LDE, hipStream_t st) {
+                    double* sn, int trow, int LDE, bool allow_reg, hipStream_t st) {
   // registers for the A operands when the base rows are one row block and the 4 waves'
   // row blocks cover Np in whole k blocks
-  if (NW == 4 && trow == 16 && Np % 64 == 0 && Np / 64 == RB)
+  if (allow_reg && NW == 4 && trow == 16 && Np % 64 == 0 && Np / 64 == RB)
     return run_i8<NW, RB, CB, true, NW == 4>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
   if (trow > 0)
     return run_i8<NW, RB, CB, true, false>(Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, sn, trow, LDE, st);
@@ -437,18 +437,22 @@ hipError_t pick_tab(const int8_t* Eq, const double* Esc, const double* E64, Fiel
 
 hipError_t launch_seg_i8(const int8_t* Eq, const double* Esc, const double* E64, FieldRef f,
                          int nb, int N, int Np, int Ltau, int n_s, int m, int k0, int kc,
-                         double ldl, double* S, double* snorm, int trow, hipStream_t st) {
+                         double ldl, double* S, double* snorm, int trow, int seg_mode, int seg_cb,
+                         hipStream_t st) {
   const int NRB = Np / 16;
   // tab mode when E repeats every trow rows (a multiple of 16, N unpadded) and the base
   // rows' slices fit in 64 KB of LDS; LDE = 16 mod 256 keeps the 16-row reads conflict free
+  // (seg_mode 2: E streamed from memory; 1: no register operands)
   const int LDE = (N + 255) / 256 * 256 + 16;
-  if (!(trow > 0 && trow % 16 == 0 && trow <= N && N == Np && (size_t)NSL * trow * LDE <= 65536))
+  if (seg_mode == 2 ||
+      !(trow > 0 && trow % 16 == 0 && trow <= N && N == Np && (size_t)NSL * trow * LDE <= 65536))
     trow = 0;
-#define SEG_I8_ARGS Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, st
+  const bool allow_reg = seg_mode == 0;
+#define SEG_I8_ARGS Eq, Esc, E64, f, nb, N, Np, Ltau, n_s, m, k0, kc, ldl, S, snorm, trow, LDE, allow_reg, st
   if (NRB <= 16) {
-    // 4 waves, up to 4 row blocks each; 32-column panels while RB <= 2
+    // 4 waves, up to 4 row blocks each; 32-column panels while RB <= 2 (seg_cb 1: 16 columns)
     const int RB = (NRB + 3) / 4;
-    const bool cb2 = Np % 32 == 0 && RB <= 2;
+    const bool cb2 = Np % 32 == 0 && RB <= 2 && seg_cb != 1;
     switch (RB) {
       case 1: return cb2 ? pick_tab<4, 1, 2>(SEG_I8_ARGS) : pick_tab<4, 1, 1>(SEG_I8_ARGS);
       case 2: return cb2 ? pick_tab<4, 2, 2>(SEG_I8_ARGS) : pick_tab<4, 2, 1>(SEG_I8_ARGS);

@@ -31,7 +31,11 @@ hipError_t launch_seg_chain(int prec, int acc_chunk, const double* E64, const fl
                             const uint16_t* Elo, const uint16_t* Ebf, const int8_t* Eq,
                             const double* Esc, FieldRef f, int nb, int N, int Np, int Ltau,
                             int n_s, int m, int k0, int kc, double ldl, double* S, double* snorm,
-                            int trow, hipStream_t st);
+                            int trow, hipStream_t st, int seg_mode = 0, int seg_cb = 0);
+// seg_mode (int8 slices): 0 any (A operands in registers where the structure allows), 1 E's
+// base rows in LDS but no register operands, 2 E streamed from memory.  seg_cb: 0 the
+// default panel width, 1 16 columns, 2 32 columns where 32 divides Np (FP64; int8 with at
+// most 2 row blocks per wave).  Every choice gives the same bits.
 
 // A[b] = Bsrc[b] Q[b] (Q = H_0 ... H_{Np-1} in compact-WY blocks: Householder vectors
 // in the strict lower triangle of QRW[b], T blocks in Tb[b][Np/16][16][16]).

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -300,6 +301,80 @@ int get_consts(const slmc_model* m, ModelConsts** out) {
   return SLMC_OK;
 }
 
+// ---- schedule and tile choices, and the autotuner's cache ------------------------------
+// sched: 0 the default per precision (gated for int8x5 and bf16x3, eager otherwise), 1
+// eager, 2 gated, 3 serial; ahead: segment blocks released ahead of the chain (gated);
+// gate: the empty gate kernel in front of the gated side work; seg_mode, seg_cb: the
+// segment kernel's variant (launch.h).  Every choice gives bitwise the same results.
+struct TuneCfg {
+  int sched = 0, ahead = 2, gate = 1, seg_mode = 0, seg_cb = 0;
+  double ms = 0.0;
+};
+typedef std::tuple<int, int, int, int, int, int, int> TuneKey;   // dev, Lx, Ly, Ltau, n_s, prec, nb bucket
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneCfg> g_tune;
+bool g_tune_loaded = false;
+
+int nb_bucket(int nb) {
+  int b = 1;
+  while (b < nb) b <<= 1;
+  return b;
+}
+
+TuneKey tune_key(int dev, const slmc_model* m, const slmc_options* o, int nb) {
+  return std::make_tuple(dev, m->Lx, m->Ly, m->Ltau, m->n_s, o->precision, nb_bucket(nb));
+}
+
+const char* tune_path() {
+  const char* p = std::getenv("SLMC_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+// Loads the cache file named by SLMC_TUNE_CACHE once (lines: Lx Ly Ltau n_s precision
+// nb_bucket sched ahead gate seg_mode seg_cb ms, device 0 and every other device alike);
+// g_tune_mu must be held.
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int Lx, Ly, Lt, ns, pr, nbb;
+  TuneCfg c;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %lf", &Lx, &Ly, &Lt, &ns, &pr, &nbb, &c.sched,
+                     &c.ahead, &c.gate, &c.seg_mode, &c.seg_cb, &c.ms) == 12) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 1;
+    for (int d = 0; d < ndev; ++d) g_tune[std::make_tuple(d, Lx, Ly, Lt, ns, pr, nbb)] = c;
+  }
+  std::fclose(f);
+}
+
+void tune_save_locked() {
+  const char* path = tune_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : g_tune) {
+    if (std::get<0>(kv.first) != 0) continue;
+    const TuneCfg& c = kv.second;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %.6f\n", std::get<1>(kv.first), std::get<2>(kv.first),
+                 std::get<3>(kv.first), std::get<4>(kv.first), std::get<5>(kv.first), std::get<6>(kv.first),
+                 c.sched, c.ahead, c.gate, c.seg_mode, c.seg_cb, c.ms);
+  }
+  std::fclose(f);
+}
+
+TuneCfg tune_lookup(const slmc_model* m, const slmc_options* o, int nb) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TuneCfg();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(tune_key(dev, m, o, nb));
+  return it == g_tune.end() ? TuneCfg() : it->second;
+}
+
 // Carves 256-byte aligned sub-buffers out of a workspace (or only measures).
 struct Arena {
   char* base;
@@ -387,8 +462,9 @@ size_t group_bytes(const slmc_model* m, int nb) {
 // The hot path for one group of items sharing a model.
 int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, const slmc_batch* batch,
               const double* x, double* logdet, int8_t* sign, double* G, int32_t* status,
-              GroupBufs& w, hipStream_t st, ModelConsts* mc = nullptr) {
+              GroupBufs& w, hipStream_t st, ModelConsts* mc = nullptr, const TuneCfg* force = nullptr) {
   int rc = SLMC_OK;
+  const TuneCfg cfg = force ? *force : tune_lookup(m, o, (int)grp.items.size());
   if (!mc) {
     rc = get_consts(m, &mc);
     if (rc) return rc;
@@ -447,11 +523,13 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     while (b) { const int t = a % b; a = b; b = t; }
     if (16 / a * m->Lx <= N) trow = 16 / a * m->Lx;
   }
-  const bool overlap = !(o->flags & SLMC_FLAG_SERIAL) && mseg > 1;
+  const bool overlap = !(o->flags & SLMC_FLAG_SERIAL) && mseg > 1 && cfg.sched != 3;
   // Gated side work (below) where a segment block and a V update about fit in the time of
-  // a QR on the CUs it leaves free (int8x5, bf16x3); the heavier FP64, FP32 and bf16x6
-  // segment products are all released at once instead and fill the chip from the start.
-  const bool gated = overlap && (o->precision == SLMC_INT8X5 || o->precision == SLMC_BF16X3);
+  // a QR on the CUs it leaves free (by default int8x5, bf16x3); the heavier FP64, FP32 and
+  // bf16x6 segment products are all released at once instead and fill the chip from the
+  // start (the autotuner may choose otherwise per model, precision and batch)
+  const bool gated = overlap && (cfg.sched == 2 ||
+                                 (cfg.sched == 0 && (o->precision == SLMC_INT8X5 || o->precision == SLMC_BF16X3)));
   std::unique_lock<std::mutex> side_lock(g_side_mu, std::defer_lock);
   SideStream* ss = nullptr;
   if (overlap) {
@@ -465,13 +543,15 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     for (int k = 0; k < (gated ? 1 : mseg); ++k) {
       ProfScope ps(0, ss->s);
       HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb, N,
-                              Np, m->Ltau, m->n_s, mseg, k, 1, ldl, w.S, w.snorm, trow, ss->s));
+                              Np, m->Ltau, m->n_s, mseg, k, 1, ldl, w.S, w.snorm, trow, ss->s, cfg.seg_mode,
+                              cfg.seg_cb));
       HIPCHK(hipEventRecord(ss->ev[k], ss->s));
     }
   } else {
     ProfScope ps(0, st);
     HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb, N,
-                            Np, m->Ltau, m->n_s, mseg, 0, mseg, ldl, w.S, w.snorm, trow, st));
+                            Np, m->Ltau, m->n_s, mseg, 0, mseg, ldl, w.S, w.snorm, trow, st, cfg.seg_mode,
+                            cfg.seg_cb));
   }
   // a3: stabilized accumulation
   double* logD[2] = {w.logD0, w.logD1};
@@ -489,7 +569,8 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   // ev[2 mseg+1+k] V update k done (s2), ev[3 mseg+1+k] wy_apply k done (st),
   // ev[4 mseg+1+k] gate k passed (s).  QR k reuses the buffers that V update k - kQB
   // reads, so step k waits for it (with the wait for segment k, before wy_apply k).
-  constexpr int kSegAhead = 2, kQB = GroupBufs::kQB;
+  const int kSegAhead = std::max(1, std::min(3, cfg.ahead));
+  constexpr int kQB = GroupBufs::kQB;
   hipEvent_t* ev_qr = overlap ? &ss->ev[mseg + 1] : nullptr;
   hipEvent_t* ev_vu = overlap ? &ss->ev[2 * mseg + 1] : nullptr;
   hipEvent_t* ev_ph = overlap ? &ss->ev[3 * mseg + 1] : nullptr;
@@ -532,12 +613,13 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     if (gated) {
       HIPCHK(hipEventRecord(ev_ph[k], st));
       HIPCHK(hipStreamWaitEvent(ss->s, ev_ph[k], 0));
-      HIPCHK(launch_order_gate(ss->s));
+      if (cfg.gate) HIPCHK(launch_order_gate(ss->s));
       HIPCHK(hipEventRecord(ev_gt[k], ss->s));
       for (int j = (k == 0 ? 1 : k + kSegAhead); j <= k + kSegAhead && j < mseg; ++j) {
         ProfScope ps(0, ss->s);
         HIPCHK(launch_seg_chain(o->precision, o->acc_chunk, mc->E64, mc->E32, mc->Elo, Ebf, mc->Eq, mc->Esc, f, nb,
-                                N, Np, m->Ltau, m->n_s, mseg, j, 1, ldl, w.S, w.snorm, trow, ss->s));
+                                N, Np, m->Ltau, m->n_s, mseg, j, 1, ldl, w.S, w.snorm, trow, ss->s,
+                                cfg.seg_mode, cfg.seg_cb));
         HIPCHK(hipEventRecord(ss->ev[j], ss->s));
       }
       if (k >= 1) {
@@ -1271,6 +1353,151 @@ int slmc_step(const slmc_model* model, const slmc_eff* eff, const slmc_options* 
   return SLMC_OK;
 }
 
+int slmc_tuning_lookup(const slmc_model* model, const slmc_options* opt, int32_t n_items,
+                       slmc_tuning* out, int32_t* tuned) {
+  g_err.clear();
+  if (!model || !opt || !out || !tuned || n_items < 1) return fail(SLMC_E_ARG, "NULL pointer or n_items < 1");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;   // a lookup needs no device
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(tune_key(dev, model, opt, n_items));
+  const TuneCfg c = it == g_tune.end() ? TuneCfg() : it->second;
+  *out = slmc_tuning{c.sched, c.ahead, c.gate, c.seg_mode, c.seg_cb, c.ms};
+  *tuned = it == g_tune.end() ? 0 : 1;
+  return SLMC_OK;
+}
+
+int slmc_autotune(const slmc_model* model, const slmc_options* opt, int32_t n_items, const double* x,
+                  void* ws, size_t ws_bytes, void* stream, slmc_tuning* chosen, int32_t* n_tried,
+                  int32_t* n_rejected) {
+  g_err.clear();
+  int rc = check_model(model);
+  if (rc) return rc;
+  rc = check_opt(opt);
+  if (rc) return rc;
+  if (!x || !chosen) return fail(SLMC_E_ARG, "NULL pointer");
+  if (n_items < 1) return fail(SLMC_E_ARG, "n_items must be >= 1");
+  if (opt->flags & SLMC_FLAG_SERIAL) return fail(SLMC_E_ARG, "SLMC_FLAG_SERIAL fixes the schedule: nothing to tune");
+  const size_t gb = group_bytes(model, n_items), small = align256((size_t)n_items * 8);
+  if (!ws || ws_bytes < gb + 6 * small)
+    return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, gb + 6 * small);
+  ModelConsts* mc = nullptr;
+  rc = get_consts(model, &mc);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Arena a(ws);
+  GroupBufs w;
+  const int N = model->Lx * model->Ly, Np = roundup16(N);
+  carve(a, n_items, Np, (model->Ltau + model->n_s - 1) / model->n_s, w);
+  double* ld[2] = {a.take<double>(n_items), a.take<double>(n_items)};
+  int8_t* sg[2] = {(int8_t*)a.take<double>(n_items), (int8_t*)a.take<double>(n_items)};
+  int32_t* stt[2] = {(int32_t*)a.take<double>(n_items), (int32_t*)a.take<double>(n_items)};
+  Group grp{0, {}};
+  for (int b = 0; b < n_items; ++b) grp.items.push_back(b);
+  slmc_batch bt{n_items, nullptr, nullptr, nullptr};
+  std::vector<double> hl[2] = {std::vector<double>(n_items), std::vector<double>(n_items)};
+  std::vector<int8_t> hs[2] = {std::vector<int8_t>(n_items), std::vector<int8_t>(n_items)};
+  std::vector<int32_t> ht[2] = {std::vector<int32_t>(n_items), std::vector<int32_t>(n_items)};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int tried = 0, rejected = 0;
+  // one candidate: outputs into slot j (0 = the default, the reference), compared bitwise
+  // with the default's, then timed over reps calls; returns ms per call, < 0 if rejected
+  auto run = [&](const TuneCfg& c, int j, double* ms_out) -> int {
+    const int reps = 2;
+    int r = run_group(model, opt, grp, &bt, x, ld[j], sg[j], nullptr, stt[j], w, st, mc, &c);
+    if (r) return r;
+    HIPCHK(hipMemcpyAsync(hl[j].data(), ld[j], n_items * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hs[j].data(), sg[j], n_items, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ht[j].data(), stt[j], n_items * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ++tried;
+    if (j == 1 && (std::memcmp(hl[0].data(), hl[1].data(), n_items * 8) != 0 || hs[0] != hs[1] ||
+                   ht[0] != ht[1])) {
+      ++rejected;
+      *ms_out = -1.0;
+      return SLMC_OK;
+    }
+    HIPCHK(hipEventRecord(e0, st));
+    for (int k = 0; k < reps; ++k) {
+      r = run_group(model, opt, grp, &bt, x, ld[j], sg[j], nullptr, stt[j], w, st, mc, &c);
+      if (r) return r;
+    }
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    *ms_out = ms / reps;
+    return SLMC_OK;
+  };
+  TuneCfg best;   // the default
+  double best_ms = 0.0;
+  rc = run(best, 0, &best_ms);
+  // candidates, coordinate-wise: first the segment kernel's variant under the default
+  // schedule, then the schedule with the best variant
+  std::vector<TuneCfg> seg;
+  if (opt->precision == SLMC_INT8X5) {
+    for (int mode = 0; mode < 3; ++mode)
+      for (int cb = 0; cb < 2; ++cb) {
+        TuneCfg c;
+        c.seg_mode = mode;
+        c.seg_cb = cb;
+        if (mode || cb) seg.push_back(c);
+      }
+  } else if (opt->precision == SLMC_FP64) {
+    for (int cb = 1; cb <= 2; ++cb) {
+      TuneCfg c;
+      c.seg_cb = cb;
+      if (cb == 1 || Np % 32 == 0) seg.push_back(c);
+    }
+  }
+  for (size_t i = 0; i < seg.size() && rc == SLMC_OK; ++i) {
+    double ms = 0.0;
+    rc = run(seg[i], 1, &ms);
+    if (rc == SLMC_OK && ms >= 0.0 && ms < best_ms) { best = seg[i]; best_ms = ms; }
+  }
+  std::vector<TuneCfg> sch;
+  for (int sc = 1; sc <= 3; ++sc) {
+    if (sc != 2) {
+      TuneCfg c = best;
+      c.sched = sc;
+      sch.push_back(c);
+      continue;
+    }
+    for (int ahead = 1; ahead <= 3; ++ahead)
+      for (int gate = 0; gate <= 1; ++gate) {
+        TuneCfg c = best;
+        c.sched = 2;
+        c.ahead = ahead;
+        c.gate = gate;
+        sch.push_back(c);
+      }
+  }
+  for (size_t i = 0; i < sch.size() && rc == SLMC_OK; ++i) {
+    double ms = 0.0;
+    rc = run(sch[i], 1, &ms);
+    if (rc == SLMC_OK && ms >= 0.0 && ms < best_ms) { best = sch[i]; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  best.ms = best_ms;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[tune_key(dev, model, opt, n_items)] = best;
+    tune_save_locked();
+  }
+  *chosen = slmc_tuning{best.sched, best.ahead, best.gate, best.seg_mode, best.seg_cb, best.ms};
+  if (n_tried) *n_tried = tried;
+  if (n_rejected) *n_rejected = rejected;
+  return SLMC_OK;
+}
+
 int slmc_profile(int enable) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = enable != 0;
@@ -1331,6 +1558,9 @@ void slmc_cache_clear(void) {
     (void)hipSetDevice(cur);
   }
   g_side.clear();
+  std::lock_guard<std::mutex> lk3(g_tune_mu);
+  g_tune.clear();
+  g_tune_loaded = false;
 }
 
 }  // extern "C"

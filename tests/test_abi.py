@@ -171,3 +171,24 @@ def test_binding_rejects_mis_shaped_tensors_before_any_call():
     with pytest.raises(TypeError):
         slmc.green([m, m2], torch.zeros(1720, **f64), model_idx=[0, 1], x_off=[0, 640],
                    g_off=[0, 256], n_items=2, G=torch.zeros(1552, **f64))
+
+
+def test_tuning_lookup_defaults_without_gpu_work(tmp_path, monkeypatch):
+    # no tuning yet: the defaults; a cache file is read at the first lookup after a clear
+    m = slmc.model(6, 6, 30, 10)
+    t, tuned = slmc.tuning(m, 8, slmc.options("int8x5"))
+    assert not tuned and t["schedule"] == "default" and t["seg_ahead"] == 2 and t["gate"] == 1
+    f = tmp_path / "tune.txt"
+    f.write_text("6 6 30 10 5 8 2 3 0 1 1 1.250000\n")
+    monkeypatch.setenv("SLMC_TUNE_CACHE", str(f))
+    slmc.cache_clear()
+    try:
+        t, tuned = slmc.tuning(m, 7, slmc.options("int8x5"))   # batch 7 rounds up to 8
+        assert tuned and t == {"schedule": "gated", "seg_ahead": 3, "gate": 0, "seg_mode": 1, "seg_cb": 1,
+                               "ms_per_call": 1.25}
+        assert not slmc.tuning(m, 9, slmc.options("int8x5"))[1]
+        assert not slmc.tuning(m, 8, slmc.options("fp64"))[1]
+    finally:
+        monkeypatch.delenv("SLMC_TUNE_CACHE")
+        slmc.cache_clear()
+    assert not slmc.tuning(m, 8, slmc.options("int8x5"))[1]
