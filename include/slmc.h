@@ -379,8 +379,9 @@ typedef struct {
  * coordinate: the segment kernel's variant under the default schedule (int8x5: seg_mode
  * x seg_cb; FP64: seg_cb), then the schedule (serial, eager, gated with seg_ahead 1-3 and
  * gate 0/1).  Each candidate's log-dets, signs and statuses are compared bitwise with the
- * default's before it is timed (one warm call, then 2 timed calls, HIP events on
- * `stream`); a candidate that differs is rejected.  Synchronous (it waits for `stream`).
+ * default's before it is timed (one warm call, then 3 timed calls, HIP events on
+ * `stream`); a candidate that differs is rejected.  The fastest is timed against the
+ * default once more, alternating, and kept only if at least 2% faster.  Synchronous (it waits for `stream`).
  * With the environment variable SLMC_TUNE_CACHE naming a file, the choices are read from
  * it at first use and written back after each tuning.  ws: device workspace of at least
  * slmc_workspace_bytes(model, 1, {n_items}, opt) + 6 * roundup256(8 n_items) bytes.

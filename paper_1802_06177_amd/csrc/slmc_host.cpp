@@ -1406,7 +1406,7 @@ int slmc_autotune(const slmc_model* model, const slmc_options* opt, int32_t n_it
   // one candidate: outputs into slot j (0 = the default, the reference), compared bitwise
   // with the default's, then timed over reps calls; returns ms per call, < 0 if rejected
   auto run = [&](const TuneCfg& c, int j, double* ms_out) -> int {
-    const int reps = 2;
+    const int reps = 3;
     int r = run_group(model, opt, grp, &bt, x, ld[j], sg[j], nullptr, stt[j], w, st, mc, &c);
     if (r) return r;
     HIPCHK(hipMemcpyAsync(hl[j].data(), ld[j], n_items * 8, hipMemcpyDeviceToHost, st));
@@ -1479,6 +1479,26 @@ int slmc_autotune(const slmc_model* model, const slmc_options* opt, int32_t n_it
     double ms = 0.0;
     rc = run(sch[i], 1, &ms);
     if (rc == SLMC_OK && ms >= 0.0 && ms < best_ms) { best = sch[i]; best_ms = ms; }
+  }
+  // the winner against the default once more, alternating, to keep a choice only when it
+  // is faster beyond the spread of single timings
+  if (rc == SLMC_OK && (best.sched != 0 || best.ahead != 2 || best.gate != 1 || best.seg_mode != 0 ||
+                        best.seg_cb != 0)) {
+    double tb = 0.0, td = 0.0;
+    const TuneCfg def;
+    for (int r = 0; r < 2 && rc == SLMC_OK; ++r) {
+      double ms = 0.0;
+      rc = run(best, 1, &ms);
+      tb += ms;
+      if (rc == SLMC_OK) rc = run(def, 1, &ms);
+      td += ms;
+    }
+    if (rc == SLMC_OK && !(tb < 0.98 * td)) {
+      best = def;
+      best_ms = td / 2;
+    } else {
+      best_ms = tb / 2;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

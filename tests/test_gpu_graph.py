@@ -72,7 +72,7 @@ def test_slmc_step_replays_from_a_captured_graph(prec):
     from synth import gen, eff_coefficients
     md = dict(Lx=8, Ly=8, Ltau=40, n_s=10, t=1.0, mu=0.0, dtau=0.1, lam=1.5, omega0=1.0, c_kin=0.5)
     m = slmc.model_from_dict(md)
-    eff = slmc.eff_model(**eff_coefficients(3, 0, 1.5, delta=0.4))
+    eff = slmc.eff_model(**eff_coefficients(3, 0, 1.5, delta=2.5))   # large moves: some rejected
     C, K, seed, c0 = 6, 4, 2718, 40
     x0 = gen(701, 0).normal(0.0, 1.0, size=(C, 40, 64))
     opt = slmc.options(prec, 1)
