@@ -548,15 +548,17 @@ def main():
     xs = np.stack([workload_item("W4", b % 128, lam_idx)[1] for b in range(B)])
 
     # the autotuner picks the schedule and tile choices of both paths on these fields first
-    tune = None
-    if not args.no_tune and not args.serial:
-        tune = {}
-        for p in ([args.precision] + ([] if args.precision == "fp64" or args.no_fp64 else ["fp64"])):
-            o = slmc.options(p, args.residual if p != "fp64" else 0, args.acc_chunk)
+    tune = {}
+    for p in ([args.precision] + ([] if args.precision == "fp64" or args.no_fp64 else ["fp64"])):
+        o = slmc.options(p, args.residual if p != "fp64" else 0, args.acc_chunk)
+        if not args.no_tune and not args.serial:
             ch, tried, rej = slmc.autotune(slmc.model_from_dict(md),
                                            torch.tensor(xs, dtype=torch.float64, device="cuda:0"), o)
-            tune[p] = dict(ch, candidates=tried, rejected=rej)
-        _progress("autotune done: %s" % tune)
+            tune[p] = dict(ch, source="tuned in this run", candidates=tried, rejected=rej)
+        else:
+            ch, tuned = slmc.tuning(slmc.model_from_dict(md), B, o)
+            tune[p] = dict(ch, source="cache file" if tuned else "defaults")
+    _progress("schedule and tile choices: %s" % tune)
     main_run = run(slmc, torch, md, eff, xs, B, args.precision, args)
     _progress("headline run done: %.1f evals/s" % (B * args.steps / (main_run["ms"] / 1e3)))
     ms_per_step = main_run["ms"] / args.steps

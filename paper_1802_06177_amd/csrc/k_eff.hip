@@ -65,6 +65,17 @@ __device__ __forceinline__ double local_delta(const double* x, int N, int Lx, in
   return de;
 }
 
+// log(u01(r)) < z, decided as the FP64 comparison decides it: the FP32 logarithm (hardware
+// log2, error below 4e-6 absolute for u >= 2^-32, plus 6e-8 from rounding u to FP32)
+// settles every case farther than 1e-4 from the boundary, and only the rest takes the
+// FP64 logarithm (a long software sequence, most of a site update's arithmetic otherwise).
+__device__ __forceinline__ bool log_u_below(uint32_t r, double z) {
+  const float lf = __logf((float)u01(r));
+  if ((double)lf < z - 1e-4) return true;
+  if ((double)lf > z + 1e-4) return false;
+  return log(u01(r)) < z;
+}
+
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* red) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -168,7 +179,7 @@ __global__ __launch_bounds__(1024) void eff_sweep_k(double* __restrict__ x, int 
         const double xo = xs[l * N + i];
         const double xn = xo + p.delta * (2.0 * u01(r.x) - 1.0);
         const double de = local_delta(xs, N, Lx, Ly, Ltau, p, ix, iy, l, xn);
-        if (log(u01(r.y)) < -de) {
+        if (log_u_below(r.y, -de)) {
           xs[l * N + i] = xn;
           ++acc;
         }
