@@ -62,8 +62,11 @@ __device__ __forceinline__ double xval(const double* QT, const double* V, const 
   return dbi[r] * QT[(size_t)r * Np + j] + dsm[r] * V[(size_t)r * Np + j];
 }
 
-template <int NRBMAX>
-__global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
+// NT threads per item: 512 (8 waves, one panel row per thread) up to Np = 256, where the
+// trailing update's registers fit two waves per SIMD and the second wave on each SIMD hides
+// the first one's memory latency; 256 (4 waves, panel rows t and t + 256) above.
+template <int NRBMAX, int NT>
+__global__ __launch_bounds__(NT) void lu_k(const double* __restrict__ QT,
                                             const double* __restrict__ V,
                                             const double* __restrict__ logD,
                                             const int* __restrict__ qsign,
@@ -75,6 +78,8 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
                                             int8_t* __restrict__ sign_out,
                                             int32_t* __restrict__ status_out, int N, int Np) {
   extern __shared__ double lds[];
+  constexpr int NW = NT / 64;
+  constexpr bool TWO = NT < 448;           // a second panel row per thread (Np <= 448)
   const int b = blockIdx.x;
   const int NRB = Np >> 4;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
@@ -84,11 +89,11 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
   double* ud = dsm + Np;                   // [Np] pivots (U diagonal)
   double* Li = ud + Np;                    // [16][LDY]
   double* Ui = Li + 16 * LDY;              // [16][LDY]
-  double* redv = Ui + 16 * LDY;            // [8]
-  double* cand = redv + 8;                 // [2][4][17]: each wave's pivot candidate row + key
-  int* prow = (int*)(cand + 2 * 4 * 17);   // [Np]
-  int* redi = prow + Np;                   // [8]
-  int* cnt = redi + 8;                     // [2]: swaps, singular
+  double* redv = Ui + 16 * LDY;            // [2 NW]
+  double* cand = redv + 2 * NW;            // [2][NW][17]: each wave's pivot candidate row + key
+  int* prow = (int*)(cand + 2 * NW * 17);  // [Np]
+  int* redi = prow + Np;                   // [NW]
+  int* cnt = redi + NW;                    // [2]: swaps, singular
   int* phys = cnt + 2;                     // [Np] panel position -> slot
   int* posof = phys + Np;                  // [Np] slot -> panel position
 
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
   const double* Vb = V + (size_t)b * Np * Np;
   double* L = LU + (size_t)b * Np * Np;
   double* DIb = DI + (size_t)b * NRB * 512;
-  for (int i = tid; i < Np; i += 256) {
+  for (int i = tid; i < Np; i += NT) {
     const double ld = logD[(size_t)b * Np + i];
     dbi[i] = exp(-fmax(ld, 0.0));
     dsm[i] = exp(fmin(ld, 0.0));
@@ -104,7 +109,7 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
   }
   if (tid == 0) { cnt[0] = 0; cnt[1] = 0; }
   __syncthreads();
-  for (int idx = tid; idx < Np * 16; idx += 256) {
+  for (int idx = tid; idx < Np * 16; idx += NT) {
     const int r = idx >> 4, jj = idx & 15;
     Pn0[r * LDY + jj] = xval(QTb, Vb, dbi, dsm, Np, r, jj);
   }
@@ -114,27 +119,27 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
     const int j0 = 16 * p, K = Np - j0, nrbK = NRB - p;
     double* Pn = Pn0 + (p & 1) * Np * LDY;
     double* Pnx = Pn0 + ((p + 1) & 1) * Np * LDY;
-    // Panel (K rows x 16 columns): thread t keeps slots t and t + 256 in registers.  Rows
+    // Panel (K rows x 16 columns): thread t keeps slot t (and t + NT) in registers.  Rows
     // never move: a row chosen as pivot leaves the search, and thread 0 keeps the
     // position <-> slot maps of the equivalent row exchanges (and their count).  One
     // barrier per column: every wave publishes its best candidate row, every thread then
     // takes the winner from LDS.
-    const bool h0 = tid < K, h1 = tid + 256 < K;
+    const bool h0 = tid < K, h1 = TWO && tid + NT < K;
     double ra[16], rc[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       ra[j] = h0 ? Pn[tid * LDY + j] : 0.0;
-      rc[j] = h1 ? Pn[(tid + 256) * LDY + j] : 0.0;
+      rc[j] = h1 ? Pn[(tid + NT) * LDY + j] : 0.0;
     }
-    for (int i = tid; i < K; i += 256) { phys[i] = i; posof[i] = i; }
+    for (int i = tid; i < K; i += NT) { phys[i] = i; posof[i] = i; }
     bool a0 = h0, a1 = h1;
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
       const uint64_t k0 = a0 ? pivot_key(ra[cc], tid) : 0ull;
-      const uint64_t k1 = a1 ? pivot_key(rc[cc], tid + 256) : 0ull;
+      const uint64_t k1 = a1 ? pivot_key(rc[cc], tid + NT) : 0ull;
       const uint64_t mine = umax64(k0, k1);
       const uint64_t kw = wave_max_u64(mine);
-      double* cd = cand + (cc & 1) * 68 + w * 17;
+      double* cd = cand + (cc & 1) * (NW * 17) + w * 17;
       if (kw != 0ull && mine == kw) {
         const bool second = (k1 == kw);
 #pragma unroll
@@ -143,11 +148,11 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
       }
       if (kw == 0ull && lane == 0) cd[16] = 0.0;
       __syncthreads();
-      const double* c0 = cand + (cc & 1) * 68;
+      const double* c0 = cand + (cc & 1) * (NW * 17);
       uint64_t best = 0ull;
       int bw = 0;
 #pragma unroll
-      for (int ww = 0; ww < 4; ++ww) {
+      for (int ww = 0; ww < NW; ++ww) {
         const uint64_t kk = (uint64_t)__double_as_longlong(c0[ww * 17 + 16]);
         if (kk > best) { best = kk; bw = ww; }
       }
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
         if (u == 0.0 || u != u) cnt[1] = 1;
       }
       if (sp == tid) a0 = false;
-      if (sp == tid + 256) a1 = false;
+      if (sp == tid + NT) a1 = false;
       const double ui = (u != 0.0) ? 1.0 / u : 0.0;
       if (a0) {
         const double l = ra[cc] * ui;
@@ -195,14 +200,14 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
       pr0 = prow[j0 + phys[tid]];
     }
     if (h1) {
-      const int q = posof[tid + 256];
+      const int q = posof[tid + NT];
 #pragma unroll
       for (int j = 0; j < 16; ++j) Pn[q * LDY + j] = rc[j];
-      pr1 = prow[j0 + phys[tid + 256]];
+      pr1 = prow[j0 + phys[tid + NT]];
     }
     __syncthreads();
     if (h0) prow[j0 + tid] = pr0;
-    if (h1) prow[j0 + tid + 256] = pr1;
+    if (h1) prow[j0 + tid + NT] = pr1;
     __syncthreads();
     // inverses of the unit-lower L11 (wave 0) and upper U11 (wave 1), one column per lane,
     // the column in registers (its zero entries add exact zeros to the sums, which keep the
@@ -234,12 +239,12 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
       for (int i = 0; i < 16; ++i) Ui[i * LDY + j] = x[i];
     }
     __syncthreads();
-    for (int idx = tid; idx < 512; idx += 256) {
+    for (int idx = tid; idx < 512; idx += NT) {
       const int which = idx >> 8, e = idx & 255, i = e >> 4, j = e & 15;
       DIb[(size_t)p * 512 + idx] = which ? Ui[i * LDY + j] : Li[i * LDY + j];
     }
     // trailing update: U12 = L11^-1 A12, A22 -= L21 U12
-    for (int cb = p + 1 + w; cb < NRB; cb += 4) {
+    for (int cb = p + 1 + w; cb < NRB; cb += NW) {
       // opaque copies of the lane coordinates: keeps the per-row addresses from being
       // hoisted out of this loop (they would pin hundreds of registers)
       int c = lane & 15, g = lane >> 4;
@@ -279,7 +284,7 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
         }
       }
     }
-    for (int idx = tid; idx < K * 16; idx += 256) {
+    for (int idx = tid; idx < K * 16; idx += NT) {
       const int r = idx >> 4, jj = idx & 15;
       L[(size_t)prow[j0 + r] * Np + j0 + jj] = Pn[r * LDY + jj];
     }
@@ -290,7 +295,7 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
   // log|det X|, sign, and the outputs
   double s = 0.0, sd = 0.0;
   int neg = 0;
-  for (int i = tid; i < Np; i += 256) {
+  for (int i = tid; i < Np; i += NT) {
     const double u = ud[i];
     s += log(fabs(u));
     neg += u < 0.0;
@@ -300,12 +305,16 @@ __global__ __launch_bounds__(256) void lu_k(const double* __restrict__ QT,
   s = sum64(s);
   sd = sum64(sd);
   for (int off = 32; off >= 1; off >>= 1) neg += __shfl_xor(neg, off, 64);
-  if (lane == 0) { redv[w] = s; redv[4 + w] = sd; redi[w] = neg; }
+  if (lane == 0) { redv[w] = s; redv[NW + w] = sd; redi[w] = neg; }
   __syncthreads();
   if (tid == 0) {
-    const double lx = redv[0] + redv[1] + redv[2] + redv[3];
-    const double lb = redv[4] + redv[5] + redv[6] + redv[7];
-    const int nn = redi[0] + redi[1] + redi[2] + redi[3];
+    double lx = 0.0, lb = 0.0;
+    int nn = 0;
+    for (int k = 0; k < NW; ++k) {
+      lx += redv[k];
+      lb += redv[NW + k];
+      nn += redi[k];
+    }
     double ld = lb + lx - (double)(Np - N) * LN2;
     const int sgn = qsign[b] * (((nn + cnt[0]) & 1) ? -1 : 1);
     int stt = 0;
@@ -627,9 +636,11 @@ template <int NRBMAX>
 hipError_t run_lu(const double* QT, const double* V, const double* logD, const int* qsign,
                   const int* st_in, double* LU, int* prow, double* DI, const int* item_of,
                   double* lo, int8_t* so, int32_t* sto, int nb, int N, int Np, hipStream_t st) {
-  const size_t lds = (size_t)(2 * Np * LDY + 3 * Np + 2 * 16 * LDY + 8 + 2 * 4 * 17) * sizeof(double) +
-                     (size_t)(3 * Np + 10) * sizeof(int);
-  hipLaunchKernelGGL(lu_k<NRBMAX>, dim3(nb), dim3(256), lds, st, QT, V, logD, qsign, st_in, LU,
+  constexpr int NT = NRBMAX <= 16 ? 512 : 256;
+  constexpr int NW = NT / 64;
+  const size_t lds = (size_t)(2 * Np * LDY + 3 * Np + 2 * 16 * LDY + 2 * NW + 2 * NW * 17) * sizeof(double) +
+                     (size_t)(3 * Np + NW + 2) * sizeof(int);
+  hipLaunchKernelGGL((lu_k<NRBMAX, NT>), dim3(nb), dim3(NT), lds, st, QT, V, logD, qsign, st_in, LU,
                      prow, DI, item_of, lo, so, sto, N, Np);
   return hipGetLastError();
 }

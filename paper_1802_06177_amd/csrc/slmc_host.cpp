@@ -459,6 +459,23 @@ size_t group_bytes(const slmc_model* m, int nb) {
   return a.used;
 }
 
+// Whether a group's items need the item tables (field / G offsets, item map) uploaded into
+// the workspace: only when they are not one contiguous, constant-stride range.
+bool group_needs_tables(const slmc_model* m, const Group& grp, const slmc_batch* batch, bool with_G) {
+  const int nb = (int)grp.items.size(), N = m->Lx * m->Ly;
+  const int i0 = grp.items[0];
+  const int64_t xn = (int64_t)m->Ltau * N;
+  auto xo = [&](int item) { return batch->x_off ? batch->x_off[item] : (int64_t)item * xn; };
+  auto go = [&](int item) { return batch->g_off ? batch->g_off[item] : (int64_t)item * N * N; };
+  bool contiguous = true, x_aff = true, g_aff = true;
+  for (int j = 0; j < nb; ++j) {
+    contiguous &= (grp.items[j] == i0 + j);
+    x_aff &= (xo(grp.items[j]) == xo(i0) + (int64_t)j * xn);
+    g_aff &= (go(grp.items[j]) == go(i0) + (int64_t)j * N * N);
+  }
+  return !x_aff || !contiguous || (with_G && !g_aff);
+}
+
 // The hot path for one group of items sharing a model.
 int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, const slmc_batch* batch,
               const double* x, double* logdet, int8_t* sign, double* G, int32_t* status,
@@ -496,7 +513,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   int32_t* st_out = status + (contiguous ? i0 : 0);
   double* g_out = G ? G + go(i0) : nullptr;
   const int64_t* goff = nullptr;
-  if (!x_aff || !contiguous || (G && !g_aff)) {
+  if (group_needs_tables(m, grp, batch, G != nullptr)) {
     std::vector<int64_t> xv(nb), gv(nb);
     std::vector<int> iv(nb);
     for (int j = 0; j < nb; ++j) { xv[j] = xo(grp.items[j]); gv[j] = go(grp.items[j]); iv[j] = grp.items[j]; }
@@ -699,9 +716,12 @@ int fermion_call(const slmc_model* models, int32_t n_models, const slmc_batch* b
     return fail(SLMC_E_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
   Arena a(ws);
   hipStream_t st = (hipStream_t)stream;
-  // a packed batch may need item tables uploaded into the workspace (synchronous copies),
-  // which kernels of an earlier call on this stream may still read
-  if (batch->model_idx || batch->x_off || batch->g_off) HIPCHK(hipStreamSynchronize(st));
+  // a packed batch whose items are not constant-stride ranges uploads item tables into the
+  // workspace (synchronous copies), which kernels of an earlier call on this stream may
+  // still read; affine batches pass their offsets in kernel arguments and do not wait
+  bool uploads = false;
+  for (auto& g : groups) uploads |= group_needs_tables(&models[g.model], g, batch, G != nullptr);
+  if (uploads) HIPCHK(hipStreamSynchronize(st));
   for (auto& g : groups) {
     const slmc_model* m = &models[g.model];
     GroupBufs w;
