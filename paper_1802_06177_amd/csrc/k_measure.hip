@@ -119,18 +119,24 @@ __global__ __launch_bounds__(256) void prop_gemm_k(const double* __restrict__ A,
 }
 
 // Per (item, slice): s_nn = N m^2 + (2/N)(tr G - q), m = (2/N) sum_i p_i (1 - G_ii),
-// q = sum_ij p_i p_j G_ij G_ji.  One workgroup of 256 threads per G; tile pairs in a fixed
-// order, partial sums reduced in a fixed order.
-__global__ __launch_bounds__(256) void cdw_k(const double* __restrict__ G, int64_t sg, int Lx, int N,
-                                             double* __restrict__ s_nn, double* __restrict__ m_st,
-                                             int64_t so) {
+// q = sum_ij p_i p_j G_ij G_ji.  The 16x16 tile pairs (I, J >= I) are spread over
+// ceil(nt/2) workgroups per item, workgroup k taking the tile rows I = k and I = nt-1-k
+// (nt + 1 pairs each: balanced); each writes its three partial sums, reduced in a fixed
+// order, and cdw_fin_k adds the partials of an item in order.
+constexpr int CDW_MAXG = 14;   // workgroups per item: ceil(nt/2) for N <= 448
+
+__global__ __launch_bounds__(256) void cdw_part_k(const double* __restrict__ G, int64_t sg, int Lx,
+                                                  int N, double* __restrict__ part) {
   __shared__ double T1[16][17], T2[16][17];
   __shared__ double red[3][4];
-  const int b = blockIdx.x, tid = threadIdx.x, r = tid >> 4, cc = tid & 15;
+  const int nt = (N + 15) / 16, ng = (nt + 1) / 2;
+  const int b = blockIdx.x / ng, k = blockIdx.x - b * ng;
+  const int tid = threadIdx.x, r = tid >> 4, cc = tid & 15;
   const double* Gb = G + b * sg;
-  const int nt = (N + 15) / 16;
   double q = 0.0, tr = 0.0, d = 0.0;
-  for (int I = 0; I < nt; ++I) {
+  for (int h = 0; h < 2; ++h) {
+    const int I = h == 0 ? k : nt - 1 - k;
+    if (h == 1 && I == k) break;
     for (int J = I; J < nt; ++J) {
       const int i = 16 * I + r, j = 16 * J + cc, i2 = 16 * J + r, j2 = 16 * I + cc;
       T1[r][cc] = (i < N && j < N) ? Gb[(int64_t)i * N + j] : 0.0;     // G[I-tile][J-tile]
@@ -157,14 +163,28 @@ __global__ __launch_bounds__(256) void cdw_k(const double* __restrict__ G, int64
   }
   if ((tid & 63) == 0) { red[0][tid >> 6] = q; red[1][tid >> 6] = tr; red[2][tid >> 6] = d; }
   __syncthreads();
-  if (tid == 0) {
-    const double Q = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-    const double TR = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
-    const double D = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
-    const double m = 2.0 * D / N;
-    s_nn[b * so] = N * m * m + 2.0 * (TR - Q) / N;
-    m_st[b * so] = m;
+  if (tid < 3) {
+    double* pp = part + ((int64_t)b * CDW_MAXG + k) * 3;
+    pp[tid] = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
   }
+}
+
+__global__ __launch_bounds__(256) void cdw_fin_k(const double* __restrict__ part, int nb, int N,
+                                                 double* __restrict__ s_nn, double* __restrict__ m_st,
+                                                 int64_t so) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int ng = ((N + 15) / 16 + 1) / 2;
+  const double* pp = part + (int64_t)b * CDW_MAXG * 3;
+  double Q = 0.0, TR = 0.0, D = 0.0;
+  for (int k = 0; k < ng; ++k) {
+    Q += pp[3 * k];
+    TR += pp[3 * k + 1];
+    D += pp[3 * k + 2];
+  }
+  const double m = 2.0 * D / N;
+  s_nn[b * so] = N * m * m + 2.0 * (TR - Q) / N;
+  m_st[b * so] = m;
 }
 
 // dst[b sd + e] = src[b ss + e], e < n (batched copy with item strides)
@@ -211,8 +231,13 @@ hipError_t launch_propagate(const double* Gin, int64_t sgin, double* Gout, int64
 }
 
 hipError_t launch_cdw(const double* G, int64_t sg, int nb, int Lx, int N, double* s_nn, double* m_st,
-                      int64_t so, hipStream_t st) {
-  hipLaunchKernelGGL(cdw_k, dim3(nb), dim3(256), 0, st, G, sg, Lx, N, s_nn, m_st, so);
+                      int64_t so, double* part, hipStream_t st) {
+  const int ng = ((N + 15) / 16 + 1) / 2;
+  if (ng > CDW_MAXG) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cdw_part_k, dim3(nb * ng), dim3(256), 0, st, G, sg, Lx, N, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cdw_fin_k, dim3((nb + 255) / 256), dim3(256), 0, st, part, nb, N, s_nn, m_st, so);
   return hipGetLastError();
 }
 

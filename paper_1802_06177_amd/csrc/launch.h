@@ -127,7 +127,7 @@ hipError_t launch_propagate(const double* Gin, int64_t sgin, double* Gout, int64
                             hipStream_t st);
 // s_nn[b so], m_st[b so] of G + b sg (N x N, row-major)
 hipError_t launch_cdw(const double* G, int64_t sg, int nb, int Lx, int N, double* s_nn, double* m_st,
-                      int64_t so, hipStream_t st);
+                      int64_t so, double* part, hipStream_t st);
 // dst[b sd + e] = src[b ss + e] for e < n, b < nb
 hipError_t launch_copy_items(const double* src, int64_t ss, double* dst, int64_t sd, int64_t n, int nb,
                              hipStream_t st);

@@ -753,6 +753,7 @@ size_t slices_bytes(const slmc_model* m, int nb) {
   size_t b = group_bytes(m, nb);
   b += align256((size_t)nb * N * m->Ltau * 8) + 3 * align256((size_t)nb * nn * 8);
   b += 3 * align256((size_t)nb * 8);
+  b += align256((size_t)nb * 14 * 3 * 8);   // CDW partial sums (14 workgroups per item at most)
   return b;
 }
 
@@ -1034,6 +1035,7 @@ int slmc_green_slices(const slmc_model* model, const slmc_options* opt, int32_t 
   double* ld = a.take<double>(n_items);
   int8_t* sg = (int8_t*)a.take<int>(n_items);
   int32_t* sta = a.take<int32_t>(n_items);
+  double* cpart = a.take<double>((size_t)n_items * 14 * 3);
   hipStream_t st = (hipStream_t)stream;
   Group grp{0, {}};
   for (int b = 0; b < n_items; ++b) grp.items.push_back(b);
@@ -1063,7 +1065,7 @@ int slmc_green_slices(const slmc_model* model, const slmc_options* opt, int32_t 
       HIPCHK(launch_copy_items(ga.first, nn, G_all + (int64_t)anchor * nn, (int64_t)Lt * nn, nn,
                                n_items, st));
     }
-    HIPCHK(launch_cdw(ga.first, ga.second, n_items, model->Lx, N, s_nn + anchor, m_st + anchor, Lt, st));
+    HIPCHK(launch_cdw(ga.first, ga.second, n_items, model->Lx, N, s_nn + anchor, m_st + anchor, Lt, cpart, st));
     // propagate through the block: slices r .. min(r + n_wrap, Lt) - 2
     auto prev = ga;
     for (int l = r; l <= std::min(r + n_wrap, Lt) - 2; ++l) {
@@ -1071,7 +1073,7 @@ int slmc_green_slices(const slmc_model* model, const slmc_options* opt, int32_t 
       auto gn = gslot(l, pp);
       HIPCHK(launch_propagate(prev.first, prev.second, gn.first, gn.second, T, mc->E64, mc->Einv,
                               mc->Np, x, l, ldl, n_items, N, Lt, st));
-      HIPCHK(launch_cdw(gn.first, gn.second, n_items, model->Lx, N, s_nn + l, m_st + l, Lt, st));
+      HIPCHK(launch_cdw(gn.first, gn.second, n_items, model->Lx, N, s_nn + l, m_st + l, Lt, cpart, st));
       prev = gn;
     }
     pp ^= 1;
