@@ -48,9 +48,9 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "int8x5": 15}   # pe
 # (factors 2.0 and 1.0).  They are not measured by this script: they are read from the
 # committed summary named in TRAFFIC_SOURCE and are valid only for the kernel versions it
 # was taken on (the bench line carries the source with the figure).
-TRAFFIC = {("qr", "int8x5"): 619.7e6, ("seg_chain", "int8x5"): 82.5e6}
+TRAFFIC = {("qr", "int8x5"): 619.8e6, ("seg_chain", "int8x5"): 82.4e6, ("lu", "int8x5"): 687.4e6}
 TRAFFIC_SOURCE = ("profiles/fermion_step_16x16_ltau160_int8x5_128chains.md (rocprofv3 --pmc "
-                  "FETCH_SIZE / WRITE_SIZE of the seg_chain_i8 and qr_k kernels as committed in 28bbe9a)")
+                  "FETCH_SIZE / WRITE_SIZE of the seg_chain_i8, qr_k and lu_k kernels as of commit 4e3c7fb)")
 
 
 def run(slmc, torch, md, eff, xs, B, prec, args):
@@ -183,16 +183,19 @@ def uneven_rates(slmc, torch, np, prec, reps=3):
 
 
 def _timed(torch, fn, reps):
-    """Seconds per call of fn from HIP events (one untimed call first)."""
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    """Seconds per call of fn from HIP events (one untimed call first): the median over
+    reps calls, each between its own pair of events, so that a stall of the host between
+    two launches of one call does not stand for the call's time."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     fn()
     torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(reps):
+    for e0, e1 in evs:
+        e0.record()
         fn()
-    ev1.record()
+        e1.record()
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / 1e3 / reps
+    ts = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in evs)
+    return ts[len(ts) // 2]
 
 
 def _green_all(slmc, torch, np, md, xs, prec, resid, chunk=0, reps=10):
