@@ -36,6 +36,11 @@ def _E(md):
     (4, 4, 12, 4, 3, 1.0, 3),      # propagated between evaluations
     (2, 3, 10, 5, 10, 1.5, 2),     # propagated through the whole sweep
     (8, 8, 40, 10, 10, 0.8, 2),
+    # above N = 64 the delayed updates: 32 kept (a flush after every 32 accepts and at the
+    # end of each slice), 16 at N = 272 where 32 do not fit in LDS
+    (10, 10, 8, 4, 4, 0.8, 1),
+    (16, 16, 4, 2, 4, 0.8, 1),
+    (17, 16, 2, 1, 2, 0.8, 1),
 ])
 def test_local_sweep_matches_oracle(Lx, Ly, Ltau, n_s, n_rec, delta, chains):
     md = _md(Lx, Ly, Ltau, n_s, mu=0.05)
