@@ -357,18 +357,31 @@ __device__ __forceinline__ void load_block(dx4 (&blk)[NRBMAX], int nrbK, const d
   }
 }
 
-// blk <- (I - Y T Y^T)^T blk for the panel (Y in Pn, T in Tl).
+// blk <- (I - Y T Y^T)^T blk for the panel (Y in Pn, T in Tl).  Only the top row block of
+// Y needs the unit-lower masking; the Y values of the next row block (pair) are read from
+// LDS while the current one's products issue, and the update runs over pairs of row
+// blocks so that consecutive matrix-core instructions go to independent accumulators.
+// Every accumulator sees its products in the same order as a plain loop would.
 template <int NRBMAX>
 __device__ __forceinline__ void apply_panel(dx4 (&blk)[NRBMAX], int nrbK, const double* Pn,
                                             const double* Tl, int g, int c) {
   // W = Y^T blk: four independent accumulators (one per k-step) keep the pipe full
   dx4 aw[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
+  double yn[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) yn[s] = yval(Pn, drow64(g, s), c);
 #pragma unroll
   for (int rb = 0; rb < NRBMAX; ++rb) {
     if (rb < nrbK) {
+      double yc[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        aw[s] = mfma64(yval(Pn, 16 * rb + drow64(g, s), c), blk[rb][s], aw[s]);
+      for (int s = 0; s < 4; ++s) yc[s] = yn[s];
+      if (rb + 1 < nrbK) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) yn[s] = Pn[(16 * (rb + 1) + drow64(g, s)) * LDY + c];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) aw[s] = mfma64(yc[s], blk[rb][s], aw[s]);
     }
   }
   const dx4 W = aw[0] + aw[1] + aw[2] + aw[3];
@@ -378,12 +391,38 @@ __device__ __forceinline__ void apply_panel(dx4 (&blk)[NRBMAX], int nrbK, const 
   dx4 Wt = zero4d();
 #pragma unroll
   for (int s = 0; s < 4; ++s) Wt = mfma64(tv[s], W[s], Wt);
-  // blk -= Y W': consecutive instructions go to different row blocks
+  // blk -= Y W', row blocks in pairs: for each k-step s the two blocks' products in turn
+  double qa[4], qb[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
+    qa[s] = -yval(Pn, c, drow64(g, s));
+    qb[s] = 0.0;
+    if (1 < nrbK) qb[s] = -Pn[(16 + c) * LDY + drow64(g, s)];
+  }
 #pragma unroll
-    for (int rb = 0; rb < NRBMAX; ++rb) {
-      if (rb < nrbK) blk[rb] = mfma64(-yval(Pn, 16 * rb + c, drow64(g, s)), Wt[s], blk[rb]);
+  for (int rb = 0; rb < NRBMAX; rb += 2) {
+    if (rb < nrbK) {
+      double ca[4], cb[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) { ca[s] = qa[s]; cb[s] = qb[s]; }
+      if (rb + 2 < nrbK) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) qa[s] = -Pn[(16 * (rb + 2) + c) * LDY + drow64(g, s)];
+        if (rb + 3 < nrbK) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) qb[s] = -Pn[(16 * (rb + 3) + c) * LDY + drow64(g, s)];
+        }
+      }
+      if (rb + 1 < nrbK) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          blk[rb] = mfma64(ca[s], Wt[s], blk[rb]);
+          if (rb + 1 < NRBMAX) blk[rb + 1] = mfma64(cb[s], Wt[s], blk[rb + 1]);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) blk[rb] = mfma64(ca[s], Wt[s], blk[rb]);
+      }
     }
   }
 }
@@ -453,12 +492,21 @@ __device__ __forceinline__ void update_block_chunked(int nrbK, int j0, int cb, b
         for (int v = 0; v < 4; ++v) blk[rb][v] = src[(16 * (r0 + rb) + drow64(g, v)) * Np];
       }
     }
+    double yn[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) yn[s] = yval(Pc, 16 * r0 + drow64(g, s), c);
 #pragma unroll
     for (int rb = 0; rb < CH; ++rb) {
       if (r0 + rb < nrbK) {
+        double yc[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          aw[s] = mfma64(yval(Pc, 16 * (r0 + rb) + drow64(g, s), c), blk[rb][s], aw[s]);
+        for (int s = 0; s < 4; ++s) yc[s] = yn[s];
+        if (rb + 1 < CH && r0 + rb + 1 < nrbK) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) yn[s] = Pc[(16 * (r0 + rb + 1) + drow64(g, s)) * LDY + c];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) aw[s] = mfma64(yc[s], blk[rb][s], aw[s]);
       }
     }
   }
@@ -529,14 +577,27 @@ __device__ __forceinline__ void apply_block_split(dx4 (&blk)[RBQ], int nrbK, int
   int c = lane & 15, g = lane >> 4;
   __asm__ volatile("" : "+v"(c), "+v"(g));
   double* dst = Q + (size_t)j0 * Np + 16 * cb + c;
+  // (the Y values of the next row block are read from LDS while the current one's products
+  // issue; same products, same order per accumulator)
   dx4 aw[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
+  double yn[4] = {0.0, 0.0, 0.0, 0.0};
+  if (w < nrbK) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) yn[s] = yval(Pc, 16 * w + drow64(g, s), c);
+  }
 #pragma unroll
   for (int r = 0; r < RBQ; ++r) {
     const int rb = w + QR_PANEL_WAVES * r;
     if (rb < nrbK) {
+      double yc[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        aw[s] = mfma64(yval(Pc, 16 * rb + drow64(g, s), c), blk[r][s], aw[s]);
+      for (int s = 0; s < 4; ++s) yc[s] = yn[s];
+      if (rb + QR_PANEL_WAVES < nrbK) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) yn[s] = Pc[(16 * (rb + QR_PANEL_WAVES) + drow64(g, s)) * LDY + c];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) aw[s] = mfma64(yc[s], blk[r][s], aw[s]);
     }
   }
   const dx4 Wp = aw[0] + aw[1] + aw[2] + aw[3];
@@ -551,12 +612,22 @@ __device__ __forceinline__ void apply_block_split(dx4 (&blk)[RBQ], int nrbK, int
   dx4 Wt = zero4d();
 #pragma unroll
   for (int s = 0; s < 4; ++s) Wt = mfma64(tv[s], W[s], Wt);
+  // blk -= Y W': this wave's row blocks, their Y values read up front
+  double ya[RBQ][4];
+#pragma unroll
+  for (int r = 0; r < RBQ; ++r) {
+    const int rb = w + QR_PANEL_WAVES * r;
+    if (rb < nrbK) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ya[r][s] = -yval(Pc, 16 * rb + c, drow64(g, s));
+    }
+  }
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
 #pragma unroll
     for (int r = 0; r < RBQ; ++r) {
       const int rb = w + QR_PANEL_WAVES * r;
-      if (rb < nrbK) blk[r] = mfma64(-yval(Pc, 16 * rb + c, drow64(g, s)), Wt[s], blk[r]);
+      if (rb < nrbK) blk[r] = mfma64(ya[r][s], Wt[s], blk[r]);
     }
   }
 #pragma unroll
