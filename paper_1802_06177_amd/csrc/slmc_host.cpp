@@ -53,12 +53,14 @@ struct ProfScope {
 thread_local std::string g_err;
 
 // Library-owned side streams per device (default priority) and the events that order
-// them against the caller's stream: s runs the segment products, s2 the V updates.
+// them against the caller's stream: s runs the segment products, s2 the V updates, s3 the
+// smaller lattices of a packed call of several models (beside the largest one's chain).
 // g_side_mu is held while a call enqueues on them, so the events are never re-recorded
 // before the waits on them are enqueued.
 struct SideStream {
-  hipStream_t s = nullptr, s2 = nullptr;
+  hipStream_t s = nullptr, s2 = nullptr, s3 = nullptr;
   std::vector<hipEvent_t> ev;
+  hipEvent_t fork3 = nullptr, join3 = nullptr;
 };
 std::mutex g_side_mu;
 std::map<int, SideStream> g_side;
@@ -87,6 +89,9 @@ int side_stream_locked(int nev, SideStream** out) {
   SideStream& ss = g_side[dev];
   if (!ss.s) HIPCHK(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
   if (!ss.s2) HIPCHK(hipStreamCreateWithFlags(&ss.s2, hipStreamNonBlocking));
+  if (!ss.s3) HIPCHK(hipStreamCreateWithFlags(&ss.s3, hipStreamNonBlocking));
+  if (!ss.fork3) HIPCHK(hipEventCreateWithFlags(&ss.fork3, hipEventDisableTiming));
+  if (!ss.join3) HIPCHK(hipEventCreateWithFlags(&ss.join3, hipEventDisableTiming));
   while ((int)ss.ev.size() < nev) {
     hipEvent_t e = nullptr;
     HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -722,12 +727,54 @@ int fermion_call(const slmc_model* models, int32_t n_models, const slmc_batch* b
   bool uploads = false;
   for (auto& g : groups) uploads |= group_needs_tables(&models[g.model], g, batch, G != nullptr);
   if (uploads) HIPCHK(hipStreamSynchronize(st));
-  for (auto& g : groups) {
-    const slmc_model* m = &models[g.model];
-    GroupBufs w;
-    carve(a, (int)g.items.size(), roundup16(m->Lx * m->Ly), (m->Ltau + m->n_s - 1) / m->n_s, w);
-    rc = run_group(m, opt, g, batch, x, logdet, sign, G, status, w, st);
+  std::vector<GroupBufs> bufs(groups.size());
+  for (size_t k = 0; k < groups.size(); ++k) {
+    const slmc_model* m = &models[groups[k].model];
+    carve(a, (int)groups[k].items.size(), roundup16(m->Lx * m->Ly), (m->Ltau + m->n_s - 1) / m->n_s, bufs[k]);
+  }
+  // Several models: the one with the longest sequential chain (stabilization blocks times
+  // the QR's columns) runs with its own schedule on the caller's stream, the others one
+  // after another in the serial schedule on a third library stream beside it (forked from
+  // and joined back to the caller's stream), so that the smaller lattices fill the compute
+  // units the large one's chain leaves idle.  Results are those of any other schedule.
+  int big = -1;
+  if (groups.size() > 1 && !(opt->flags & SLMC_FLAG_SERIAL)) {
+    int64_t best = -1;
+    for (size_t k = 0; k < groups.size(); ++k) {
+      const slmc_model* m = &models[groups[k].model];
+      const int64_t len = (int64_t)((m->Ltau + m->n_s - 1) / m->n_s) * roundup16(m->Lx * m->Ly);
+      if (len > best) { best = len; big = (int)k; }
+    }
+  }
+  if (big < 0) {
+    for (size_t k = 0; k < groups.size(); ++k) {
+      rc = run_group(&models[groups[k].model], opt, groups[k], batch, x, logdet, sign, G, status, bufs[k], st);
+      if (rc) return rc;
+    }
+    return SLMC_OK;
+  }
+  SideStream* ss = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    rc = side_stream_locked(1, &ss);
     if (rc) return rc;
+    HIPCHK(hipEventRecord(ss->fork3, st));
+    HIPCHK(hipStreamWaitEvent(ss->s3, ss->fork3, 0));
+  }
+  TuneCfg serial_cfg;
+  serial_cfg.sched = 3;
+  for (size_t k = 0; k < groups.size(); ++k) {
+    if ((int)k == big) continue;
+    rc = run_group(&models[groups[k].model], opt, groups[k], batch, x, logdet, sign, G, status, bufs[k],
+                   ss->s3, nullptr, &serial_cfg);
+    if (rc) return rc;
+  }
+  rc = run_group(&models[groups[big].model], opt, groups[big], batch, x, logdet, sign, G, status, bufs[big], st);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    HIPCHK(hipEventRecord(ss->join3, ss->s3));
+    HIPCHK(hipStreamWaitEvent(st, ss->join3, 0));
   }
   return SLMC_OK;
 }
@@ -1594,9 +1641,13 @@ void slmc_cache_clear(void) {
     (void)hipSetDevice(kv.first);
     if (kv.second.s) (void)hipStreamSynchronize(kv.second.s);
     if (kv.second.s2) (void)hipStreamSynchronize(kv.second.s2);
+    if (kv.second.s3) (void)hipStreamSynchronize(kv.second.s3);
     for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
+    if (kv.second.fork3) (void)hipEventDestroy(kv.second.fork3);
+    if (kv.second.join3) (void)hipEventDestroy(kv.second.join3);
     if (kv.second.s) (void)hipStreamDestroy(kv.second.s);
     if (kv.second.s2) (void)hipStreamDestroy(kv.second.s2);
+    if (kv.second.s3) (void)hipStreamDestroy(kv.second.s3);
     (void)hipSetDevice(cur);
   }
   g_side.clear();
