@@ -100,7 +100,10 @@ typedef struct {
  * joined back to the caller's stream with events, so that the sequential QR chain
  * overlaps the remaining segment products and the V updates (for SLMC_INT8X5 and
  * SLMC_BF16X3 released step by step into the time of each QR, otherwise queued up
- * front).  Results are identical either way; calls from several host threads on one
+ * front; the autotuner may choose otherwise per model, precision and batch size).  In a
+ * packed call of several models, the model with the longest chain runs so on the caller's
+ * stream while the other models run one after another in the serial schedule on a third
+ * library stream beside it.  Results are identical either way; calls from several host threads on one
  * device serialize while they enqueue.  A call on one model can be captured into a HIP
  * graph on the caller's stream (the library's streams fork from it and join back through
  * events; no memset, no host synchronization); a packed call whose items are not laid out
