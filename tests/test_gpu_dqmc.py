@@ -41,6 +41,7 @@ def _E(md):
     (10, 10, 8, 4, 4, 0.8, 1),
     (16, 16, 4, 2, 4, 0.8, 1),
     (17, 16, 2, 1, 2, 0.8, 1),
+    (21, 21, 2, 1, 2, 0.8, 1),     # the largest lattice (N = 441, LDS rows padded to 448)
 ])
 def test_local_sweep_matches_oracle(Lx, Ly, Ltau, n_s, n_rec, delta, chains):
     md = _md(Lx, Ly, Ltau, n_s, mu=0.05)

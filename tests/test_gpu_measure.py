@@ -95,6 +95,14 @@ def test_propagated_slices_match_oracle(Lx, Ly, Ltau, n_s, n_wrap):
     _check(md, xs, n_wrap, "fp64", 1e-9)
 
 
+def test_largest_lattice_slices_match_oracle():
+    # N = 441: the CDW estimators over 14 workgroups per item (their upper limit), ragged
+    # 64x64 propagation tiles (441 = 6 x 64 + 57), two anchors and two propagated slices
+    md = _md(21, 21, 4, 2)
+    xs = [gen(404, 21).normal(0.0, 1.0, size=(4, 441))]
+    _check(md, xs, 2, "fp64", 1e-9)
+
+
 def test_int8x5_slices_match_oracle():
     md = _md(8, 8, 40, 10)
     xs = [gen(403, k).normal(0.0, 1.0, size=(40, 64)) for k in range(2)]
