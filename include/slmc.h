@@ -103,11 +103,12 @@ typedef struct {
  * front; the autotuner may choose otherwise per model, precision and batch size).  In a
  * packed call of several models, the model with the longest chain runs so on the caller's
  * stream while the other models run one after another in the serial schedule on a third
- * library stream beside it.  Results are identical either way; calls from several host threads on one
- * device serialize while they enqueue.  A call on one model can be captured into a HIP
- * graph on the caller's stream (the library's streams fork from it and join back through
- * events; no memset, no host synchronization); a packed call whose items are not laid out
- * at a constant stride uploads its item tables synchronously and cannot be captured. */
+ * library stream beside it (also forked and joined with events).  Results are identical either way; calls from several host threads on one
+ * device serialize while they enqueue.  A call can be captured into a HIP graph on the
+ * caller's stream (the library's streams fork from it and join back through events; no
+ * memset, no host synchronization) when the items of each model are contiguous and laid
+ * out at a constant stride; a packed call whose items are not uploads its item tables
+ * synchronously and cannot be captured. */
 enum slmc_flags {
   SLMC_FLAG_SERIAL = 1,  /* run every kernel on the caller's stream, in order           */
   SLMC_FLAG_STREAM_E = 2 /* SLMC_INT8X5: read every E slice from device memory in each

@@ -1,4 +1,5 @@
-"""HIP-graph capture of one evaluation call (single model) and of a whole SLMC step: the
+"""HIP-graph capture of one evaluation call (single model, and a packed call of two models at
+constant strides) and of a whole SLMC step: the
 library forks its side streams from the caller's stream with events and joins them back,
 clears with a kernel rather than a memset and does no host synchronization on these paths,
 so the calls can be captured and replayed.  Every replay is checked bitwise against the
@@ -137,3 +138,62 @@ def test_slmc_step_replays_from_a_captured_graph(prec):
                   opt, ws=ws_e)
         torch.cuda.synchronize()
     assert int(cg.item()) == c0 + K
+
+
+@pytest.mark.parametrize("prec", ["fp64", "int8x5"])
+def test_packed_constant_stride_call_replays_from_a_captured_graph(prec):
+    # a packed call of two models whose items are laid out model by model at constant
+    # strides: no item table is uploaded and nothing waits on the host, so the call (the
+    # larger model's overlapped schedule on the caller's stream, the other model serially
+    # on a third library stream) can be captured and replayed
+    from synth import gen
+    mds = [dict(Lx=8, Ly=8, Ltau=40, n_s=10, t=1.0, mu=0.0, dtau=0.1, lam=1.5, omega0=1.0, c_kin=0.5),
+           dict(Lx=4, Ly=6, Ltau=30, n_s=10, t=1.0, mu=0.1, dtau=0.1, lam=1.2, omega0=1.0, c_kin=0.5)]
+    models = [slmc.model_from_dict(d) for d in mds]
+    counts = [3, 4]
+    midx = [0] * counts[0] + [1] * counts[1]
+    xs_sz = [d["Ltau"] * d["Lx"] * d["Ly"] for d in mds]
+    gs_sz = [(d["Lx"] * d["Ly"]) ** 2 for d in mds]
+    x_off = np.cumsum([0] + [xs_sz[k] for k in midx[:-1]])
+    g_off = np.cumsum([0] + [gs_sz[k] for k in midx[:-1]])
+    nx, ng = int(sum(xs_sz[k] for k in midx)), int(sum(gs_sz[k] for k in midx))
+    opt = slmc.options(prec, 1)
+    nbytes = slmc.workspace_bytes(models, len(midx), opt, model_idx=midx, x_off=x_off, g_off=g_off)
+
+    def fields(seed):
+        return np.concatenate([gen(seed, b).normal(0.0, 1.0, size=xs_sz[k]) for b, k in enumerate(midx)])
+
+    xa, xb = fields(811), fields(812)
+    # eager references on buffers of their own
+    ws_e = torch.empty(nbytes, dtype=torch.uint8, device=DEV)
+    refs = []
+    for xv in (xa, xb):
+        Ge = torch.empty(ng, dtype=torch.float64, device=DEV)
+        out = slmc.green(models, torch.tensor(xv, dtype=torch.float64, device=DEV), opt, model_idx=midx,
+                         x_off=x_off, g_off=g_off, n_items=len(midx), G=Ge, ws=ws_e)
+        refs.append(_host(out))
+    torch.cuda.synchronize()
+    assert np.all(refs[0][3] == 0) and np.all(refs[1][3] == 0)
+    x = torch.tensor(xa, dtype=torch.float64, device=DEV)
+    G = torch.empty(ng, dtype=torch.float64, device=DEV)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=DEV)
+    torch.cuda.synchronize()
+    print("case: capture packed 8x8 + 4x6 prec=%s" % prec, flush=True)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out = slmc.green(models, x, opt, model_idx=midx, x_off=x_off, g_off=g_off, n_items=len(midx),
+                         G=G, ws=ws)
+    torch.cuda.synchronize()
+    for r, xv in enumerate((xa, xb, xa, xb)):
+        print("case: replay %d" % r, flush=True)
+        x.copy_(torch.tensor(xv, dtype=torch.float64, device=DEV))
+        graph.replay()
+        torch.cuda.synchronize()
+        got = _host(out)
+        for u, v in zip(got, refs[r % 2]):
+            assert np.array_equal(u, v)
+        # eager work between the replays
+        slmc.green(models, torch.tensor(xb, dtype=torch.float64, device=DEV), opt, model_idx=midx,
+                   x_off=x_off, g_off=g_off, n_items=len(midx),
+                   G=torch.empty(ng, dtype=torch.float64, device=DEV), ws=ws_e)
+        torch.cuda.synchronize()
