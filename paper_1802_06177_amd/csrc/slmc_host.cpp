@@ -591,7 +591,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   // ev[2 mseg+1+k] V update k done (s2), ev[3 mseg+1+k] wy_apply k done (st),
   // ev[4 mseg+1+k] gate k passed (s).  QR k reuses the buffers that V update k - kQB
   // reads, so step k waits for it (with the wait for segment k, before wy_apply k).
-  const int kSegAhead = std::max(1, std::min(3, cfg.ahead));
+  const int kSegAhead = std::max(1, std::min(8, cfg.ahead));
   constexpr int kQB = GroupBufs::kQB;
   hipEvent_t* ev_qr = overlap ? &ss->ev[mseg + 1] : nullptr;
   hipEvent_t* ev_vu = overlap ? &ss->ev[2 * mseg + 1] : nullptr;
@@ -1535,7 +1535,7 @@ int slmc_autotune(const slmc_model* model, const slmc_options* opt, int32_t n_it
       sch.push_back(c);
       continue;
     }
-    for (int ahead = 1; ahead <= 3; ++ahead)
+    for (int ahead : {1, 2, 3, 4, 6, 8})
       for (int gate = 0; gate <= 1; ++gate) {
         TuneCfg c = best;
         c.sched = 2;
