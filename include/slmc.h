@@ -364,7 +364,8 @@ int slmc_step(const slmc_model* model, const slmc_eff* eff, const slmc_options* 
 /* The schedule and tile choices of one model, precision and batch size (the batch size
  * rounded up to a power of two): schedule 0 the default per precision (step-by-step
  * release of the side work, "gated", for SLMC_INT8X5 and SLMC_BF16X3; everything queued
- * up front, "eager", otherwise), 1 eager, 2 gated, 3 serial (as SLMC_FLAG_SERIAL); seg_ahead
+ * up front, "eager", otherwise), 1 eager, 2 gated, 3 serial (as SLMC_FLAG_SERIAL), 4 gated
+ * with each V update queued behind the segment block on the same library stream; seg_ahead
  * 1-8 segment blocks released ahead of the chain (gated); gate 0/1 an empty kernel in front
  * of the gated side work; seg_mode (SLMC_INT8X5) 0 A operands in registers where E's
  * translation symmetry allows, 1 E's base rows in LDS only, 2 E streamed from memory;
@@ -381,8 +382,8 @@ typedef struct {
  * precision and batch size; later slmc_logdet / slmc_green / accept calls that match use
  * it (calls on other batch sizes keep the defaults).  Candidates are tried coordinate by
  * coordinate: the segment kernel's variant under the default schedule (int8x5: seg_mode
- * x seg_cb; FP64: seg_cb), then the schedule (serial, eager, gated with seg_ahead 1, 2, 3, 4, 6 or 8 and
- * gate 0/1).  Each candidate's log-dets, signs and statuses are compared bitwise with the
+ * x seg_cb; FP64: seg_cb), then the schedule (serial, eager, gated or gated with the V updates behind the
+ * segment blocks, each with seg_ahead 1, 2, 3, 4, 6 or 8 and gate 0/1).  Each candidate's log-dets, signs and statuses are compared bitwise with the
  * default's before it is timed (one warm call, then 3 timed calls, HIP events on
  * `stream`); a candidate that differs is rejected.  The fastest is timed against the
  * default once more, alternating, and kept only if at least 2% faster.  Synchronous (it waits for `stream`).

@@ -417,7 +417,7 @@ def step(m, eff, x_cur, x_prop, logw_cur, eeff_cur, n_sweeps, n_clusters, seed, 
     return out
 
 
-SCHEDULES = {0: "default", 1: "eager", 2: "gated", 3: "serial"}
+SCHEDULES = {0: "default", 1: "eager", 2: "gated", 3: "serial", 4: "gated, V behind segments"}
 
 
 def _tuning_dict(t):

@@ -308,7 +308,8 @@ int get_consts(const slmc_model* m, ModelConsts** out) {
 
 // ---- schedule and tile choices, and the autotuner's cache ------------------------------
 // sched: 0 the default per precision (gated for int8x5 and bf16x3, eager otherwise), 1
-// eager, 2 gated, 3 serial; ahead: segment blocks released ahead of the chain (gated);
+// eager, 2 gated, 3 serial, 4 gated with each V update queued behind the segment block on
+// the same side stream (the segment block then has the free CUs to itself); ahead: segment blocks released ahead of the chain (gated);
 // gate: the empty gate kernel in front of the gated side work; seg_mode, seg_cb: the
 // segment kernel's variant (launch.h).  Every choice gives bitwise the same results.
 struct TuneCfg {
@@ -550,8 +551,9 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
   // a QR on the CUs it leaves free (by default int8x5, bf16x3); the heavier FP64, FP32 and
   // bf16x6 segment products are all released at once instead and fill the chip from the
   // start (the autotuner may choose otherwise per model, precision and batch)
-  const bool gated = overlap && (cfg.sched == 2 ||
+  const bool gated = overlap && (cfg.sched == 2 || cfg.sched == 4 ||
                                  (cfg.sched == 0 && (o->precision == SLMC_INT8X5 || o->precision == SLMC_BF16X3)));
+  const bool v_behind = gated && cfg.sched == 4;
   std::unique_lock<std::mutex> side_lock(g_side_mu, std::defer_lock);
   SideStream* ss = nullptr;
   if (overlap) {
@@ -645,10 +647,11 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
         HIPCHK(hipEventRecord(ss->ev[j], ss->s));
       }
       if (k >= 1) {
-        HIPCHK(hipStreamWaitEvent(ss->s2, ev_gt[k], 0));
-        rc = vupd(k - 1, ss->s2);
+        hipStream_t sv = v_behind ? ss->s : ss->s2;
+        if (!v_behind) HIPCHK(hipStreamWaitEvent(ss->s2, ev_gt[k], 0));
+        rc = vupd(k - 1, sv);
         if (rc) return rc;
-        HIPCHK(hipEventRecord(ev_vu[k - 1], ss->s2));
+        HIPCHK(hipEventRecord(ev_vu[k - 1], sv));
       }
     }
     {
@@ -659,7 +662,7 @@ int run_group(const slmc_model* m, const slmc_options* o, const Group& grp, cons
     // V_k = F P^T V_{k-1} is needed only by the recombination: off the chain's critical
     // path on s2 when overlapping (gated: released above one step later, the last one here)
     if (gated && k < mseg - 1) continue;
-    hipStream_t sv = overlap ? ss->s2 : st;
+    hipStream_t sv = overlap ? (v_behind ? ss->s : ss->s2) : st;
     if (overlap) {
       HIPCHK(hipEventRecord(ev_qr[k], st));
       HIPCHK(hipStreamWaitEvent(sv, ev_qr[k], 0));
@@ -1528,8 +1531,8 @@ int slmc_autotune(const slmc_model* model, const slmc_options* opt, int32_t n_it
     if (rc == SLMC_OK && ms >= 0.0 && ms < best_ms) { best = seg[i]; best_ms = ms; }
   }
   std::vector<TuneCfg> sch;
-  for (int sc = 1; sc <= 3; ++sc) {
-    if (sc != 2) {
+  for (int sc = 1; sc <= 4; ++sc) {
+    if (sc != 2 && sc != 4) {
       TuneCfg c = best;
       c.sched = sc;
       sch.push_back(c);
@@ -1538,7 +1541,7 @@ int slmc_autotune(const slmc_model* model, const slmc_options* opt, int32_t n_it
     for (int ahead : {1, 2, 3, 4, 6, 8})
       for (int gate = 0; gate <= 1; ++gate) {
         TuneCfg c = best;
-        c.sched = 2;
+        c.sched = sc;
         c.ahead = ahead;
         c.gate = gate;
         sch.push_back(c);
