@@ -944,10 +944,28 @@ __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
 // layout of a B operand (k = g + 4s for slice s).  With Y_p the block of Householder
 // vectors and T_p its compact-WY factor,
 //   W^T = Y_p^T B^T,  W'^T = T_p^T W^T,  B^T -= Y_p W'^T
-// apply (I - Y_p T_p Y_p^T) from the right, block after block, without a transpose.  Y_p
-// and T_p are staged in LDS for the 4 waves; the next block is loaded into registers while
-// the current one is applied.
+// apply (I - Y_p T_p Y_p^T) from the right, block after block, without a transpose.
+//
+// Y_p and T_p are staged in LDS for the 4 waves, double-buffered: block p+1 is copied from
+// global memory straight into LDS (global_load_lds_dwordx4, no registers) while block p is
+// applied, so the registers go to the panel and to operand prefetch: each step's 4 LDS
+// operands are read while the previous step's 4 matrix-core instructions issue.  Rows of a
+// staged block sit at stride LYD doubles (even, so every 16-byte slot is aligned; the
+// column reads of the update spread over the banks).  The unit-lower masking of the top
+// 16 rows is applied in LDS by the threads whose copies wrote them.
 constexpr int LDW = 18;   // row stride of the per-wave 16x16 transpose buffers
+constexpr int LYD = 18;   // row stride of a staged Householder block
+
+// 16 bytes from global memory into LDS: lane L of the wave writes bytes 16 L .. 16 L + 15
+// from lds_base (the same in every lane)
+__device__ __forceinline__ void lds_copy16(const double* src, double* lds_base) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
+}
+
+// doubles of one staging buffer (at least the 4 per-wave transpose buffers, which alias
+// the second one before the first copy into it and after the last)
+__host__ __device__ constexpr int wy_ybuf(int Np) { return (Np > 64 ? Np : 64) * LYD; }
 
 template <int NRBMAX>
 __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restrict__ Bsrc,
@@ -958,33 +976,75 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
                                                       double* __restrict__ npart,
                                                       int transpose_out, int nb, int Np) {
   extern __shared__ double lds[];
-  constexpr int LY = 17;                   // Y_p row stride (odd: conflict-free columns)
-  const int NRB = Np >> 4, npg = (NRB + 3) >> 2;
-  double* Ys = lds;                        // [Np][LY]: rows j0 .. Np-1 of block p, local
-  double* Ts = Ys + Np * LY;               // [256]: T_p
-  double* wb = Ts + 256 + (threadIdx.x >> 6) * 16 * LDW;   // [16][LDW] of this wave
+  constexpr int NSLOT = (9 * 16 * NRBMAX + 255) / 256;   // copy instructions per block
+  const int NRB = Np >> 4, npg = (NRB + 3) >> 2, YB = wy_ybuf(Np);
+  // staging buffer k: Y block at lds + k YB ([K][LYD]: rows j0 .. Np-1, local), T block at
+  // lds + 2 YB + 256 k (offsets from the shared array, so every access stays an LDS access)
   const int id = xcd_remap(blockIdx.x, nb * npg);
   if (id < 0) return;
   const int b = id / npg, tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4,
             c = lane & 15;
+  double* wb = lds + YB + w * 16 * LDW;                  // [16][LDW] of this wave
   const int rp = 4 * (id % npg) + w, r0 = 16 * rp;
   const bool act = rp < NRB;
   const double* Y = QRW + (size_t)b * Np * Np;
   const double* T = Tb + (size_t)b * NRB * 256;
 
+  // block p: 16-byte slot q = 9 r + m2 holds Y[j0 + r][j0 + 2 m2 ..], m2 = 8 is padding;
+  // instruction i of wave w fills slots 256 i + 64 w .. + 63
+  auto stage = [&](int p, int k) {
+    double* yb = lds + k * YB;
+    double* tb = lds + 2 * YB + 256 * k;
+    const int j0 = 16 * p, nslot = 9 * (Np - j0);
+    const double* Yp = Y + (size_t)j0 * Np + j0;
+#pragma unroll
+    for (int i = 0; i < NSLOT; ++i) {
+      const int q = tid + 256 * i, r = q / 9, m2 = q - 9 * r;
+      if (q < nslot && m2 < 8) lds_copy16(Yp + (size_t)r * Np + 2 * m2, yb + 2 * (256 * i + 64 * w));
+    }
+    if (tid < 128) lds_copy16(T + (size_t)p * 256 + 2 * tid, tb + 2 * 64 * w);
+  };
+  // after this thread's copies have landed: unit diagonal, zeros above, in the top rows
+  auto mask_top = [&](int k) {
+    double* yb = lds + k * YB;
+    if (tid < 144) {
+      const int r = tid / 9, m = 2 * (tid - 9 * (tid / 9));
+      if (m < 16) {
+        double* e = yb + r * LYD + m;
+        const double y0 = e[0], y1 = e[1];
+        e[0] = r > m ? y0 : (r == m ? 1.0 : 0.0);
+        e[1] = r > m + 1 ? y1 : (r == m + 1 ? 1.0 : 0.0);
+      }
+    }
+  };
+  auto wait_copies = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };   // vmcnt(0)
+
+  // the panel's tiles: every row load is issued before the first one is turned around, so
+  // the loads of all tiles are in flight together
   dx4 bt[NRBMAX];
 #pragma unroll
   for (int t = 0; t < NRBMAX; ++t) {
     bt[t] = zero4d();
+    if (t < NRB && act && Bsrc) {
+      // lane: row lane >> 2 of the panel, columns 4 (lane & 3) .. + 3 of tile t
+      const double* src = Bsrc + (size_t)b * bstride + (size_t)(r0 + (lane >> 2)) * Np + 16 * t +
+                          4 * (lane & 3);
+      const double2 x01 = ((const double2*)src)[0], x23 = ((const double2*)src)[1];
+      bt[t][0] = x01.x;
+      bt[t][1] = x01.y;
+      bt[t][2] = x23.x;
+      bt[t][3] = x23.y;
+    }
+  }
+  stage(0, 0);
+#pragma unroll
+  for (int t = 0; t < NRBMAX; ++t) {
     if (t < NRB && act) {
       if (Bsrc) {
-        // a 16x16 tile of B, coalesced, turned around in the wave's LDS buffer
-        const double* src = Bsrc + (size_t)b * bstride + (size_t)(r0 + (lane >> 2)) * Np + 16 * t +
-                            4 * (lane & 3);
-        const double2 x01 = ((const double2*)src)[0], x23 = ((const double2*)src)[1];
+        // turned around in the wave's LDS buffer into the B^T tile layout
         double* d = wb + (lane >> 2) * LDW + 4 * (lane & 3);
-        ((double2*)d)[0] = x01;
-        ((double2*)d)[1] = x23;
+        ((double2*)d)[0] = double2{bt[t][0], bt[t][1]};
+        ((double2*)d)[1] = double2{bt[t][2], bt[t][3]};
         wave_lds_fence();
 #pragma unroll
         for (int v = 0; v < 4; ++v) bt[t][v] = wb[c * LDW + g + 4 * v];
@@ -995,65 +1055,73 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
       }
     }
   }
-
-  // block p of Y (rows 16p .. Np-1, columns 16p .. 16p+15; unit lower on top), one element
-  // per (thread, i): local row (tid + 256 i) >> 4, column (tid + 256 i) & 15
-  double yp[NRBMAX], tpre;
-  auto yload = [&](int p) {
-    const int j0 = 16 * p, K = Np - j0;
-    tpre = T[(size_t)p * 256 + tid];
-#pragma unroll
-    for (int i = 0; i < NRBMAX; ++i) {
-      const int idx = tid + 256 * i, r = idx >> 4, m = idx & 15;
-      yp[i] = 0.0;
-      if (r < K) {
-        const double y = Y[(size_t)(j0 + r) * Np + j0 + m];
-        yp[i] = r > 15 ? y : (r > m ? y : (r == m ? 1.0 : 0.0));
-      }
-    }
-  };
-  auto ystore = [&](int p) {
-    const int K = Np - 16 * p;
-#pragma unroll
-    for (int i = 0; i < NRBMAX; ++i) {
-      const int idx = tid + 256 * i, r = idx >> 4, m = idx & 15;
-      if (r < K) Ys[r * LY + m] = yp[i];
-    }
-    Ts[tid] = tpre;
-  };
-  yload(0);
-  ystore(0);
-  __syncthreads();
+  wait_copies();
+  mask_top(0);
+  __syncthreads();   // block 0 staged; the transpose buffers are free
+  if (NRB > 1) stage(1, 1);
 
   for (int p = 0; p < NRB; ++p) {
-    if (p + 1 < NRB) yload(p + 1);
+    const double* Ys = lds + (p & 1) * YB;
+    const double* Ts = lds + 2 * YB + 256 * (p & 1);
     if (act) {
+      // operands ping-pong between two register sets by the parity of the (unrolled) step,
+      // so a step's reads land while the previous step's products issue, with no copies
+      double oa[4] = {0.0, 0.0, 0.0, 0.0}, ob[4] = {0.0, 0.0, 0.0, 0.0};
+      // W^T = Y_p^T B^T: step kb reads rows 16 (kb - p) + 4 s + g of the block, column c
+      if (p & 1) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) ob[s] = Ys[(4 * s + g) * LYD + c];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) oa[s] = Ys[(4 * s + g) * LYD + c];
+      }
       dx4 wt = zero4d();
 #pragma unroll
       for (int kb = 0; kb < NRBMAX; ++kb) {
         if (kb >= p && kb < NRB) {
+          double* cur = (kb & 1) ? ob : oa;
+          double* nxt = (kb & 1) ? oa : ob;
+          // the last step re-reads its own rows: an unconditional read keeps the wait
+          // before the next step's products from covering this read
+          const int kn = (kb + 1 < NRB ? kb + 1 : kb) - p;
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            wt = mfma64(Ys[(16 * (kb - p) + 4 * s + g) * LY + c], bt[kb][s], wt);
+          for (int s = 0; s < 4; ++s) nxt[s] = Ys[(16 * kn + 4 * s + g) * LYD + c];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) wt = mfma64(cur[s], bt[kb][s], wt);
         }
       }
       dx4 wp = zero4d();
 #pragma unroll
-      for (int s = 0; s < 4; ++s) wp = mfma64(Ts[(4 * s + g) * 16 + c], wt[s], wp);
+      for (int s = 0; s < 4; ++s) wp = mfma64(-Ts[(4 * s + g) * 16 + c], wt[s], wp);
+      // wp holds -W'^T (negating T negates every product and sum exactly), so
+      // B^T -= Y_p W'^T is B^T + Y_p wp: step cb reads row 16 (cb - p) + c of the block,
+      // columns 4 s + g
+      if (p & 1) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) ob[s] = Ys[c * LYD + 4 * s + g];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) oa[s] = Ys[c * LYD + 4 * s + g];
+      }
 #pragma unroll
       for (int cb = 0; cb < NRBMAX; ++cb) {
         if (cb >= p && cb < NRB) {
+          double* cur = (cb & 1) ? ob : oa;
+          double* nxt = (cb & 1) ? oa : ob;
+          const int kn = (cb + 1 < NRB ? cb + 1 : cb) - p;
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            bt[cb] = mfma64(-Ys[(16 * (cb - p) + c) * LY + 4 * s + g], wp[s], bt[cb]);
+          for (int s = 0; s < 4; ++s) nxt[s] = Ys[(16 * kn + c) * LYD + 4 * s + g];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) bt[cb] = mfma64(cur[s], wp[s], bt[cb]);
         }
       }
     }
-    __syncthreads();   // every wave is done with Y_p
     if (p + 1 < NRB) {
-      ystore(p + 1);
-      __syncthreads();
+      wait_copies();
+      mask_top((p + 1) & 1);
     }
+    __syncthreads();   // block p+1 staged and masked; every wave is done with block p
+    if (p + 2 < NRB) stage(p + 2, p & 1);
   }
 
   if (!act) return;
@@ -1092,9 +1160,12 @@ __global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restric
 // of a strip sum their tiles kb >= rb.  One of them leaves its partial tile in LDS and the
 // other adds it after the block row's barrier and stores the output tile; the two swap
 // roles every block row, so a single partial buffer is never written before it is read.
-// The 16 rows of F that block row rb needs (columns 16 rb .. Np-1, the stored Householder
-// vectors below the diagonal masked to zero) are staged in LDS once for the 8 waves,
-// double-buffered with the next block row in registers.
+// The 16 rows of F that block row rb needs (columns 16 rb .. Np-1) are copied from global
+// memory straight into LDS (global_load_lds_dwordx4), double-buffered with the block row
+// being applied, at row stride Np + 2 (even: 16-byte slots stay aligned).  The stored
+// Householder vectors below the diagonal are masked to zero where they are read (only the
+// diagonal block holds any), and each step's 4 LDS operands are read while the previous
+// step's 4 matrix-core instructions issue.
 template <int NRBMAX>
 __global__ __launch_bounds__(512, 4) void vupd_split_k(const double* __restrict__ QRW,
                                                        const int* __restrict__ perm,
@@ -1103,7 +1174,7 @@ __global__ __launch_bounds__(512, 4) void vupd_split_k(const double* __restrict_
                                                        double* __restrict__ Vn, int nb, int Np) {
   extern __shared__ double lds[];
   constexpr int NH = (NRBMAX + 1) / 2;
-  const int LDF = Np + 1;
+  const int LDF = Np + 2, FB = 16 * LDF;
   const int NRB = Np >> 4, npg = (NRB + 3) >> 2;
   const int id = xcd_remap(blockIdx.x, nb * npg);
   if (id < 0) return;
@@ -1114,74 +1185,119 @@ __global__ __launch_bounds__(512, 4) void vupd_split_k(const double* __restrict_
   const bool act = cs < NRB;
   const double* F = QRW + (size_t)b * Np * Np;
   const int* pb = perm + (size_t)b * Np;
-  double* part = lds + 2 * 16 * LDF + (w * 64 + lane) * 4;   // [4 strips][64 lanes][4]
+  double* part = lds + 2 * FB + (w * 64 + lane) * 4;   // [4 strips][64 lanes][4]
+  double* rs = lds + 2 * FB + 1024;                     // [Np]: the output row scales
+
+  // block row rb into buffer k: wave wv copies rows 2 wv and 2 wv + 1, 64 16-byte slots
+  // (columns 2 j, 2 j + 1 for j = 64 u + lane) per instruction, the slots 8 rb <= j < Np / 2
+  auto stage = [&](int rb, int k) {
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const int r = 2 * wv + rr;
+#pragma unroll
+      for (int u = 0; u < (8 * NRBMAX + 63) / 64; ++u) {
+        const int j = 64 * u + lane;
+        if (j >= 8 * rb && 2 * j < Np)
+          lds_copy16(F + (size_t)(16 * rb + r) * Np + 2 * j, lds + k * FB + r * LDF + 128 * u);
+      }
+    }
+  };
+  auto wait_copies = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };   // vmcnt(0)
+  stage(0, 0);
 
   // the factor is S_r R S_c (diagonal scalings from the QR): W = S_c P^T V_old here, the
   // output rows scaled by S_r when stored
   const double* csc = scales + (size_t)b * 2 * Np;
-  const double* rsc = csc + Np;
+  for (int r = tid; r < Np; r += 512) rs[r] = csc[Np + r];
+  // the gather in three passes (permutation, rows of V_old, scales) with every load of a
+  // pass in flight together; rows and columns clamped into the item for unused tiles
   dx4 wt[NH];
+  int src[NH][4];
+  const int colc = act ? col : 0;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    const int kb = 2 * i + h < NRB ? 2 * i + h : NRB - 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) src[i][v] = pb[16 * kb + g + 4 * v];
+  }
+  if (Vo) {
+    const double* vb = Vo + (size_t)b * Np * Np + colc;
+#pragma unroll
+    for (int i = 0; i < NH; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) wt[i][v] = vb[(size_t)src[i][v] * Np];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NH; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) wt[i][v] = src[i][v] == col ? 1.0 : 0.0;
+  }
 #pragma unroll
   for (int i = 0; i < NH; ++i) {
     const int kb = 2 * i + h;
-    wt[i] = zero4d();
-    if (kb < NRB && act) {
+    const bool use = kb < NRB && act;
+    const int kc = kb < NRB ? kb : NRB - 1;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int q = 16 * kb + g + 4 * v, src = pb[q];
-        const double x = Vo ? Vo[(size_t)b * Np * Np + (size_t)src * Np + col] : (src == col ? 1.0 : 0.0);
-        wt[i][v] = csc[q] * x;
-      }
+    for (int v = 0; v < 4; ++v) {
+      const double sc = csc[16 * kc + g + 4 * v];
+      wt[i][v] = use ? sc * wt[i][v] : 0.0;
     }
   }
-  // block row rb of R (upper triangle of QRW): thread tid holds column tid & 255 of rows
-  // 8 (tid >> 8) .. + 7
-  const int fc = tid & 255, fr = 8 * (tid >> 8);
-  double st[8];
-  auto fload = [&](int rb) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int row = 16 * rb + fr + i;
-      st[i] = (fc >= row && fc < Np) ? F[(size_t)row * Np + fc] : 0.0;
-    }
-  };
-  auto fstore = [&](int buf, int rb) {
-    double* Fs = lds + buf * 16 * LDF;
-    if (fc >= 16 * rb && fc < Np) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Fs[(fr + i) * LDF + fc] = st[i];
-    }
-  };
-  fload(0);
-  fstore(0, 0);
+  wait_copies();
   __syncthreads();
+  if (NRB > 1) stage(1, 1);
   double* out = Vn + (size_t)b * Np * Np;
   for (int rb = 0; rb < NRB; ++rb) {
-    if (rb + 1 < NRB) fload(rb + 1);
     const bool fin = h == (rb & 1);   // this wave finishes the tile of block row rb
     dx4 acc = zero4d();
     if (act) {
-      const double* Fs = lds + (rb & 1) * 16 * LDF;
+      const double* Fs = lds + (rb & 1) * FB + c * LDF + g;
+      // step i (kb = 2 i + h >= rb) reads F[16 rb + c][16 kb + 4 s + g]; the first step of
+      // the finishing wave is the diagonal block, zero below the diagonal
+      const int i0 = (rb - h + 1) >> 1;
+      double oa[4] = {0.0, 0.0, 0.0, 0.0}, ob[4] = {0.0, 0.0, 0.0, 0.0};
+      if (2 * i0 + h < NRB) {
+        double f[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double v = Fs[16 * (2 * i0 + h) + 4 * s];
+          f[s] = (fin && 4 * s + g < c) ? 0.0 : v;
+        }
+        if (i0 & 1) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) ob[s] = f[s];
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) oa[s] = f[s];
+        }
+      }
 #pragma unroll
       for (int i = 0; i < NH; ++i) {
         const int kb = 2 * i + h;
         if (kb >= rb && kb < NRB) {
+          double* cur = (i & 1) ? ob : oa;
+          double* nxt = (i & 1) ? oa : ob;
+          const int kn = kb + 2 < NRB ? kb + 2 : kb;
 #pragma unroll
-          for (int s = 0; s < 4; ++s) acc = mfma64(Fs[c * LDF + 16 * kb + 4 * s + g], wt[i][s], acc);
+          for (int s = 0; s < 4; ++s) nxt[s] = Fs[16 * kn + 4 * s];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc = mfma64(cur[s], wt[i][s], acc);
         }
       }
       if (!fin) *(dx4*)part = acc;
     }
-    if (rb + 1 < NRB) fstore((rb + 1) & 1, rb + 1);
-    __syncthreads();
+    if (rb + 1 < NRB) wait_copies();
+    __syncthreads();   // block row rb+1 staged; every wave is done with block row rb
     if (act && fin) {
       acc += *(const dx4*)part;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * rb + g + 4 * v;
-        out[(size_t)row * Np + col] = rsc[row] * acc[v];
+        out[(size_t)row * Np + col] = rs[row] * acc[v];
       }
     }
+    // issued after this step's LDS reads, which therefore wait for no copy
+    if (rb + 2 < NRB) stage(rb + 2, rb & 1);
   }
 }
 
@@ -1240,7 +1356,7 @@ hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QR
   if (NRB <= 16) {
     // register-resident panels (Np <= 256)
     const int npg = (NRB + 3) / 4;
-    const size_t lds_r = (size_t)(Np * 17 + 256 + 4 * 16 * LDW) * sizeof(double);
+    const size_t lds_r = (size_t)(2 * wy_ybuf(Np) + 512) * sizeof(double);
 #define WY_REG(NR)                                                                              \
   hipLaunchKernelGGL(wy_apply_reg_k<NR>, dim3(xcd_grid(nb * npg)), dim3(256), lds_r, st, Bsrc,   \
                      bstride, QRW, Tb, A, npart, transpose_out, nb, Np)
@@ -1275,7 +1391,7 @@ hipError_t launch_vupd(const double* QRW, const int* perm, const double* key, co
   if (NRB <= 16) {
     // register-resident strips (Np <= 256): two F block rows and the partial tiles in LDS
     const int npg = (NRB + 3) / 4;
-    const size_t lds = ((size_t)2 * 16 * (Np + 1) + 4 * 64 * 4) * sizeof(double);
+    const size_t lds = ((size_t)2 * 16 * (Np + 2) + 4 * 64 * 4 + Np) * sizeof(double);
 #define VUPD_SPLIT(NR)                                                                        \
   hipLaunchKernelGGL(vupd_split_k<NR>, dim3(xcd_grid(nb * npg)), dim3(512), lds, st, QRW, perm, \
                      key, Vo, Vn, nb, Np)
