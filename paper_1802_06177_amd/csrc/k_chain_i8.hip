@@ -112,14 +112,20 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
   const int pan = id % npan, k = k0 + (id / npan) % kc, b = id / (npan * kc);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
   const int NRB = Np >> 4, c0 = pan * W;
+  const bool full = NW * RB <= NRB;   // every wave's row blocks exist
   const double* xb = field_of(f, b);
   const int l0 = k * n_s, len = min(n_s, Ltau - l0);
   double* Sout = S + ((size_t)b * m + k) * Np * Np;
   double* nout = snorm + ((size_t)b * m + k) * Np;
 
-  fill_v(vbuf, xb, l0, N, Np, ldl);
-  for (int i = tid; i < Np; i += 64 * NW) escs[i] = Esc[i];
-  if (len > 1) fill_v(vbuf + Np, xb, l0 + 1, N, Np, ldl);
+  // v of the first two slices: both loads of a thread in flight before either is used
+  for (int q = tid; q < Np; q += 64 * NW) {
+    const double x0 = q < N ? xb[(size_t)l0 * N + q] : 0.0;
+    const double x1 = (q < N && len > 1) ? xb[(size_t)(l0 + 1) * N + q] : 0.0;
+    escs[q] = Esc[q];
+    vbuf[q] = q < N ? exp(-ldl * x0) : 1.0;
+    if (len > 1) vbuf[Np + q] = q < N ? exp(-ldl * x1) : 1.0;
+  }
   // zero the k padding of the slices once (rows Np .. Npk-1 are never written later)
   for (int idx = tid; idx < NSL * W * (Npk - Np); idx += 64 * NW) {
     const int pc = idx / (Npk - Np), r = Np + idx - pc * (Npk - Np);
@@ -129,10 +135,21 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
     // the slices of E's first trow rows, 16-byte chunks from the [row][k block][slice][64]
     // layout into [slice][row][LDE]
     const int nkb = Npk >> 6, nch = trow * nkb * NSL * 4;
-    for (int idx = tid; idx < nch; idx += 64 * NW) {
-      const int q4 = idx & 3, t = idx >> 2, p = t % NSL, kb = (t / NSL) % nkb, row = t / (NSL * nkb);
-      *(ix4*)(E0 + (p * trow + row) * LDE + 64 * kb + 16 * q4) =
-          *(const ix4*)(Eq + (((size_t)row * nkb + kb) * NSL + p) * 64 + 16 * q4);
+    // 8 chunks per thread in flight, then stored
+    for (int base = 0; base < nch; base += 8 * 64 * NW) {
+      ix4 tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + tid + u * 64 * NW;
+        const int q4 = idx & 3, t = idx >> 2, p = t % NSL, kb = (t / NSL) % nkb, row = t / (NSL * nkb);
+        if (idx < nch) tmp[u] = *(const ix4*)(Eq + (((size_t)row * nkb + kb) * NSL + p) * 64 + 16 * q4);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + tid + u * 64 * NW;
+        const int q4 = idx & 3, t = idx >> 2, p = t % NSL, kb = (t / NSL) % nkb, row = t / (NSL * nkb);
+        if (idx < nch) *(ix4*)(E0 + (p * trow + row) * LDE + 64 * kb + 16 * q4) = tmp[u];
+      }
     }
   }
   __syncthreads();
@@ -227,16 +244,29 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
     __syncthreads();
   };
 
-  // first panel: v_{l0+1} E diag(v_l0)
+  // first panel: v_{l0+1} E diag(v_l0); when every wave's row blocks exist the loads run
+  // without a per-element branch, so all of them are in flight together
+  if (full) {
 #pragma unroll
-  for (int r = 0; r < RB; ++r)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
+      for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 16 * (w + NW * r) + drow32(g, i), col = c0 + 16 * cb + c;
-        vals[r][cb][i] = (w + NW * r < NRB) ? vbuf[Np + row] * E64[(size_t)row * Np + col] * vbuf[col] : 0.0;
-      }
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * (w + NW * r) + drow32(g, i), col = c0 + 16 * cb + c;
+          vals[r][cb][i] = vbuf[Np + row] * E64[(size_t)row * Np + col] * vbuf[col];
+        }
+  } else {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * (w + NW * r) + drow32(g, i), col = c0 + 16 * cb + c;
+          vals[r][cb][i] = (w + NW * r < NRB) ? vbuf[Np + row] * E64[(size_t)row * Np + col] * vbuf[col] : 0.0;
+        }
+  }
   make_slices();
 
   const int nkb = Npk >> 6;
@@ -257,7 +287,16 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
   for (int t = 1; t < len; ++t) {
     const bool last = (t == len - 1);
     double* vnext = vbuf + ((t + 1) & 1) * Np;   // v of slice l0+t+1 (unused when last)
-    if (!last) fill_v(vnext, xb, l0 + t + 1, N, Np, ldl);
+    // the field of slice l0+t+1 is loaded here and turned into vnext after the products,
+    // so the load's latency hides behind them
+    double xn[2] = {0.0, 0.0};
+    if (!last) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int q = tid + 64 * NW * j;
+        if (q < N) xn[j] = xb[(size_t)(l0 + t + 1) * N + q];
+      }
+    }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -348,6 +387,13 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
         }
       }
     }
+    if (!last) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int q = tid + 64 * NW * j;
+        if (q < Np) vnext[q] = q < N ? exp(-ldl * xn[j]) : 1.0;
+      }
+    }
     __syncthreads();   // every wave is done with the slices; vnext is filled
     if (!last) {
 #pragma unroll
@@ -359,7 +405,9 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void seg_chain_i8(const int8_t* __
             const int row = 16 * (w + NW * r) + drow32(g, i);
             const double x = recombine5(acc[r][cb][0][i], acc[r][cb][1][i], acc[r][cb][2][i],
                                         acc[r][cb][3][i], acc[r][cb][4][i]);
-            vals[r][cb][i] = (w + NW * r < NRB) ? vnext[row] * (escs[row] * fcur[cb] * x) : 0.0;
+            // branch-free when every row block exists (the LDS reads then overlap)
+            if (full) vals[r][cb][i] = vnext[row] * (escs[row] * fcur[cb] * x);
+            else vals[r][cb][i] = (w + NW * r < NRB) ? vnext[row] * (escs[row] * fcur[cb] * x) : 0.0;
           }
       make_slices();
     } else {
