@@ -452,30 +452,50 @@ __global__ __launch_bounds__(256, 2) void lu_solve_lds_k(int mode, const double*
   const int* pb = prow + (size_t)b * Np;
   const double* DIb = DI + (size_t)b * NRB * 512;
   const int col = 16 * cb + c;
+  // the pivot map in LDS: the gathers below take their row indices from there
+  double* dbl = lds + 2 * 16 * LDL;        // [Np] Db^-1 (right-hand side of mode 0)
+  int* pl = (int*)(dbl + Np);
+  for (int i = tid; i < Np; i += 256) {
+    pl[i] = pb[i];
+    if (mode == 0) dbl[i] = exp(-fmax(logD[(size_t)b * Np + i], 0.0));
+  }
+  __syncthreads();
 
+  // right-hand side through the pivot map: all loads of a thread issued before the first
+  // is used
   dx4 y[NRBMAX];
+  const int colc = act ? col : 0;
 #pragma unroll
   for (int rb = 0; rb < NRBMAX; ++rb) {
     y[rb] = zero4d();
-    if (rb < NRB && act) {
+    if (rb < NRB) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int pr = pb[16 * rb + drow64(g, v)];
-        if (mode == 0)
-          y[rb][v] = exp(-fmax(logD[(size_t)b * Np + pr], 0.0)) * QT[(size_t)b * Np * Np + (size_t)pr * Np + col];
-        else
-          y[rb][v] = R[(size_t)b * Np * Np + (size_t)pr * Np + col];
+        const int pr = pl[16 * rb + drow64(g, v)];
+        y[rb][v] = (mode == 0 ? QT : R)[(size_t)b * Np * Np + (size_t)pr * Np + colc];
+      }
+    }
+  }
+  if (mode == 0) {
+#pragma unroll
+    for (int rb = 0; rb < NRBMAX; ++rb) {
+      if (rb < NRB) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          y[rb][v] = dbl[pl[16 * rb + drow64(g, v)]] * y[rb][v];
+        }
       }
     }
   }
 
-  // staging of block row rb: row i of the block (factor row pb[16 rb + i]), columns
+  // staging of block row rb: row i of the block (factor row pl[16 rb + i]), columns
   // [lo, hi): thread tid holds column tid of each of the 16 rows
   double st[16];
   auto sload = [&](int rb, int lo, int hi) {
     const bool in = tid >= lo && tid < hi;
+    const int tc = in ? tid : 0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) st[i] = in ? Lb[(size_t)pb[16 * rb + i] * Np + tid] : 0.0;
+    for (int i = 0; i < 16; ++i) st[i] = Lb[(size_t)pl[16 * rb + i] * Np + tc];
   };
   auto sstore = [&](int buf, int lo, int hi) {
     double* Ls = lds + buf * 16 * LDL;
@@ -485,10 +505,17 @@ __global__ __launch_bounds__(256, 2) void lu_solve_lds_k(int mode, const double*
     }
   };
 
-  // forward: L y = P rhs (columns 0 .. 16 rb - 1 of block row rb)
+  // forward: L y = P rhs (columns 0 .. 16 rb - 1 of block row rb); the inverse of the
+  // diagonal block is read one block row ahead
+  double di[4], din[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) di[s] = DIb[c * 16 + drow64(g, s)];
   sload(0, 0, 0);
   for (int rb = 0; rb < NRB; ++rb) {
     if (rb + 1 < NRB) sload(rb + 1, 0, 16 * (rb + 1));
+    const int rn = rb + 1 < NRB ? rb + 1 : rb;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) din[s] = DIb[(size_t)rn * 512 + c * 16 + drow64(g, s)];
     if (act) {
       const double* Ls = lds + (rb & 1) * 16 * LDL;
 #pragma unroll
@@ -502,19 +529,26 @@ __global__ __launch_bounds__(256, 2) void lu_solve_lds_k(int mode, const double*
           }
           dx4 nv = zero4d();
 #pragma unroll
-          for (int s = 0; s < 4; ++s) nv = mfma64(DIb[(size_t)k * 512 + c * 16 + drow64(g, s)], t[s], nv);
+          for (int s = 0; s < 4; ++s) nv = mfma64(di[s], t[s], nv);
           y[k] = nv;
         }
       }
     }
     if (rb + 1 < NRB) sstore((rb + 1) & 1, 0, 16 * (rb + 1));
+#pragma unroll
+    for (int s = 0; s < 4; ++s) di[s] = din[s];
     __syncthreads();
   }
   // backward: U x = y (columns 16 (rb + 1) .. Np - 1 of block row rb)
+#pragma unroll
+  for (int s = 0; s < 4; ++s) di[s] = DIb[(size_t)(NRB - 1) * 512 + 256 + c * 16 + drow64(g, s)];
   sload(NRB - 1, Np, Np);
   for (int rb = NRB - 1; rb >= 0; --rb) {
     const int buf = (NRB - 1 - rb) & 1;
     if (rb > 0) sload(rb - 1, 16 * rb, Np);
+    const int rn = rb > 0 ? rb - 1 : rb;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) din[s] = DIb[(size_t)rn * 512 + 256 + c * 16 + drow64(g, s)];
     if (act) {
       const double* Ls = lds + buf * 16 * LDL;
 #pragma unroll
@@ -530,27 +564,48 @@ __global__ __launch_bounds__(256, 2) void lu_solve_lds_k(int mode, const double*
           }
           dx4 nv = zero4d();
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            nv = mfma64(DIb[(size_t)k * 512 + 256 + c * 16 + drow64(g, s)], t[s], nv);
+          for (int s = 0; s < 4; ++s) nv = mfma64(di[s], t[s], nv);
           y[k] = nv;
         }
       }
     }
     if (rb > 0) sstore(buf ^ 1, 16 * rb, Np);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) di[s] = din[s];
     __syncthreads();
   }
 
   if (!act) return;
   double* Gi = Gint + (size_t)b * Np * Np;
   double* Go = Gout ? Gout + (goff ? goff[b] : (int64_t)b * N * N) : nullptr;
+  if (accumulate) {
+    // the previous G, every load in flight before the first sum (straight-line when all
+    // NRBMAX row blocks exist)
+    if (NRB == NRBMAX) {
+      // 4 row blocks (16 loads) at a time: the scheduling barriers keep the register
+      // footprint of the loads in flight within the budget
+#pragma unroll
+      for (int rb = 0; rb < NRBMAX; ++rb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[rb][v] += Gi[(size_t)(16 * rb + drow64(g, v)) * Np + col];
+        if ((rb & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < NRBMAX; ++rb)
+        if (rb < NRB) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) y[rb][v] += Gi[(size_t)(16 * rb + drow64(g, v)) * Np + col];
+        }
+    }
+  }
 #pragma unroll
   for (int rb = 0; rb < NRBMAX; ++rb) {
     if (rb < NRB) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * rb + drow64(g, v);
-        double val = y[rb][v];
-        if (accumulate) val += Gi[(size_t)row * Np + col];
+        const double val = y[rb][v];
         Gi[(size_t)row * Np + col] = val;
         if (Go && row < N && col < N) Go[(size_t)row * N + col] = val;
       }
@@ -651,7 +706,7 @@ hipError_t run_solve(int mode, const double* QT, const double* logD, const doubl
                      double* Gout, const int64_t* goff, int nb, int N, int Np, hipStream_t st) {
   if (NRBMAX <= 16) {
     const int npg = (Np / 16 + 3) / 4;
-    const size_t lds = (size_t)2 * 16 * (Np + 1) * sizeof(double);
+    const size_t lds = (size_t)(2 * 16 * (Np + 1) + Np) * sizeof(double) + (size_t)Np * sizeof(int);
     hipLaunchKernelGGL(lu_solve_lds_k<NRBMAX <= 16 ? NRBMAX : 16>, dim3(xcd_grid(nb * npg)), dim3(256), lds,
                        st, mode, QT, logD, R, LU, prow, DI, Gint, acc, Gout, goff, nb, N, Np);
     return hipGetLastError();
