@@ -37,6 +37,12 @@ __device__ __forceinline__ fx4 mfmabf(bfx8 a, bfx8 b, fx4 c) {
 __device__ __forceinline__ int drow64(int g, int v) { return g + 4 * v; }
 __device__ __forceinline__ int drow32(int g, int v) { return 4 * g + v; }
 
+// orders this wave's earlier LDS accesses before its later ones (lanes of one wave
+// exchanging values through LDS)
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 __device__ __forceinline__ dx4 zero4d() { dx4 z = {0.0, 0.0, 0.0, 0.0}; return z; }
 __device__ __forceinline__ fx4 zero4f() { fx4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
 

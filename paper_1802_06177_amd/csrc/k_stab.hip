@@ -216,11 +216,6 @@ __device__ __forceinline__ double readlane64(double v, int l) {
                           __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-__device__ __forceinline__ void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // Householder factorization (LAPACK convention: beta = -sign(alpha)||x||, v_0 = 1,
 // tau = (beta - alpha)/beta) of the K x 16 panel held in registers by the first 4 waves
 // (one per SIMD): thread t < 256 owns local rows t (row0) and t + 256 (row1, only when
