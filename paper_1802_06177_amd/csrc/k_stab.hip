@@ -933,7 +933,7 @@ __global__ __launch_bounds__(256) void vupd_k(const double* __restrict__ QRW,
   }
 }
 
-// A = B Q for Np <= 256: one wave per 16-row panel of B, the 4 panels of one item sharing
+// A = B Q for Np <= 400: one wave per 16-row panel of B, the 4 panels of one item sharing
 // a workgroup.  The panel lives in registers as the 16x16 tiles of B^T in the matrix-core
 // accumulator layout (lane (g, c), register v: B^T[16t + g + 4v][c]), which is also the
 // layout of a B operand (k = g + 4s for slice s).  With Y_p the block of Householder
@@ -962,8 +962,11 @@ __device__ __forceinline__ void lds_copy16(const double* src, double* lds_base) 
 // the second one before the first copy into it and after the last)
 __host__ __device__ constexpr int wy_ybuf(int Np) { return (Np > 64 ? Np : 64) * LYD; }
 
+// Up to Np = 256 two workgroups share a CU (two waves per SIMD, 256 registers each); up to
+// Np = 400 (25 tiles of the panel per wave) one workgroup per CU, whose waves then have
+// the whole register file of their SIMD (the LDS staging buffers take 119 KB there).
 template <int NRBMAX>
-__global__ __launch_bounds__(256, 2) void wy_apply_reg_k(const double* __restrict__ Bsrc,
+__global__ __launch_bounds__(256, NRBMAX > 16 ? 1 : 2) void wy_apply_reg_k(const double* __restrict__ Bsrc,
                                                       int64_t bstride,
                                                       const double* __restrict__ QRW,
                                                       const double* __restrict__ Tb,
@@ -1348,8 +1351,8 @@ hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QR
                            const double* Tb, double* A, double* npart, int transpose_out,
                            int nb, int Np, hipStream_t st) {
   const int NRB = Np / 16;
-  if (NRB <= 16) {
-    // register-resident panels (Np <= 256)
+  if (NRB <= 25) {
+    // register-resident panels (Np <= 400)
     const int npg = (NRB + 3) / 4;
     const size_t lds_r = (size_t)(2 * wy_ybuf(Np) + 512) * sizeof(double);
 #define WY_REG(NR)                                                                              \
@@ -1357,7 +1360,8 @@ hipError_t launch_wy_apply(const double* Bsrc, int64_t bstride, const double* QR
                      bstride, QRW, Tb, A, npart, transpose_out, nb, Np)
     if (NRB <= 4) WY_REG(4);
     else if (NRB <= 8) WY_REG(8);
-    else WY_REG(16);
+    else if (NRB <= 16) WY_REG(16);
+    else WY_REG(25);
 #undef WY_REG
     return hipGetLastError();
   }
