@@ -229,6 +229,9 @@ __device__ __forceinline__ double readlane64(double v, int l) {
 // double-buffered by column parity.
 constexpr int QR_PANEL_WAVES = 4;
 constexpr int QR_SPIN_LIMIT = 1 << 16;   // about 2 ms of s_sleep(1) polls
+// Np from 272 to 400: the trailing update by pairs of waves, each with half of a column
+// block in registers (update_block_pair); above, the chunked two-pass update of one wave
+#define QR_PAIR_UPDATE(NRBMAX) ((NRBMAX) == 25)
 
 // Arrive-and-wait among the 4 panel waves through a monotonically increasing LDS counter
 // (the other waves keep working meanwhile).  The release on arrival orders the wave's
@@ -538,6 +541,126 @@ __device__ __forceinline__ void update_block_chunked(int nrbK, int j0, int cb, b
   }
 }
 
+// Arrive-and-wait between the two waves of an update pair, as panel_sync does for the
+// panel waves (bounded the same way).
+__device__ __forceinline__ void pair_sync(int* cnt, int& epoch, int lane, int* timeout) {
+  ++epoch;
+  if (lane == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int target = 2 * epoch;
+  int spins = 0;
+  while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+    if (spins >= 16) __builtin_amdgcn_s_sleep(1);
+    if (++spins > QR_SPIN_LIMIT) {
+      *timeout = 1;
+      break;
+    }
+  }
+}
+
+// update_block for large Np by a pair of waves: wave h holds one half of the column
+// block's row blocks (the first ceil(nrbK / 2), or the rest) in registers, loaded once;
+// the two partial products Y^T blk meet in LDS (wb: [2 halves][64 lanes][4]) behind a pair
+// sync, both waves form the same W = W_0 + W_1, and each applies the update to its own
+// half and stores it.  The caller alternates wb between two buffers from one column block
+// to the next: a wave's arrival at the sync waits for its own earlier LDS reads, so the
+// partner cannot overwrite a buffer that is still being read.
+template <int HB>
+__device__ __forceinline__ void update_block_pair(int nrbK, int j0, int cb, bool from_a,
+                                                  const double* __restrict__ Ab,
+                                                  const int* __restrict__ iperm,
+                                                  double* __restrict__ Q, int Np, const double* Pc,
+                                                  const double* Tc, double* wb, int h, int* pcnt,
+                                                  int& pepoch, int lane, int* timeout) {
+  int c = lane & 15, g = lane >> 4;
+  __asm__ volatile("" : "+v"(c), "+v"(g));
+  const int col = 16 * cb + c;
+  const int n0 = (nrbK + 1) >> 1;
+  const int r0 = h ? n0 : 0, nr = h ? nrbK - n0 : n0;
+  const double* src = (from_a ? Ab + iperm[col] : Q + (size_t)j0 * Np + col) + (size_t)16 * r0 * Np;
+  double* dst = Q + (size_t)(j0 + 16 * r0) * Np + col;
+  const double* Ph = Pc + 16 * r0 * LDY;
+  dx4 blk[HB];
+#pragma unroll
+  for (int rb = 0; rb < HB; ++rb) {
+    if (rb < nr) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) blk[rb][v] = src[(16 * rb + drow64(g, v)) * Np];
+    }
+  }
+  dx4 aw[4] = {zero4d(), zero4d(), zero4d(), zero4d()};
+  double yn[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) yn[s] = yval(Pc, 16 * r0 + drow64(g, s), c);
+#pragma unroll
+  for (int rb = 0; rb < HB; ++rb) {
+    if (rb < nr) {
+      double yc[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) yc[s] = yn[s];
+      // the next row block's Y values (unconditional, the row block clamped into the half:
+      // below the diagonal block, so no masking)
+      const int rn = min(rb + 1, nr - 1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) yn[s] = Ph[(16 * rn + drow64(g, s)) * LDY + c];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) aw[s] = mfma64(yc[s], blk[rb][s], aw[s]);
+    }
+  }
+  // every load of the half has been consumed by now; saying so spares the stores and the
+  // products below the compiler's per-instruction waits on loads it cannot see completed
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  *(dx4*)(wb + (h * 64 + lane) * 4) = aw[0] + aw[1] + aw[2] + aw[3];
+  pair_sync(pcnt, pepoch, lane, timeout);
+  const dx4 W = *(const dx4*)(wb + lane * 4) + *(const dx4*)(wb + (64 + lane) * 4);
+  double tv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) tv[s] = Tc[drow64(g, s) * LDY + c];
+  dx4 Wt = zero4d();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) Wt = mfma64(tv[s], W[s], Wt);
+  // blk -= Y W', row blocks in pairs (consecutive products go to independent accumulators);
+  // the next pair's Y values are read while the current pair's products issue
+  // (unconditionally, row blocks clamped into the half); every accumulator still sees
+  // s = 0 .. 3 in order
+  double qa[4], qb[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    qa[s] = -yval(Pc, 16 * r0 + c, drow64(g, s));
+    qb[s] = -yval(Pc, 16 * (r0 + min(1, nr - 1)) + c, drow64(g, s));
+  }
+#pragma unroll
+  for (int rb = 0; rb < HB; rb += 2) {
+    if (rb < nr) {
+      double ca[4], cb[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) { ca[s] = qa[s]; cb[s] = qb[s]; }
+      const int ra = min(rb + 2, nr - 1), rbb = min(rb + 3, nr - 1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        qa[s] = -yval(Pc, 16 * (r0 + ra) + c, drow64(g, s));
+        qb[s] = -yval(Pc, 16 * (r0 + rbb) + c, drow64(g, s));
+      }
+      if (rb + 1 < nr) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          blk[rb] = mfma64(ca[s], Wt[s], blk[rb]);
+          if (rb + 1 < HB) blk[rb + 1] = mfma64(cb[s], Wt[s], blk[rb + 1]);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) blk[rb] = mfma64(ca[s], Wt[s], blk[rb]);
+      }
+    }
+  }
+#pragma unroll
+  for (int rb = 0; rb < HB; ++rb) {
+    if (rb < nr) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[(16 * rb + drow64(g, v)) * Np] = blk[rb][v];
+    }
+  }
+}
+
 // Rows of a column block owned by panel wave w in the split update below (row blocks w,
 // w+4, .. of the rows j0 ..), loaded ahead of use: from A through the column order on the
 // first step (from_a), from Q after.
@@ -663,15 +786,19 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
   double* beta = key + Np;                  // [Np]
   double* tauA = beta + Np;                 // [Np]
   double* nt = tauA + Np;                   // [8]
-  int* iperm = (int*)(nt + 8);              // [Np]
+  // [2 pairs][2 buffers][2 halves][64][4] partial Y^T blk of the update pairs (pair update only)
+  double* wp2 = nt + 8;
+  int* iperm = (int*)(wp2 + (QR_PAIR_UPDATE(NRBMAX) ? 2048 : 0));   // [Np]
   int* flag = iperm + Np;                   // [2]: non-finite input, sync timeout
   int* cnt = flag + 2;                      // [1] panel-wave sync counter
   int* blkrdy = cnt + 1;                    // [1] last step whose first trailing block is stored
+  int* pcnt = blkrdy + 1;                   // [2] update-pair sync counters
+  int* blkcnt = pcnt + 2;                   // [1] pair update: halves of first trailing blocks stored
 
   const double* Ab = A + (size_t)b * astride;
   double* Q = QRW + (size_t)b * Np * Np;
   double* Tg = Tb + (size_t)b * NRB * 256;
-  if (tid == 0) { flag[0] = 0; flag[1] = 0; cnt[0] = 0; blkrdy[0] = -1; }
+  if (tid == 0) { flag[0] = 0; flag[1] = 0; cnt[0] = 0; blkrdy[0] = -1; pcnt[0] = 0; pcnt[1] = 0; blkcnt[0] = 0; }
   __syncthreads();
 
   // ---- pre-pivoting: order columns by log ||A e_j|| + log D_prev[j], descending
@@ -771,13 +898,40 @@ __global__ __launch_bounds__(QR_THREADS) void qr_k(const double* __restrict__ A,
       // else from Q once wave 4 has stored it (its first block this step)
       if (q + 1 < NRB) {
         if (p >= 0) {
+          // (pair update: both halves of block p + 2 of every step 0 .. p stored)
+          int* const rdy = QR_PAIR_UPDATE(NRBMAX) ? blkcnt : blkrdy;
+          const int want = QR_PAIR_UPDATE(NRBMAX) ? 2 * (p + 1) : p;
           int spins = 0;
-          while (__hip_atomic_load(blkrdy, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < p) {
+          while (__hip_atomic_load(rdy, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < want) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > QR_SPIN_LIMIT) { flag[1] = 1; break; }
           }
         }
         prefetch_block<RBQ>(nblk, NRB - q, jq, q + 1, p < 0, Ab, iperm, Q, Np, w, lane);
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+  } else if constexpr (QR_PAIR_UPDATE(NRBMAX)) {
+    // two pairs of update waves, each pair one column block at a time (pair 0 starts with
+    // block q+1, which the panel waves prefetch for the next step)
+    // (wave-uniform: the half's row-block bounds become scalar branches)
+    const int uw = __builtin_amdgcn_readfirstlane(w) - QR_PANEL_WAVES, pr = uw >> 1, h = uw & 1;
+    int pepoch = 0, pbuf = 0;
+    for (int p = -1; p < NRB - 1; ++p) {
+      const int q = p + 1;
+      if (p >= 0) {
+        for (int cb = q + 1 + pr; cb < NRB; cb += 2) {
+          update_block_pair<(NRBMAX + 1) / 2>(NRB - p, 16 * p, cb, p == 0, Ab, iperm, Q, Np,
+                                              Pn0 + (p & 1) * Np * LDY, Tl0 + (p & 1) * 16 * LDY,
+                                              wp2 + pr * 1024 + (pbuf & 1) * 512, h, pcnt + pr,
+                                              pepoch, lane, flag + 1);
+          ++pbuf;
+          if (cb == q + 1) {
+            __threadfence_block();
+            if (lane == 0) __hip_atomic_fetch_add(blkcnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
       }
       __threadfence_block();
       __syncthreads();
@@ -1304,8 +1458,8 @@ hipError_t run_qr(const double* A, int64_t astride, const double* norm2, int64_t
                   const double* logDp, double* QRW, double* Tb, int* perm, double* key,
                   double* logD, int* qsign, int* status, int nb, int Np, hipStream_t st) {
   const size_t lds = (size_t)(2 * Np * LDY + 2 * 16 * LDY + 2 * QR_PANEL_WAVES * 16 + 32 +
-                              QR_PANEL_WAVES * 256 + 3 * Np + 8) *
-                         sizeof(double) + (size_t)(Np + 6) * sizeof(int);
+                              QR_PANEL_WAVES * 256 + 3 * Np + 8 + (QR_PAIR_UPDATE(NRBMAX) ? 2048 : 0)) *
+                         sizeof(double) + (size_t)(Np + 8) * sizeof(int);
   hipLaunchKernelGGL(qr_k<NRBMAX>, dim3(nb), dim3(QR_THREADS), lds, st, A, astride, norm2, nstride, nparts,
                      logDp, QRW, Tb, perm, key, logD, qsign, status, Np);
   return hipGetLastError();
