@@ -128,9 +128,13 @@ def test_fp64_free_fermion_16x16():
     assert np.max(np.abs(G[0] - pins.free_green(16, 16, 1.0, 0.0, 16.0))) < 1e-9
 
 
-@pytest.mark.parametrize("Lx,Ly,Ltau,n_s", [(20, 20, 24, 8), (21, 21, 18, 6)])
+@pytest.mark.parametrize("Lx,Ly,Ltau,n_s", [(16, 17, 16, 8), (18, 18, 16, 8), (20, 20, 24, 8),
+                                             (21, 21, 18, 6)])
 def test_fp64_largest_lattices(Lx, Ly, Ltau, n_s):
-    # N = 400 and N = 441 (padded to 448, the largest size the library accepts)
+    # N = 272 and 324 (padded to 336): the QR's trailing update by wave pairs at its smallest
+    # size (17 row blocks, halves of 9 and 8) and at an odd split (21: 11 and 10); N = 400
+    # (its largest size, 13 and 12), and N = 441 (padded to 448, the largest size the library
+    # accepts)
     md = _md(Lx, Ltau, n_s, 1.5, Ly=Ly)
     g = gen(95, Lx * Ly)
     xs = [g.normal(0.0, 1.0, size=(Ltau, Lx * Ly)) for _ in range(2)]
