@@ -330,6 +330,341 @@ __global__ __launch_bounds__(NT) void lu_k(const double* __restrict__ QT,
   }
 }
 
+// Arrive-and-wait among the 4 panel waves of lu_la_k through a monotonically increasing LDS
+// counter (the update waves keep working meanwhile); release on arrival, acquire on the
+// wait.  Bounded: past the spin limit it sets *timeout (reported as a device fault) and
+// goes on, so every wave reaches the end of the kernel.
+constexpr int LU_PANEL_WAVES = 4;
+constexpr int LU_SPIN_LIMIT = 1 << 16;
+
+__device__ __forceinline__ void lu_panel_sync(int* cnt, int& epoch, int lane, int* timeout) {
+  ++epoch;
+  if (lane == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int target = LU_PANEL_WAVES * epoch;
+  int spins = 0;
+  while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+    if (spins >= 16) __builtin_amdgcn_s_sleep(1);
+    if (++spins > LU_SPIN_LIMIT) {
+      *timeout = 1;
+      break;
+    }
+  }
+}
+
+// lu_k with look-ahead for Np <= 256 (512 threads; the panel rows, one per thread, all lie
+// in waves 0-3).  Step p: waves 0-3 update column block q = p + 1 with panel p (each wave
+// its row blocks w, w + 4, .. and, for U12, the top one) into the next panel buffer and
+// factor it as panel q, with their own sync per column instead of a workgroup barrier;
+// waves 4-7 meanwhile apply panel p to the column blocks p + 2 .. and store panel p's L
+// columns.  Panel q's row map is composed after the step's barrier, once the update waves
+// are done with panel p's.  The panel, its inverses and every product are those of lu_k, in
+// the same order, so the factors are the same bit for bit.
+template <int NRBMAX>
+__global__ __launch_bounds__(512) void lu_la_k(const double* __restrict__ QT,
+                                               const double* __restrict__ V,
+                                               const double* __restrict__ logD,
+                                               const int* __restrict__ qsign,
+                                               const int* __restrict__ st_in,
+                                               double* __restrict__ LU, int* __restrict__ prow_g,
+                                               double* __restrict__ DI,
+                                               const int* __restrict__ item_of,
+                                               double* __restrict__ logdet_out,
+                                               int8_t* __restrict__ sign_out,
+                                               int32_t* __restrict__ status_out, int N, int Np) {
+  extern __shared__ double lds[];
+  constexpr int NT = 512, NW = NT / 64, NPW = LU_PANEL_WAVES;
+  const int b = blockIdx.x;
+  const int NRB = Np >> 4;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  double* Pn0 = lds;                       // [2][Np][LDY]
+  double* dbi = Pn0 + 2 * Np * LDY;        // [Np]
+  double* dsm = dbi + Np;                  // [Np]
+  double* ud = dsm + Np;                   // [Np] pivots (U diagonal)
+  double* Li0 = ud + Np;                   // [2][16][LDY] L11^-1 of panel p / p + 1
+  double* Ui = Li0 + 2 * 16 * LDY;         // [16][LDY]
+  double* redv = Ui + 16 * LDY;            // [2 NW]
+  double* cand = redv + 2 * NW;            // [2][NPW][17]: each panel wave's candidate row + key
+  int* prow = (int*)(cand + 2 * NPW * 17); // [Np]
+  int* redi = prow + Np;                   // [NW]
+  int* cnt = redi + NW;                    // [4]: swaps, singular, panel sync, sync timeout
+  int* phys = cnt + 4;                     // [Np] panel position -> slot
+  int* posof = phys + Np;                  // [Np] slot -> panel position
+
+  const double* QTb = QT + (size_t)b * Np * Np;
+  const double* Vb = V + (size_t)b * Np * Np;
+  double* L = LU + (size_t)b * Np * Np;
+  double* DIb = DI + (size_t)b * NRB * 512;
+  for (int i = tid; i < Np; i += NT) {
+    const double ld = logD[(size_t)b * Np + i];
+    dbi[i] = exp(-fmax(ld, 0.0));
+    dsm[i] = exp(fmin(ld, 0.0));
+    prow[i] = i;
+  }
+  if (tid == 0) { cnt[0] = 0; cnt[1] = 0; cnt[2] = 0; cnt[3] = 0; }
+  __syncthreads();
+  for (int idx = tid; idx < Np * 16; idx += NT) {
+    const int r = idx >> 4, jj = idx & 15;
+    Pn0[r * LDY + jj] = xval(QTb, Vb, dbi, dsm, Np, r, jj);
+  }
+  __syncthreads();
+
+  // The two roles run separate loops with the same barriers, so that the registers of one
+  // role's data do not constrain the other's.
+  if (__builtin_amdgcn_readfirstlane(w) < NPW) {
+    int epoch = 0;
+    for (int p = -1; p < NRB; ++p) {
+      const int q = p + 1;
+      int pr0 = 0;
+      if (q < NRB) {
+        const int jq = 16 * q, Kq = Np - jq;
+        double* Pq = Pn0 + (q & 1) * Np * LDY;
+        double* Lq = Li0 + (q & 1) * 16 * LDY;
+        if (p >= 0) {
+          // column block q with panel p: U12 = L11^-1 A12 (every panel wave computes it from
+          // the top row block), A22 -= L21 U12 for this wave's row blocks, which go to Pq
+          const int j0 = 16 * p, nrbK = NRB - p;
+          const double* Pn = Pn0 + (p & 1) * Np * LDY;
+          const double* Lip = Li0 + (p & 1) * 16 * LDY;
+          int c = lane & 15, g = lane >> 4;
+          __asm__ volatile("" : "+v"(c), "+v"(g));
+          const int col = 16 * q + c;
+          constexpr int RBQ = (NRBMAX + NPW - 1) / NPW;
+          dx4 top, blk[RBQ];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int pr = prow[j0 + drow64(g, v)];
+            top[v] = (p == 0) ? xval(QTb, Vb, dbi, dsm, Np, pr, col) : L[(size_t)pr * Np + col];
+          }
+#pragma unroll
+          for (int r = 0; r < RBQ; ++r) {
+            const int rb = w + NPW * r;
+            if (rb >= 1 && rb < nrbK) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int pr = prow[j0 + 16 * rb + drow64(g, v)];
+                blk[r][v] = (p == 0) ? xval(QTb, Vb, dbi, dsm, Np, pr, col) : L[(size_t)pr * Np + col];
+              }
+            }
+          }
+          dx4 u12 = zero4d();
+#pragma unroll
+          for (int s = 0; s < 4; ++s) u12 = mfma64(Lip[c * LDY + drow64(g, s)], top[s], u12);
+          if (w == 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) L[(size_t)prow[j0 + drow64(g, v)] * Np + col] = u12[v];
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int r = 0; r < RBQ; ++r) {
+              const int rb = w + NPW * r;
+              if (rb >= 1 && rb < nrbK) blk[r] = mfma64(-Pn[(16 * rb + c) * LDY + drow64(g, s)], u12[s], blk[r]);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RBQ; ++r) {
+            const int rb = w + NPW * r;
+            if (rb >= 1 && rb < nrbK) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Pq[(16 * (rb - 1) + drow64(g, v)) * LDY + c] = blk[r][v];
+            }
+          }
+          lu_panel_sync(cnt + 2, epoch, lane, cnt + 3);
+        }
+        // panel q (Kq rows x 16 columns): thread t keeps slot t in registers; rows never move,
+        // thread 0 keeps the position <-> slot maps of the equivalent row exchanges
+        const bool h0 = tid < Kq;
+        double ra[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) ra[j] = h0 ? Pq[tid * LDY + j] : 0.0;
+        if (h0) { phys[tid] = tid; posof[tid] = tid; }
+        bool a0 = h0;
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+          const uint64_t mine = a0 ? pivot_key(ra[cc], tid) : 0ull;
+          const uint64_t kw = wave_max_u64(mine);
+          double* cd = cand + (cc & 1) * (NPW * 17) + w * 17;
+          if (kw != 0ull && mine == kw) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) cd[j] = ra[j];
+            cd[16] = __longlong_as_double((long long)kw);
+          }
+          if (kw == 0ull && lane == 0) cd[16] = 0.0;
+          lu_panel_sync(cnt + 2, epoch, lane, cnt + 3);
+          const double* c0 = cand + (cc & 1) * (NPW * 17);
+          uint64_t best = 0ull;
+          int bw = 0;
+#pragma unroll
+          for (int ww = 0; ww < NPW; ++ww) {
+            const uint64_t kk = (uint64_t)__double_as_longlong(c0[ww * 17 + 16]);
+            if (kk > best) { best = kk; bw = ww; }
+          }
+          const int sp = 511 - (int)(best & 511ull);
+          double pv[16];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) pv[j] = c0[bw * 17 + j];
+          const double u = pv[cc];
+          if (tid == 0) {
+            const int qq = posof[sp];
+            if (qq != cc) {
+              const int s0 = phys[cc];
+              phys[cc] = sp;
+              phys[qq] = s0;
+              posof[sp] = cc;
+              posof[s0] = qq;
+              cnt[0] += 1;
+            }
+            ud[jq + cc] = u;
+            if (u == 0.0 || u != u) cnt[1] = 1;
+          }
+          if (sp == tid) a0 = false;
+          const double ui = (u != 0.0) ? 1.0 / u : 0.0;
+          if (a0) {
+            const double l = ra[cc] * ui;
+#pragma unroll
+            for (int j = cc + 1; j < 16; ++j) ra[j] -= l * pv[j];
+            ra[cc] = l;
+          }
+        }
+        lu_panel_sync(cnt + 2, epoch, lane, cnt + 3);   // the position maps are final
+        if (h0) {
+          const int qq = posof[tid];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) Pq[qq * LDY + j] = ra[j];
+          pr0 = prow[jq + phys[tid]];
+        }
+        lu_panel_sync(cnt + 2, epoch, lane, cnt + 3);   // the panel in position order
+        // inverses of the unit-lower L11 (wave 0) and upper U11 (wave 1), one column per lane
+        if (w == 0 && lane < 16) {
+          const int j = lane;
+          double x[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < i; ++l) s += Pq[i * LDY + l] * x[l];
+            x[i] = (i < j) ? 0.0 : (i == j ? 1.0 : -s);
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) Lq[i * LDY + j] = x[i];
+        } else if (w == 1 && lane < 16) {
+          const int j = lane;
+          double x[16];
+#pragma unroll
+          for (int i = 15; i >= 0; --i) {
+            double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int l = i + 1; l < 16; ++l) s -= Pq[i * LDY + l] * x[l];
+            const double u = Pq[i * LDY + i];
+            x[i] = (i > j) ? 0.0 : ((u != 0.0) ? s / u : 0.0);
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) Ui[i * LDY + j] = x[i];
+        }
+        lu_panel_sync(cnt + 2, epoch, lane, cnt + 3);
+        for (int idx = tid; idx < 512; idx += NPW * 64) {
+          const int which = idx >> 8, e = idx & 255, i = e >> 4, j = e & 15;
+          DIb[(size_t)q * 512 + idx] = which ? Ui[i * LDY + j] : Lq[i * LDY + j];
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+      // panel q's row map, composed now that no wave reads panel p's any more
+      if (q < NRB && tid < Np - 16 * q) prow[16 * q + tid] = pr0;
+      __syncthreads();
+    }
+  } else {
+    for (int p = -1; p < NRB; ++p) {
+      if (p >= 0) {
+      // trailing update with panel p: U12 = L11^-1 A12, A22 -= L21 U12 for blocks p + 2 ..
+      const int j0 = 16 * p, K = Np - j0, nrbK = NRB - p;
+      const double* Pn = Pn0 + (p & 1) * Np * LDY;
+      const double* Lip = Li0 + (p & 1) * 16 * LDY;
+      for (int cb = p + 2 + (w - NPW); cb < NRB; cb += NW - NPW) {
+        int c = lane & 15, g = lane >> 4;
+        __asm__ volatile("" : "+v"(c), "+v"(g));
+        dx4 blk[NRBMAX];
+#pragma unroll
+        for (int rb = 0; rb < NRBMAX; ++rb) {
+          if (rb < nrbK) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int pr = prow[j0 + 16 * rb + drow64(g, v)];
+              blk[rb][v] = (p == 0) ? xval(QTb, Vb, dbi, dsm, Np, pr, 16 * cb + c)
+                                    : L[(size_t)pr * Np + 16 * cb + c];
+            }
+          }
+        }
+        dx4 u12 = zero4d();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) u12 = mfma64(Lip[c * LDY + drow64(g, s)], blk[0][s], u12);
+        blk[0] = u12;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int rb = 1; rb < NRBMAX; ++rb) {
+            if (rb < nrbK) blk[rb] = mfma64(-Pn[(16 * rb + c) * LDY + drow64(g, s)], u12[s], blk[rb]);
+          }
+        }
+#pragma unroll
+        for (int rb = 0; rb < NRBMAX; ++rb) {
+          if (rb < nrbK) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              L[(size_t)prow[j0 + 16 * rb + drow64(g, v)] * Np + 16 * cb + c] = blk[rb][v];
+          }
+        }
+      }
+      // panel p's L columns (and its U11 rows), at their rows through the row map
+      for (int idx = tid - NPW * 64; idx < K * 16; idx += (NW - NPW) * 64) {
+        const int r = idx >> 4, jj = idx & 15;
+        L[(size_t)prow[j0 + r] * Np + j0 + jj] = Pn[r * LDY + jj];
+      }
+      }
+      __threadfence_block();
+      __syncthreads();
+      __syncthreads();
+    }
+  }
+
+  // log|det X|, sign, and the outputs
+  double s = 0.0, sd = 0.0;
+  int neg = 0;
+  for (int i = tid; i < Np; i += NT) {
+    const double u = ud[i];
+    s += log(fabs(u));
+    neg += u < 0.0;
+    sd += fmax(logD[(size_t)b * Np + i], 0.0);
+    prow_g[(size_t)b * Np + i] = prow[i];
+  }
+  s = sum64(s);
+  sd = sum64(sd);
+  for (int off = 32; off >= 1; off >>= 1) neg += __shfl_xor(neg, off, 64);
+  if (lane == 0) { redv[w] = s; redv[NW + w] = sd; redi[w] = neg; }
+  __syncthreads();
+  if (tid == 0) {
+    double lx = 0.0, lb = 0.0;
+    int nn = 0;
+    for (int k = 0; k < NW; ++k) {
+      lx += redv[k];
+      lb += redv[NW + k];
+      nn += redi[k];
+    }
+    double ld = lb + lx - (double)(Np - N) * LN2;
+    const int sgn = qsign[b] * (((nn + cnt[0]) & 1) ? -1 : 1);
+    int stt = 0;
+    if (st_in[b] != 0 || cnt[1] != 0 || cnt[3] != 0 || !isfinite(ld)) {
+      // bit 3 of the QR status or this kernel's own sync timeout: a bounded wait ran out
+      stt = ((st_in[b] & 8) || cnt[3]) ? 4 : 5;
+      ld = __longlong_as_double(0x7ff8000000000000LL);
+    }
+    const int item = item_of ? item_of[b] : b;
+    logdet_out[item] = ld;
+    sign_out[item] = (int8_t)sgn;
+    status_out[item] = stt;
+  }
+}
+
 // X^{-1} applied to a right-hand side (mode 0: Db^{-1} U^T; mode 1: R): forward
 // substitution with the unit lower factor, then backward with the upper one, using the
 // 16x16 inverses of the diagonal blocks from the LU; one wave per (item, 16 columns), the
@@ -693,6 +1028,14 @@ hipError_t run_lu(const double* QT, const double* V, const double* logD, const i
                   double* lo, int8_t* so, int32_t* sto, int nb, int N, int Np, hipStream_t st) {
   constexpr int NT = NRBMAX <= 16 ? 512 : 256;
   constexpr int NW = NT / 64;
+  if constexpr (NRBMAX <= 16) {
+    // look-ahead form (panel rows all in waves 0-3)
+    const size_t lds = (size_t)(2 * Np * LDY + 3 * Np + 3 * 16 * LDY + 2 * NW + 2 * LU_PANEL_WAVES * 17) *
+                           sizeof(double) + (size_t)(3 * Np + NW + 4) * sizeof(int);
+    hipLaunchKernelGGL(lu_la_k<NRBMAX>, dim3(nb), dim3(NT), lds, st, QT, V, logD, qsign, st_in, LU,
+                       prow, DI, item_of, lo, so, sto, N, Np);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(2 * Np * LDY + 3 * Np + 2 * 16 * LDY + 2 * NW + 2 * NW * 17) * sizeof(double) +
                      (size_t)(3 * Np + NW + 2) * sizeof(int);
   hipLaunchKernelGGL((lu_k<NRBMAX, NT>), dim3(nb), dim3(NT), lds, st, QT, V, logD, qsign, st_in, LU,
