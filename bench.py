@@ -48,11 +48,11 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "int8x5": 15}   # pe
 # (factors 2.0 and 1.0).  They are not measured by this script: they are read from the
 # committed summary named in TRAFFIC_SOURCE and are valid only for the kernel versions it
 # was taken on (the bench line carries the source with the figure).
-TRAFFIC = {("qr", "int8x5"): 624.7e6, ("seg_chain", "int8x5"): 86.0e6, ("lu", "int8x5"): 687.1e6,
-           ("wy_apply", "int8x5"): 179.5e6, ("vupd", "int8x5"): 181.8e6}
+TRAFFIC = {("qr", "int8x5"): 624.7e6, ("seg_chain", "int8x5"): 85.9e6, ("lu", "int8x5"): 642.4e6,
+           ("wy_apply", "int8x5"): 179.5e6, ("vupd", "int8x5"): 181.9e6}
 TRAFFIC_SOURCE = ("profiles/fermion_step_16x16_ltau160_int8x5_128chains.md (rocprofv3 --pmc "
-                  "FETCH_SIZE / WRITE_SIZE of the seg_chain_i8, qr_k, lu_k, wy_apply_reg_k and "
-                  "vupd_split_k kernels as of commit 488e8df)")
+                  "FETCH_SIZE / WRITE_SIZE of the seg_chain_i8, qr_k, lu_la_k, wy_apply_reg_k and "
+                  "vupd_split_k kernels as of commit dc67a85)")
 
 
 def run(slmc, torch, md, eff, xs, B, prec, args):
